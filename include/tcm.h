@@ -1,0 +1,227 @@
+/*
+ * tcm.h -- C ABI of libtcm, an MI355X (gfx950) implementation of the two-centre multipole
+ * (TCM) method: per-molecule multipole moments (eq. 8 of Solov'yov et al., "Two center
+ * multipole expansion method: application to macromolecular systems") and their two-centre
+ * contraction into the Coulomb interaction energy of two well separated molecules (eq. 9,
+ * square truncation l1, l2 <= L as stated in the text after eq. 9).
+ *
+ * Conventions shared by every entry point
+ *   - All functions return an int status (TCM_OK or a negative TCM_E* code) and never
+ *     throw.  Outputs are written only when the call returns TCM_OK; batch calls report a
+ *     status per item and write NaN for failed items.
+ *   - Host pointers are read during the call only; the caller owns them and may reuse them
+ *     as soon as the call returns.  Device pointers passed to tcm_mol_register_device are
+ *     borrowed: they must stay valid until the molecule is released.
+ *   - Coordinates: FP64, array of structures [n][3] (x, y, z) unless stated otherwise.
+ *     Charges: FP64 [n].  Units are the caller's; eq. 1 has no prefactor, so energies come
+ *     out in charge^2 / length (multiply by 332.0637 for kcal/mol with e and Angstrom).
+ *   - Moment tables are real-packed, (L+1)^2 FP64 values for order L:
+ *       index l*l          : Q_l0 (real)
+ *       index l*l + 2m - 1 : Re Q_lm,  index l*l + 2m : Im Q_lm   (1 <= m <= l)
+ *     Q_{l,-m} = (-1)^m conj(Q_lm) is implied.  Q_lm follows eq. 8:
+ *       Q_lm = sum_i q_i r_i^l sqrt(4 pi / (2l+1)) Y_lm(theta_i, phi_i),
+ *     with Condon-Shortley phase and r_i = R_i - centre.  A table of order L' >= L may be
+ *     passed where order L is needed (its prefix is the order-L table).
+ *   - The centre of a molecule is "any suitable point" (section II); when the caller gives
+ *     none, the unweighted centroid of the atoms is used.  The radius of a molecule is
+ *     a = max_i |R_i - centre|, the quantity eq. 2 constrains.
+ *   - eq. 2 (the expansion converges only if |R0| > a_A + a_B): pair energies with
+ *     |R0| <= a_A + a_B are rejected with TCM_EDOMAIN unless TCM_UNCHECKED is set.
+ *   - Precision: TCM_F64 computes the moment pass in FP64; TCM_F32C computes it in FP32
+ *     on centred coordinates scaled by a bound on the radius, summing each thread's atoms
+ *     in FP32 and merging every partial sum above that with compensated (TwoSum,
+ *     double-float) additions.  Geometric factors, rotation and the energy contraction
+ *     are always FP64.
+ *   - A context is externally synchronised: do not call into one context from two
+ *     threads at once (the serving loop runs its own thread and locks internally).
+ */
+#ifndef TCM_H
+#define TCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TCM_OK          0
+#define TCM_EINVAL     -1   /* null pointer, n < 0, L outside [0, TCM_LMAX], non-finite input */
+#define TCM_EDOMAIN    -2   /* |R0| <= a_A + a_B: eq. 2 violated                             */
+#define TCM_ENOMEM     -3   /* device allocation failed or the HBM budget is exceeded        */
+#define TCM_EDEVICE    -4   /* HIP runtime error or an expired device-side wait               */
+#define TCM_EAGAIN     -5   /* serving queue full; retry later                               */
+#define TCM_ENOTFOUND  -6   /* unknown molecule id or ticket                                 */
+
+#define TCM_LMAX 32         /* largest multipole order accepted */
+
+/* precision of the moment pass */
+#define TCM_F64   0
+#define TCM_F32C  1
+
+/* per-request flags */
+#define TCM_UNCHECKED  1    /* skip the eq. 2 separation test (parity tests only)            */
+#define TCM_REUSE      2    /* use the molecule's resident moments if their order is >= L    */
+
+typedef struct tcm_ctx tcm_ctx;
+typedef struct tcm_plan tcm_plan;
+typedef int64_t tcm_mol_id;
+
+/* Human-readable text for a status code (static storage). */
+const char *tcm_strerror(int status);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device memory the
+ * context may hold for resident molecules and workspace (0 = no bound).  flags: reserved,
+ * pass 0.  Builds the FP64 coefficient tables on the device.  Errors: TCM_EINVAL (null
+ * ctx), TCM_EDEVICE (no such device), TCM_ENOMEM. */
+int tcm_create(tcm_ctx **ctx, int device, size_t hbm_budget_bytes, int flags);
+
+/* Release every device buffer of the context (resident molecules included). */
+void tcm_destroy(tcm_ctx *ctx);
+
+/* Run the context's work on this HIP stream (hipStream_t passed as void*; NULL = the
+ * context's own stream).  The stream must have default priority. */
+int tcm_set_stream(tcm_ctx *ctx, void *hip_stream);
+void *tcm_get_stream(tcm_ctx *ctx);
+
+/* eq. 8 for one molecule.  coords [n][3], charges [n] (host FP64); centre FP64[3] or NULL
+ * (centroid); 0 <= L <= TCM_LMAX; precision TCM_F64 or TCM_F32C.  Q_out: (L+1)^2 FP64
+ * (packed layout above).  radius_out (a = max |R_i - centre|) and centre_out (FP64[3])
+ * may be NULL.  n = 0 is allowed (all moments zero; centre = the given one or the origin).
+ * Synchronous. */
+int tcm_moments(tcm_ctx *ctx, const double *coords, const double *charges, int64_t n,
+                const double *centre, int L, int precision, double *Q_out, double *radius_out,
+                double *centre_out);
+
+/* eq. 9 with square truncation l1, l2 <= L for one pair, from host moment tables.
+ * QA, QB: packed FP64 tables of order >= L.  aA, aB: the molecules' radii (eq. 2 test).
+ * R: FP64[3], c_B - c_A.  quat_b: FP64[4] unit quaternion (w, x, y, z) rotating B actively
+ * about its centre before the contraction, or NULL for none; QB are B's moments in its
+ * unrotated frame.  flags: TCM_UNCHECKED or 0.  U_out: the energy.  Synchronous. */
+int tcm_pair_energy(tcm_ctx *ctx, const double *QA, double aA, const double *QB, double aB,
+                    const double *R, const double *quat_b, int L, int flags, double *U_out);
+
+/* ---- device-resident molecules ---------------------------------------------------- */
+
+/* Copy a molecule's atoms (host AoS FP64) to the device, in the library's resident layout
+ * (FP64 structure of arrays).  centre: FP64[3] or NULL (centroid).  precision: the moment
+ * pass used for this molecule.  The id stays valid until tcm_mol_release / tcm_destroy. */
+int tcm_mol_upload(tcm_ctx *ctx, const double *coords, const double *charges, int64_t n,
+                   const double *centre, int precision, tcm_mol_id *id_out);
+
+/* Register atoms already on the device (FP64 structure of arrays x[n], y[n], z[n], q[n],
+ * borrowed, not copied). */
+int tcm_mol_register_device(tcm_ctx *ctx, const double *d_x, const double *d_y,
+                            const double *d_z, const double *d_q, int64_t n,
+                            const double *centre, int precision, tcm_mol_id *id_out);
+
+/* Free the molecule's atoms (if uploaded) and resident moments. */
+int tcm_mol_release(tcm_ctx *ctx, tcm_mol_id id);
+
+/* Compute (or, with TCM_REUSE in flags, reuse) the molecule's order-L moments on the device
+ * and copy them to the host.  Q_out (L+1)^2 FP64; radius_out, centre_out may be NULL. */
+int tcm_mol_moments(tcm_ctx *ctx, tcm_mol_id id, int L, int flags, double *Q_out,
+                    double *radius_out, double *centre_out);
+
+/* ---- batches ----------------------------------------------------------------------- */
+
+/* One pair-energy request: molecules a and b (resident ids), R0 = c_b - c_a, optional pose
+ * of b (unit quaternion (w, x, y, z); (1, 0, 0, 0) = none), order L, flags. */
+typedef struct {
+    tcm_mol_id a;
+    tcm_mol_id b;
+    double R[3];
+    double quat_b[4];
+    int32_t L;
+    int32_t flags;
+} tcm_pair_req;
+
+/* Energies of npairs requests in one persistent launch: moments of every molecule the
+ * batch names are computed on the device (or reused, per TCM_REUSE), then every pair is
+ * rotated and contracted.  U_out[npairs], status_out[npairs] (host).  Returns TCM_OK if
+ * every item succeeded, else the first failing item's code.  Synchronous. */
+int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *U_out,
+                     int32_t *status_out);
+
+/* Plan a batch once and capture its launches in a HIP graph; tcm_plan_run replays it on
+ * the context's stream (asynchronous: outputs stay on the device until tcm_plan_results).
+ * The plan recomputes every moment the batch needs on each run (no TCM_REUSE). */
+int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
+                    tcm_plan **plan_out);
+int tcm_plan_run(tcm_ctx *ctx, tcm_plan *plan);
+/* Same work split into three launches (statistics, moment tiles, pairs) so that each
+ * phase can be timed; results are identical bit for bit. */
+int tcm_plan_run_phased(tcm_ctx *ctx, tcm_plan *plan);
+/* One synchronous phased run with HIP events recorded on the launch stream around the
+ * statistics launch, the tile launches and the pair launch; ms_out[3] receives the three
+ * elapsed times in milliseconds (measurement of the per-kernel durations). */
+int tcm_plan_run_timed(tcm_ctx *ctx, tcm_plan *plan, double *ms_out);
+/* Wait for the last run and copy U/status to the host (either may be NULL). */
+int tcm_plan_results(tcm_ctx *ctx, tcm_plan *plan, double *U_out, int32_t *status_out);
+/* Device addresses of the plan's outputs (FP64 U[npairs], int32 status[npairs]). */
+int tcm_plan_device_outputs(tcm_plan *plan, double **d_U, int32_t **d_status);
+/* Work counts of the plan: atoms, moment flops (algorithmic convention 6(L+1)(L+2) per
+ * atom), tile items, pair items. */
+int tcm_plan_info(tcm_plan *plan, int64_t *atoms, double *moment_flops, int64_t *tiles,
+                  int64_t *pairs);
+void tcm_plan_destroy(tcm_plan *plan);
+
+/* ---- tuning ------------------------------------------------------------------------ */
+
+/* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */
+int tcm_tune_get(tcm_ctx *ctx, int precision, int L, int64_t n, int *kper_out);
+int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);
+/* Time every candidate kper for (precision, L) on a synthetic molecule of n atoms and keep
+ * the fastest for n's size bucket.  best_ms_out may be NULL. */
+int tcm_autotune(tcm_ctx *ctx, int precision, int L, int64_t n, int *best_kper_out,
+                 double *best_ms_out);
+/* Persist / restore the tuning table (text file). */
+int tcm_tune_save(tcm_ctx *ctx, const char *path);
+int tcm_tune_load(tcm_ctx *ctx, const char *path);
+
+/* ---- serving ----------------------------------------------------------------------- */
+
+/* A served request: either resident molecules (ids) or new atoms given by device pointers
+ * (FP64 SoA, borrowed until the request completes).  New molecules become resident and
+ * are kept in an LRU cache bounded by the context's HBM budget. */
+typedef struct {
+    tcm_mol_id a;                  /* resident id, or -1 to use new_a */
+    tcm_mol_id b;
+    const double *new_a[4];        /* d_x, d_y, d_z, d_q when a == -1 */
+    int64_t new_na;
+    const double *new_b[4];
+    int64_t new_nb;
+    double R[3];
+    double quat_b[4];
+    int32_t L;
+    int32_t flags;
+    int32_t precision;
+    int32_t pad;
+} tcm_request;
+
+typedef struct {
+    int32_t max_inflight_batches;  /* launches in flight at once (>= 1)                    */
+    int32_t max_batch_pairs;       /* pairs admitted into one launch                        */
+    int32_t queue_capacity;        /* pending requests before tcm_submit returns TCM_EAGAIN */
+    int32_t pad;
+} tcm_server_cfg;
+
+int tcm_server_start(tcm_ctx *ctx, const tcm_server_cfg *cfg);
+/* Enqueue a request; returns a ticket.  TCM_EAGAIN when the queue is full. */
+int tcm_submit(tcm_ctx *ctx, const tcm_request *req, uint64_t *ticket_out);
+/* Non-blocking: TCM_EAGAIN while pending; on completion writes U, the item status and the
+ * latency (seconds from submit to completion) and forgets the ticket. */
+int tcm_poll(tcm_ctx *ctx, uint64_t ticket, double *U_out, int32_t *status_out,
+             double *latency_s_out);
+/* Stop accepting requests, finish the ones admitted, join the serving thread. */
+int tcm_server_stop(tcm_ctx *ctx);
+/* Counters since start: completed requests, launches, molecule cache hits/misses,
+ * admissions deferred for memory. */
+int tcm_server_stats(tcm_ctx *ctx, int64_t *completed, int64_t *launches, int64_t *cache_hits,
+                     int64_t *cache_misses, int64_t *deferred);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCM_H */

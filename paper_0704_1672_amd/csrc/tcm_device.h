@@ -1,0 +1,484 @@
+// HIP device code of libtcm for gfx950 (MI355X).  Steps of the two-centre multipole (TCM) hot
+// path and where they run:
+//   a0 STATS  centroid and scale of each molecule                  (HBM bound)
+//   a1 TILE   eq. (8) moments of a tile of atoms, one m-block       (FP32/FP64 vector ALU)
+//   a2        fixed-order merge of the tile partials, unscaling     (last TILE item)
+//   a3-a5 PAIR  Wigner rotation of B, irregular harmonics of R0, eq. (9) contraction
+//
+// Moment recurrence.  The paper evaluates Q_lm = sum_i q_i r_i^l sqrt(4pi/(2l+1)) Y_lm
+// (eq. (8)).  Here every atom's harmonics come from a three-term recurrence on the
+// direction cosines c = cos(theta), u = sin(theta) e^{i phi} in a normalisation T_lm = k_lm
+// R_lm / r^l (R_lm the Racah-normalised solid harmonic) chosen so that
+//     T_mm = u^m,   T_{m+1,m} = c T_mm,   T_lm = xi_lm c T_{l-1,m} - T_{l-2,m},
+// with rational xi_lm (xi_{m+1,m} = 1, xi_lm xi_{l-1,m} = (2l-1)(2l-3)/((l-1)^2-m^2)).
+// The recurrence step then costs one multiply (xi*c) plus one FMA per component and the
+// accumulation acc += (q r^l) T one FMA per component; k_lm is divided out once per
+// molecule in FP64.  Coordinates are centred and divided by a scale s >= max|r_i| in
+// FP64 before the FP32 cast, so |T| <= 7.2 for l <= 32 and no FP32 overflow can occur.
+//
+// Compensated accumulation (FP32 path): each thread sums its kper atoms in plain FP32,
+// then every merge above that -- across the 256 threads of the tile and across tiles --
+// is a double-float (hi, lo) TwoSum merge in a fixed order, so a molecule's moments do
+// not depend on what else shares the launch.
+// Device code of the moment pass (a1) and its fixed-order finalisation (a2), shared by the
+// per-(precision, L) tile translation units.
+#pragma once
+#include "tcm.h"
+#include "tcm_internal.h"
+
+namespace tcm {
+
+
+// ------------------------------------------------------------------ small helpers
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
+{
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (ah, al) += (bh, bl), double-float
+__device__ __forceinline__ void df_add(float& ah, float& al, float bh, float bl)
+{
+    float s, e;
+    two_sum(ah, bh, s, e);
+    e += al + bl;
+    ah = s + e;
+    al = e - (ah - s);
+}
+
+__device__ __forceinline__ int atomic_load_acq(int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_store_rel(int* p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int atomic_add_acqrel(int* p, int v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits (bounded) until *flag != 0; the result is shared with the workgroup.
+// Returns false if the wait expired or another workgroup already reported an error.
+__device__ inline bool wg_wait_flag(int* flag, const DevPlan& P, int* s_ok)
+{
+    if (threadIdx.x == 0) {
+        int ok = 0;
+        for (int64_t it = 0; it < P.spin_limit; ++it) {
+            if (atomic_load_acq(flag)) { ok = 1; break; }
+            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) atomic_store_rel(P.err, 1);
+        *s_ok = ok;
+    }
+    __syncthreads();
+    int ok = *s_ok;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __syncthreads();
+    return ok != 0;
+}
+
+// ------------------------------------------------------------------ recurrence constants
+__host__ __device__ constexpr double xi_lm(int l, int m)
+{
+    double xi = 1.0;                         // xi_{m+1,m}
+    for (int j = m + 2; j <= l; ++j)
+        xi = ((2.0 * j - 1.0) * (2.0 * j - 3.0) / (((double)j - 1.0 - m) * ((double)j - 1.0 + m))) / xi;
+    return xi;
+}
+
+// accumulator offset of (l, m) within the m-block [M0, ...] of order L (real part;
+// the imaginary part of m > 0 follows at +1)
+__host__ __device__ constexpr int acc_index(int L, int M0, int m, int l)
+{
+    int o = 0;
+    for (int mm = M0; mm < m; ++mm) o += chain_cost(L, mm);
+    return o + (l - m) * (m > 0 ? 2 : 1);
+}
+
+__host__ __device__ constexpr int acc_count(int L, int M0, int M1)
+{
+    int o = 0;
+    for (int mm = M0; mm <= M1; ++mm) o += chain_cost(L, mm);
+    return o;
+}
+
+// Runtime inverse: accumulator a of block [M0..] -> packed index h.
+__device__ inline int acc_to_packed(int L, int M0, int a)
+{
+    int m = M0;
+    while (a >= chain_cost(L, m)) { a -= chain_cost(L, m); ++m; }
+    int per = (m > 0 ? 2 : 1);
+    int l = m + a / per;
+    int part = a % per;
+    return m == 0 ? l * l : l * l + 2 * m - 1 + part;
+}
+
+// One step of the l-chain for fixed m, l = LC .. L (template recursion so that xi_lm is a
+// compile-time literal and every accumulator index is static).
+template <typename F, int L, int M0, int M, int LC>
+struct Chain {
+    __device__ __forceinline__ static void run(F* acc, const F* w, F c, F& t1r, F& t1i, F& t2r, F& t2i)
+    {
+        if constexpr (LC <= L) {
+            constexpr F xi = (F)xi_lm(LC, M);
+            const F xc = xi * c;
+            const F nr = fma(xc, t1r, -t2r);
+            constexpr int o = acc_index(L, M0, M, LC);
+            acc[o] = fma(w[LC], nr, acc[o]);
+            t2r = t1r;
+            t1r = nr;
+            if constexpr (M > 0) {
+                const F ni = fma(xc, t1i, -t2i);
+                acc[o + 1] = fma(w[LC], ni, acc[o + 1]);
+                t2i = t1i;
+                t1i = ni;
+            }
+            Chain<F, L, M0, M, LC + 1>::run(acc, w, c, t1r, t1i, t2r, t2i);
+        }
+    }
+};
+
+// All chains m = M .. M1 of the block.  (sr, si) = T_{M,M} on entry.
+template <typename F, int L, int M0, int M1, int M>
+struct Block {
+    __device__ __forceinline__ static void run(F* acc, const F* w, F c, F ur, F ui, F sr, F si)
+    {
+        if constexpr (M <= M1) {
+            constexpr int o = acc_index(L, M0, M, M);
+            acc[o] = fma(w[M], sr, acc[o]);
+            if constexpr (M > 0) acc[o + 1] = fma(w[M], si, acc[o + 1]);
+            if constexpr (M < L) {
+                F t2r = sr, t2i = si;
+                F t1r = c * sr, t1i = (M > 0) ? c * si : (F)0;   // T_{M+1,M}
+                constexpr int o1 = acc_index(L, M0, M, M + 1);
+                acc[o1] = fma(w[M + 1], t1r, acc[o1]);
+                if constexpr (M > 0) acc[o1 + 1] = fma(w[M + 1], t1i, acc[o1 + 1]);
+                Chain<F, L, M0, M, M + 2>::run(acc, w, c, t1r, t1i, t2r, t2i);
+            }
+            if constexpr (M < M1) {
+                const F nr = sr * ur - si * ui;     // T_{M+1,M+1} = u T_{M,M}
+                const F ni = sr * ui + si * ur;
+                Block<F, L, M0, M1, M + 1>::run(acc, w, c, ur, ui, nr, ni);
+            }
+        }
+    }
+};
+
+// Harmonics of one atom for m-block [M0, M1]: c = cos theta, u = (ur, ui), r = |rho|,
+// q = charge.
+template <typename F, int L, int M0, int M1>
+__device__ __forceinline__ void atom_block(F* acc, F c, F ur, F ui, F r, F q)
+{
+    F w[L + 1];
+    w[0] = q;
+#pragma unroll
+    for (int l = 1; l <= L; ++l) w[l] = w[l - 1] * r;
+    F sr = (F)1, si = (F)0;
+#pragma unroll
+    for (int m = 1; m <= M0; ++m) {
+        const F nr = sr * ur - si * ui;
+        si = sr * ui + si * ur;
+        sr = nr;
+    }
+    Block<F, L, M0, M1, M0>::run(acc, w, c, ur, ui, sr, si);
+}
+
+// ------------------------------------------------------------------ shared memory
+// One static buffer, reused by every item kind (a workgroup runs one item at a time).
+constexpr int SMEM_BYTES = 56 * 1024;        // statistics and pair kernels
+constexpr int TILE_SMEM_BYTES = 37 * 1024;   // tile kernels (transposed reductions)
+constexpr int RED_COLS_F32 = 32;             // columns per transpose-reduction chunk
+constexpr int RED_COLS_F64 = 16;
+
+struct TileCtx {
+    const MolWork* mw;
+    int tile;
+    int blk;
+    double cx, cy, cz, inv_s;
+};
+
+// Transposed reduction of NA per-thread FP32 accumulators over the 256 threads of the
+// workgroup: each column is summed by 8 threads with a TwoSum cascade over 32 rows, the
+// 8 double-float partials are merged in order, and (hi, lo) is written to out.
+template <int NA>
+__device__ __forceinline__ void reduce_write_f32(const float* acc, char* smem, int L, int M0,
+                                                  float* out_hi, float* out_lo)
+{
+    float* red = reinterpret_cast<float*>(smem);                     // [WG][33]
+    float* grp = red + WG * (RED_COLS_F32 + 1);                       // [8][32][2]
+    const int tid = threadIdx.x;
+    constexpr int NCH = (NA + RED_COLS_F32 - 1) / RED_COLS_F32;
+    static_assert(WG == 256, "reduction layout assumes 256 threads");
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+        for (int j = 0; j < RED_COLS_F32; ++j) {
+            const int a = ch * RED_COLS_F32 + j;
+            red[tid * (RED_COLS_F32 + 1) + j] = (a < NA) ? acc[a < NA ? a : 0] : 0.0f;
+        }
+        __syncthreads();
+        {
+            const int col = tid & 31, g = tid >> 5;
+            float hi = 0.0f, lo = 0.0f;
+            for (int r = 0; r < 32; ++r) {
+                float s, e;
+                two_sum(hi, red[(g * 32 + r) * (RED_COLS_F32 + 1) + col], s, e);
+                hi = s;
+                lo += e;
+            }
+            grp[(g * 32 + col) * 2] = hi;
+            grp[(g * 32 + col) * 2 + 1] = lo;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            const int a = ch * RED_COLS_F32 + tid;
+            if (a < NA) {
+                float hi = grp[tid * 2], lo = grp[tid * 2 + 1];
+                for (int g = 1; g < 8; ++g) df_add(hi, lo, grp[(g * 32 + tid) * 2], grp[(g * 32 + tid) * 2 + 1]);
+                const int h = acc_to_packed(L, M0, a);
+                out_hi[h] = hi;
+                out_lo[h] = lo;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void reduce_write_f64(const double* acc, char* smem, int L, int M0, double* out)
+{
+    double* red = reinterpret_cast<double*>(smem);                   // [WG][17]
+    double* grp = red + WG * (RED_COLS_F64 + 1);                      // [16][16]
+    const int tid = threadIdx.x;
+    constexpr int NCH = (NA + RED_COLS_F64 - 1) / RED_COLS_F64;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+        for (int j = 0; j < RED_COLS_F64; ++j) {
+            const int a = ch * RED_COLS_F64 + j;
+            red[tid * (RED_COLS_F64 + 1) + j] = (a < NA) ? acc[a < NA ? a : 0] : 0.0;
+        }
+        __syncthreads();
+        {
+            const int col = tid & 15, g = tid >> 4;                   // 16 groups of 16 rows
+            double s = 0.0;
+            for (int r = 0; r < 16; ++r) s += red[(g * 16 + r) * (RED_COLS_F64 + 1) + col];
+            grp[g * 16 + col] = s;
+        }
+        __syncthreads();
+        if (tid < 16) {
+            const int a = ch * RED_COLS_F64 + tid;
+            if (a < NA) {
+                double s = grp[tid];
+                for (int g = 1; g < 16; ++g) s += grp[g * 16 + tid];
+                out[acc_to_packed(L, M0, a)] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per-atom prologue shared by both precisions: FP64 centring and scaling, |r|^2 in FP64.
+struct AtomIn {
+    double x, y, z, q;
+};
+
+typedef __attribute__((address_space(1))) const double gdouble;
+
+__device__ __forceinline__ double gload(const double* p, int64_t i) { return ((gdouble*)p)[i]; }
+
+__device__ __forceinline__ AtomIn load_atom(const MolWork& mw, int64_t a)
+{
+    AtomIn v;
+    v.x = gload(mw.x, a);
+    v.y = gload(mw.y, a);
+    v.z = gload(mw.z, a);
+    v.q = gload(mw.q, a);
+    return v;
+}
+
+template <typename F, int L, int M0, int M1>
+__device__ __forceinline__ void tile_item(const TileCtx& tc, const DevPlan& P, char* smem)
+{
+    constexpr int NA = acc_count(L, M0, M1);
+    const MolWork& mw = *tc.mw;
+    F acc[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = (F)0;
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)tc.tile * WG * mw.kper + tid;
+    double r2max = 0.0;
+    int64_t a = base;
+    AtomIn nxt;
+    bool have = a < mw.n;
+    if (have) nxt = load_atom(mw, a);
+    for (int i = 0; i < mw.kper && have; ++i) {
+        const AtomIn cur = nxt;
+        a += WG;
+        have = (i + 1 < mw.kper) && (a < mw.n);
+        if (have) nxt = load_atom(mw, a);
+        const double dx = cur.x - tc.cx, dy = cur.y - tc.cy, dz = cur.z - tc.cz;
+        r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
+        const F px = (F)(dx * tc.inv_s), py = (F)(dy * tc.inv_s), pz = (F)(dz * tc.inv_s);
+        const F r2 = px * px + py * py + pz * pz;
+        F ir, r;
+        if constexpr (sizeof(F) == 4) {
+            ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+            r = r2 * ir;
+        } else {
+            r = sqrt(r2);
+            ir = r > 0.0 ? 1.0 / r : 0.0;
+        }
+        atom_block<F, L, M0, M1>(acc, pz * ir, px * ir, py * ir, r, (F)cur.q);
+    }
+    const int64_t nt = mw.ntiles;
+    if constexpr (sizeof(F) == 4) {
+        float* hi = P.part_f + mw.part_off + (int64_t)tc.tile * nh(L);
+        float* lo = P.part_f + mw.part_off + (nt + tc.tile) * nh(L);
+        reduce_write_f32<NA>(acc, smem, L, M0, hi, lo);
+    } else {
+        reduce_write_f64<NA>(acc, smem, L, M0, P.part_d + mw.part_off + (int64_t)tc.tile * nh(L));
+    }
+    if (tc.blk == 0) {                                   // max |r|^2 of the tile (FP64)
+        double* red = reinterpret_cast<double*>(smem);
+        red[tid] = r2max;
+        __syncthreads();
+        for (int s = WG / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+            __syncthreads();
+        }
+        if (tid == 0) P.r2_part[mw.r2_off + tc.tile] = red[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ dispatch over (L, block)
+template <typename F, int L, int B>
+__device__ __forceinline__ void dispatch_block(const TileCtx& tc, const DevPlan& P, char* smem)
+{
+    constexpr int BUDGET = sizeof(F) == 4 ? BUDGET_F32 : BUDGET_F64;
+    constexpr Partition part = make_partition(L, BUDGET);
+    if constexpr (B < part.nb) {
+        if (tc.blk == B) {
+            tile_item<F, L, part.start[B], part.start[B + 1] - 1>(tc, P, smem);
+            return;
+        }
+        dispatch_block<F, L, B + 1>(tc, P, smem);
+    }
+}
+
+// Fixed-order merge of the tile partials of one molecule; unscale to physical moments.
+__device__ inline void finalize_moments(const DevPlan& P, int mol, char* smem)
+{
+    const MolWork& mw = P.mols[mol];
+    const int tid = threadIdx.x;
+    const int L = mw.L, NHl = nh(L);
+    double* spow = reinterpret_cast<double*>(smem);       // s^l, l = 0..L
+    double* red = spow + (LMAX + 2);
+    if (tid == 0) {
+        const double s = mw.meta[4];
+        spow[0] = 1.0;
+        for (int l = 1; l <= L; ++l) spow[l] = spow[l - 1] * s;
+    }
+    double r2 = 0.0;
+    for (int t = tid; t < mw.ntiles; t += WG) r2 = fmax(r2, P.r2_part[mw.r2_off + t]);
+    red[tid] = r2;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const int64_t nt = mw.ntiles;
+    for (int h = tid; h < NHl; h += WG) {
+        double v;
+        if (mw.prec == TCM_F32C) {
+            const float* hi = P.part_f + mw.part_off;
+            const float* lo = P.part_f + mw.part_off + nt * NHl;
+            float H = 0.0f, Lo = 0.0f;
+            for (int64_t t = 0; t < nt; ++t) df_add(H, Lo, hi[t * NHl + h], lo[t * NHl + h]);
+            v = (double)H + (double)Lo;
+        } else {
+            const double* pd = P.part_d + mw.part_off;
+            v = 0.0;
+            for (int64_t t = 0; t < nt; ++t) v += pd[t * NHl + h];
+        }
+        mw.Q[h] = v * P.invk[h] * spow[l_of(h)];
+    }
+    if (tid == 0) mw.meta[3] = sqrt(red[0]);
+    __threadfence();                 // every thread publishes its writes before the flag
+    __syncthreads();
+}
+
+template <typename F, int L>
+__device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j, char* smem, int* s_misc)
+{
+    const MolWork& mw = P.mols[mol];
+    if (!wg_wait_flag(&P.sync[4 * mol + 1], P, s_misc)) return;
+    TileCtx tc;
+    tc.mw = &mw;
+    tc.tile = j / mw.nblk;
+    tc.blk = j % mw.nblk;
+    tc.cx = mw.meta[0];
+    tc.cy = mw.meta[1];
+    tc.cz = mw.meta[2];
+    tc.inv_s = 1.0 / mw.meta[4];
+    dispatch_block<F, L, 0>(tc, P, smem);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_misc[0] = atomic_add_acqrel(&P.sync[4 * mol + 2], 1);
+    __syncthreads();
+    if (s_misc[0] != mw.ntiles * mw.nblk - 1) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    finalize_moments(P, mol, smem);
+    if (threadIdx.x == 0) atomic_store_rel(&P.sync[4 * mol + 3], 1);
+    __syncthreads();
+}
+
+__device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int item)
+{
+    int lo = 0, hi = n;                        // prefix[lo] <= item < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Persistent kernel over the tile items [begin, end) of the molecules of one (precision, L)
+// group.  Workgroups claim items from queue[slot] until the range is exhausted.
+template <typename F, int L>
+__global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int slot, int begin, int end)
+{
+    __shared__ __align__(16) char smem[TILE_SMEM_BYTES];
+    __shared__ int s_item;
+    __shared__ int s_misc[4];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int it = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = end;
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= end) break;
+        const int j = item - P.n_stats;
+        const int mol = find_owner(P.tile_prefix, P.nmol, j);
+        tile_item_entry<F, L>(P, mol, j - P.tile_prefix[mol], smem, s_misc);
+        __syncthreads();
+    }
+}
+
+#define TCM_TILE_CASE(F, LL)                                                                   \
+    case LL:                                                                                   \
+        hipLaunchKernelGGL((tcm_tiles<F, LL>), dim3(grid), dim3(WG), 0, s, P, slot, begin, end); \
+        break;
+
+}  // namespace tcm

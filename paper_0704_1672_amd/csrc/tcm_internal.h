@@ -1,0 +1,155 @@
+// Internal definitions shared by the HIP kernels and the host runtime of libtcm.
+//
+// Work decomposition of one batch (one launch of the persistent kernel):
+//   item kinds, in queue order
+//     STATS  (molecule, chunk)          centroid sums + bounding box of a chunk of atoms
+//     TILE   (molecule, tile, m-block)  eq. (8) moments of 256*kper atoms for one m-block
+//     PAIR   (pair)                     pose rotation, geometric factors, eq. (9) contraction
+//   the last STATS item of a molecule finalises its centre and scale; the last TILE item
+//   finalises its moments (fixed-order merge of the tile partials); PAIR items wait on both
+//   molecules.  Dependencies always point to earlier queue positions, which running
+//   workgroups have already claimed, so every wait ends.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcm {
+
+constexpr int LMAX = 32;           // largest multipole order the library accepts
+constexpr int WG = 256;            // threads per workgroup (4 wave64s)
+constexpr int STATS_PER_THREAD = 32;
+constexpr int STATS_CHUNK = WG * STATS_PER_THREAD;   // atoms per STATS item
+
+__host__ __device__ constexpr int nh(int L) { return (L + 1) * (L + 1); }
+
+// Per molecule whose moments are computed in this batch.
+struct MolWork {
+    const double* x;               // FP64 SoA coordinates and charges (device)
+    const double* y;
+    const double* z;
+    const double* q;
+    int64_t n;
+    int32_t L;                     // order computed (moment table (L+1)^2)
+    int32_t prec;                  // 0 = FP64 path, 1 = FP32 compensated path
+    int32_t kper;                  // atoms per thread per tile
+    int32_t nblk;                  // m-blocks for (prec, L)
+    int32_t ntiles;
+    int32_t nstats;
+    int32_t has_centre;
+    int32_t pad0;
+    double centre[3];              // used when has_centre
+    double* Q;                     // out: (L+1)^2 FP64 packed moments
+    double* meta;                  // out: [0..2] centre, [3] radius, [4] scale
+    int64_t part_off;              // element offset of the tile partials
+    int64_t stats_off;             // record offset of the STATS partials (10 doubles each)
+    int64_t r2_off;                // offset of the per-tile max |r|^2 partials
+};
+
+// Per requested pair energy.
+struct PairWork {
+    const double* QA;              // packed FP64 moments, order >= L
+    const double* QB;
+    const double* metaA;           // meta[3] = radius of A (eq. (2))
+    const double* metaB;
+    int32_t depA;                  // molecule index in this batch to wait for, or -1
+    int32_t depB;
+    int32_t L;
+    int32_t flags;                 // TCM_UNCHECKED skips the eq. (2) test
+    double R[3];                   // c_B - c_A
+    double quat[4];                // active rotation of B about c_B, (w, x, y, z)
+    int32_t has_rot;
+    int32_t out;                   // index into U / status
+};
+
+struct DevPlan {
+    const MolWork* mols;
+    const PairWork* pairs;
+    const int32_t* stats_prefix;   // nmol+1 cumulative STATS items
+    const int32_t* tile_prefix;    // nmol+1 cumulative TILE items (ntiles * nblk)
+    int32_t nmol;
+    int32_t npairs;
+    int32_t n_stats;
+    int32_t n_tiles;
+    // synchronisation state, cleared before each run by a fill kernel
+    int32_t* sync;                 // [4*nmol] stats_cnt, stats_done, tile_cnt, mom_done
+    int32_t* queue;                // one claim counter per launch of the run
+    int32_t* err;                  // [1] set when a bounded wait expires
+    // scratch
+    float* part_f;                 // FP32 path tile partials (hi block, then lo block)
+    double* part_d;                // FP64 path tile partials
+    double* stats_part;            // STATS partials, 10 doubles per item
+    double* r2_part;               // per-tile max |r|^2 (FP64)
+    // outputs
+    double* U;
+    int32_t* status;
+    // FP64 coefficient tables (device)
+    const double* invk;            // 1/k_lm of the normalised recurrence, per packed index
+    const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
+    const double* rot;             // rotation tables: for each l, D then D^{-1}, (2l+1)^2 each
+    int64_t spin_limit;            // bound on every device-side wait
+};
+
+// Packed index helpers (layout of every moment table at the boundary):
+//   m = 0: l*l ; m > 0: Re at l*l + 2m - 1, Im at l*l + 2m.
+__host__ __device__ inline int l_of(int h)
+{
+    int l = 0;
+    while ((l + 1) * (l + 1) <= h) ++l;
+    return l;
+}
+
+// m-block partition of the (l, m >= 0) harmonics for the moment tile.  Accumulator cost
+// of the m-chain is (L-m+1) values (times 2 for m > 0: real and imaginary parts).
+__host__ __device__ constexpr int chain_cost(int L, int m) { return (L - m + 1) * (m > 0 ? 2 : 1); }
+
+__host__ __device__ constexpr int total_cost(int L)
+{
+    int t = 0;
+    for (int m = 0; m <= L; ++m) t += chain_cost(L, m);
+    return t;
+}
+
+// Partition of m = 0..L into contiguous m-blocks so that no block holds more than `budget`
+// accumulators; each block takes up to an even share of the remaining cost.
+struct Partition {
+    int nb;
+    int start[LMAX + 2];
+};
+
+__host__ __device__ constexpr Partition make_partition(int L, int budget)
+{
+    Partition p{};
+    const int total = total_cost(L);
+    for (int nb = (total + budget - 1) / budget;; ++nb) {
+        int m = 0, blk = 0, remaining = total;
+        bool ok = true;
+        while (m <= L) {
+            if (blk == nb) { ok = false; break; }
+            p.start[blk] = m;
+            int share = (remaining + (nb - blk) - 1) / (nb - blk);
+            if (share > budget) share = budget;
+            int used = 0;
+            const int m0 = m;
+            while (m <= L && (m == m0 || used + chain_cost(L, m) <= share)) {
+                used += chain_cost(L, m);
+                ++m;
+            }
+            if (used > budget) ok = false;
+            remaining -= used;
+            ++blk;
+        }
+        if (ok) {
+            p.nb = blk;
+            p.start[blk] = L + 1;
+            return p;
+        }
+    }
+}
+
+__host__ __device__ constexpr int num_blocks(int L, int budget) { return make_partition(L, budget).nb; }
+__host__ __device__ constexpr int block_start(int L, int budget, int b) { return make_partition(L, budget).start[b]; }
+
+constexpr int BUDGET_F32 = 160;    // FP32 accumulators per thread per m-block
+constexpr int BUDGET_F64 = 64;     // FP64 accumulators per thread per m-block
+
+}  // namespace tcm

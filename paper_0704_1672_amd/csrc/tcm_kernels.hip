@@ -1,0 +1,375 @@
+// Statistics (a0) and pair (a3-a5) kernels of libtcm, the clear kernel, and the launchers.
+#include "tcm_device.h"
+
+namespace tcm {
+
+// ------------------------------------------------------------------ STATS items
+__device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk, char* smem, int* s_misc)
+{
+    const MolWork& mw = P.mols[mol];
+    const int tid = threadIdx.x;
+    double v[9] = {0, 0, 0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    const int64_t base = (int64_t)chunk * STATS_CHUNK;
+    for (int i = 0; i < STATS_PER_THREAD; ++i) {
+        const int64_t a = base + tid + (int64_t)i * WG;
+        if (a >= mw.n) break;
+        const double x = mw.x[a], y = mw.y[a], z = mw.z[a];
+        v[0] += x; v[1] += y; v[2] += z;
+        v[3] = fmin(v[3], x); v[4] = fmin(v[4], y); v[5] = fmin(v[5], z);
+        v[6] = fmax(v[6], x); v[7] = fmax(v[7], y); v[8] = fmax(v[8], z);
+    }
+    double* red = reinterpret_cast<double*>(smem);   // [9][WG]
+    for (int k = 0; k < 9; ++k) red[k * WG + tid] = v[k];
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            for (int k = 0; k < 3; ++k) red[k * WG + tid] += red[k * WG + tid + s];
+            for (int k = 3; k < 6; ++k) red[k * WG + tid] = fmin(red[k * WG + tid], red[k * WG + tid + s]);
+            for (int k = 6; k < 9; ++k) red[k * WG + tid] = fmax(red[k * WG + tid], red[k * WG + tid + s]);
+        }
+        __syncthreads();
+    }
+    double* rec = P.stats_part + (mw.stats_off + chunk) * 10;
+    if (tid < 9) rec[tid] = red[tid * WG];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_misc[0] = atomic_add_acqrel(&P.sync[4 * mol + 0], 1);
+    __syncthreads();
+    if (s_misc[0] != mw.nstats - 1) return;
+    // last chunk of this molecule: merge chunk records in order
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    if (tid == 0) {
+        double sx = 0, sy = 0, sz = 0;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int c = 0; c < mw.nstats; ++c) {
+            const double* r = P.stats_part + (mw.stats_off + c) * 10;
+            sx += r[0]; sy += r[1]; sz += r[2];
+            for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], r[3 + d]); hi[d] = fmax(hi[d], r[6 + d]); }
+        }
+        double c[3];
+        if (mw.has_centre || mw.n == 0) {
+            c[0] = mw.centre[0]; c[1] = mw.centre[1]; c[2] = mw.centre[2];
+        } else {
+            c[0] = sx / (double)mw.n; c[1] = sy / (double)mw.n; c[2] = sz / (double)mw.n;
+        }
+        double s2 = 0.0;
+        if (mw.n > 0)
+            for (int d = 0; d < 3; ++d) {
+                const double e = fmax(fabs(hi[d] - c[d]), fabs(c[d] - lo[d]));
+                s2 += e * e;
+            }
+        double s = sqrt(s2);
+        if (!(s > 0.0)) s = 1.0;
+        mw.meta[0] = c[0]; mw.meta[1] = c[1]; mw.meta[2] = c[2];
+        mw.meta[4] = s;
+        __threadfence();
+        atomic_store_rel(&P.sync[4 * mol + 1], 1);
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ PAIR items
+// LDS layout (doubles): sA[NH(LMAX)], sB[NH(LMAX)], sI[2*(2LMAX+1)(2LMAX+2)/2] (the rotation
+// temporary aliases sI), spow[2LMAX+2], scs[3][LMAX+1][2], red[WG].
+constexpr int NHMAX = nh(LMAX);
+constexpr int NI = (2 * LMAX + 1) * (2 * LMAX + 2) / 2;
+
+__device__ void rot_phase(double* v, int L, const double* cs /*[LMAX+1][2]*/)
+{
+    // (Re, Im) of each m > 0 rotated by m*angle: Q_lm -> e^{i m angle} Q_lm
+    const int NHl = nh(L);
+    for (int h = threadIdx.x; h < NHl; h += WG) {
+        const int l = l_of(h), off = h - l * l;
+        if (off & 1) {                         // Re part of m = (off+1)/2
+            const int m = (off + 1) >> 1;
+            const double c = cs[2 * m], s = cs[2 * m + 1];
+            const double re = v[h], im = v[h + 1];
+            v[h] = c * re - s * im;
+            v[h + 1] = s * re + c * im;
+        }
+    }
+}
+
+__device__ void rot_matvec(const double* tab, const double* in, double* out, int L, bool inverse)
+{
+    const int NHl = nh(L);
+    for (int h = threadIdx.x; h < NHl; h += WG) {
+        const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
+        // tables for order l start at 2 * sum_{j<l} (2j+1)^2 = 2 l (4l^2-1)/3
+        const double* D = tab + (int64_t)2 * l * (4 * l * l - 1) / 3 + (inverse ? n * n : 0) + (int64_t)i * n;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += D[j] * in[l * l + j];
+        out[h] = s;
+    }
+}
+
+__device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem, int* s_misc)
+{
+    const PairWork& pw = P.pairs[p];
+    const int tid = threadIdx.x;
+    if (pw.depA >= 0 && !wg_wait_flag(&P.sync[4 * pw.depA + 3], P, s_misc)) return;
+    if (pw.depB >= 0 && !wg_wait_flag(&P.sync[4 * pw.depB + 3], P, s_misc)) return;
+    const int L = pw.L, NHl = nh(L);
+    const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
+    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    const double aA = pw.metaA[3], aB = pw.metaB[3];
+    if (!(Rn > 0.0) || (!(pw.flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
+        if (tid == 0) {
+            P.status[pw.out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
+            P.U[pw.out] = __builtin_nan("");
+        }
+        return;
+    }
+    double* sA = reinterpret_cast<double*>(smem);
+    double* sB = sA + NHMAX;
+    double* sI = sB + NHMAX;                 // complex, index (L'(L'+1)/2 + M)
+    double* sT = sI;                         // rotation temporary (before sI is built)
+    double* spow = sI + 2 * NI;
+    double* scs = spow + (2 * LMAX + 2);     // [3][LMAX+1][2]
+    double* red = scs + 3 * (LMAX + 1) * 2;
+    if (tid == 0) {
+        const double ir = 1.0 / Rn;
+        spow[0] = 1.0;
+        for (int l = 1; l <= 2 * L + 1; ++l) spow[l] = spow[l - 1] * ir;
+    }
+    if (pw.has_rot && tid <= L) {
+        // ZYZ Euler angles of the unit quaternion: R = Rz(alpha) Ry(beta) Rz(gamma)
+        const double qn = sqrt(pw.quat[0] * pw.quat[0] + pw.quat[1] * pw.quat[1] +
+                               pw.quat[2] * pw.quat[2] + pw.quat[3] * pw.quat[3]);
+        const double w = pw.quat[0] / qn, x = pw.quat[1] / qn, y = pw.quat[2] / qn, z = pw.quat[3] / qn;
+        const double beta = 2.0 * atan2(sqrt(x * x + y * y), sqrt(w * w + z * z));
+        const double ap = atan2(z, w), am = atan2(-x, y);
+        const double ang[3] = {ap - am /*gamma*/, beta, ap + am /*alpha*/};
+        for (int k = 0; k < 3; ++k) {
+            double s, c;
+            sincos(tid * ang[k], &s, &c);
+            scs[(k * (LMAX + 1) + tid) * 2] = c;
+            scs[(k * (LMAX + 1) + tid) * 2 + 1] = s;
+        }
+    }
+    __syncthreads();
+    for (int h = tid; h < NHl; h += WG) {
+        const double sc = spow[l_of(h)];
+        sA[h] = pw.QA[h] * sc * P.invf[h];
+        sB[h] = pw.QB[h] * sc;
+    }
+    __syncthreads();
+    if (pw.has_rot) {
+        // Q' = Z(alpha) D^{-1} Z(beta) D Z(gamma) Q, D = representation of a +90 degree
+        // rotation about x, Z(phi) = diag(e^{i m phi})
+        rot_phase(sB, L, scs);
+        __syncthreads();
+        rot_matvec(P.rot, sB, sT, L, false);
+        __syncthreads();
+        rot_phase(sT, L, scs + 2 * (LMAX + 1));
+        __syncthreads();
+        rot_matvec(P.rot, sT, sB, L, true);
+        __syncthreads();
+        rot_phase(sB, L, scs + 4 * (LMAX + 1));
+        __syncthreads();
+    }
+    for (int h = tid; h < NHl; h += WG) sB[h] *= P.invf[h];
+    // irregular harmonics of the unit vector n = R/|R|, factorial-scaled:
+    //   I_00 = 1, I_MM = -(2M-1)(nx + i ny) I_{M-1,M-1}, I_{M+1,M} = (2M+1) nz I_MM,
+    //   I_LM = (2L-1) nz I_{L-1,M} - ((L-1)^2 - M^2) I_{L-2,M}
+    const int L2 = 2 * L;
+    if (tid <= L2) {
+        const int M = tid;
+        const double nx = Rx / Rn, ny = Ry / Rn, nz = Rz / Rn;
+        double cr = 1.0, ci = 0.0;
+        for (int k = 1; k <= M; ++k) {
+            const double f = -(2.0 * k - 1.0);
+            const double tr = f * (cr * nx - ci * ny);
+            ci = f * (cr * ny + ci * nx);
+            cr = tr;
+        }
+        double pr = 0.0, pi = 0.0;         // I_{L-2,M}
+        double qr = cr, qi = ci;           // I_{L-1,M}
+        sI[2 * (M * (M + 1) / 2 + M)] = cr;
+        sI[2 * (M * (M + 1) / 2 + M) + 1] = ci;
+        for (int Lp = M + 1; Lp <= L2; ++Lp) {
+            const double a = 2.0 * Lp - 1.0, b = (Lp - 1.0) * (Lp - 1.0) - (double)M * M;
+            const double nr = a * nz * qr - b * pr, ni = a * nz * qi - b * pi;
+            pr = qr; pi = qi; qr = nr; qi = ni;
+            sI[2 * (Lp * (Lp + 1) / 2 + M)] = nr;
+            sI[2 * (Lp * (Lp + 1) / 2 + M) + 1] = ni;
+        }
+    }
+    __syncthreads();
+    // rows (l1, m1 >= 0): V = sum_{l2, m2} (-1)^{l2} b_{l2 m2} conj(I_{l1+l2, m1+m2})
+    // (negative m2 folded in through b_{l,-m} = (-1)^m conj(b_lm)); U = Re sum w a V.
+    double Upart = 0.0;
+    const int nrows = (L + 1) * (L + 2) / 2;
+    for (int r = tid; r < nrows; r += WG) {
+        int l1 = 0;
+        while ((l1 + 1) * (l1 + 2) / 2 <= r) ++l1;
+        const int m1 = r - l1 * (l1 + 1) / 2;
+        double Vr = 0.0, Vi = 0.0;
+        for (int l2 = 0; l2 <= L; ++l2) {
+            const int Lp = l1 + l2;
+            const double* Irow = sI + 2 * (Lp * (Lp + 1) / 2);
+            double vr = 0.0, vi = 0.0;
+            {   // m2 = 0
+                const double br = sB[l2 * l2];
+                const double Ir = Irow[2 * m1], Ii = Irow[2 * m1 + 1];
+                vr += br * Ir;
+                vi -= br * Ii;
+            }
+            for (int m2 = 1; m2 <= l2; ++m2) {
+                const double br = sB[l2 * l2 + 2 * m2 - 1], bi = sB[l2 * l2 + 2 * m2];
+                // b * conj(I_{Lp, m1+m2})
+                const double Ir = Irow[2 * (m1 + m2)], Ii = Irow[2 * (m1 + m2) + 1];
+                vr += br * Ir + bi * Ii;
+                vi += bi * Ir - br * Ii;
+                // (-1)^{m2} conj(b) * conj(I_{Lp, m1-m2})
+                const int M = m1 - m2;
+                double Jr, Ji;                       // conj(I_{Lp, M})
+                if (M >= 0) {
+                    Jr = Irow[2 * M];
+                    Ji = -Irow[2 * M + 1];
+                } else {                             // = (-1)^M I_{Lp, -M}
+                    const double sg = ((-M) & 1) ? -1.0 : 1.0;
+                    Jr = sg * Irow[2 * (-M)];
+                    Ji = sg * Irow[2 * (-M) + 1];
+                }
+                const double sg2 = (m2 & 1) ? -1.0 : 1.0;
+                vr += sg2 * (br * Jr + bi * Ji);
+                vi += sg2 * (br * Ji - bi * Jr);
+            }
+            if (l2 & 1) { Vr -= vr; Vi -= vi; } else { Vr += vr; Vi += vi; }
+        }
+        double ar, ai;
+        if (m1 == 0) { ar = sA[l1 * l1]; ai = 0.0; }
+        else { ar = sA[l1 * l1 + 2 * m1 - 1]; ai = sA[l1 * l1 + 2 * m1]; }
+        const double t = ar * Vr - ai * Vi;
+        Upart += (m1 == 0) ? t : 2.0 * t;
+    }
+    red[tid] = Upart;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        P.U[pw.out] = red[0] / Rn;
+        P.status[pw.out] = TCM_OK;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int slot, int begin, int end)
+{
+    __shared__ __align__(16) char smem[9 * WG * sizeof(double)];
+    __shared__ int s_item;
+    __shared__ int s_misc[4];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= end) break;
+        const int mol = find_owner(P.stats_prefix, P.nmol, item);
+        stats_item(P, mol, item - P.stats_prefix[mol], smem, s_misc);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(WG) void tcm_pairs(DevPlan P, int slot, int begin, int end)
+{
+    __shared__ __align__(16) char smem[SMEM_BYTES];
+    __shared__ int s_item;
+    __shared__ int s_misc[4];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int it = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = end;
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= end) break;
+        pair_item(P, item, smem, s_misc);
+        __syncthreads();
+    }
+}
+
+// Clears the synchronisation state of a run (a kernel, not a memset, so that it can sit
+// in a captured graph).
+__global__ void tcm_clear(int32_t* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+template <typename F>
+struct NumBlocksTable {
+    int v[LMAX + 1];
+    constexpr NumBlocksTable() : v()
+    {
+        for (int L = 0; L <= LMAX; ++L) v[L] = num_blocks(L, sizeof(F) == 4 ? BUDGET_F32 : BUDGET_F64);
+    }
+};
+
+int num_blocks_for(int prec, int L)
+{
+    static constexpr NumBlocksTable<float> t32{};
+    static constexpr NumBlocksTable<double> t64{};
+    if (L < 0 || L > LMAX) return 0;
+    return prec == TCM_F32C ? t32.v[L] : t64.v[L];
+}
+
+hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int grid = (int)((n + 255) / 256);
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(tcm_clear, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+{
+    if (end <= begin) return hipSuccess;
+    if (grid > end - begin) grid = end - begin;
+    hipLaunchKernelGGL(tcm_stats, dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+{
+    if (end <= begin) return hipSuccess;
+    if (grid > end - begin) grid = end - begin;
+    hipLaunchKernelGGL(tcm_pairs, dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_f32_a(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f32_d(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f64_a(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f64_b(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f64_c(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f64_d(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+{
+    if (end <= begin) return hipSuccess;
+    if (grid > end - begin) grid = end - begin;
+    if (prec == TCM_F32C) {
+        if (L <= 12) return launch_tiles_f32_a(L, P, slot, begin, end, grid, s);
+        if (L <= 20) return launch_tiles_f32_b(L, P, slot, begin, end, grid, s);
+        if (L <= 26) return launch_tiles_f32_c(L, P, slot, begin, end, grid, s);
+        return launch_tiles_f32_d(L, P, slot, begin, end, grid, s);
+    }
+    if (L <= 12) return launch_tiles_f64_a(L, P, slot, begin, end, grid, s);
+    if (L <= 20) return launch_tiles_f64_b(L, P, slot, begin, end, grid, s);
+    if (L <= 26) return launch_tiles_f64_c(L, P, slot, begin, end, grid, s);
+    return launch_tiles_f64_d(L, P, slot, begin, end, grid, s);
+}
+
+}  // namespace tcm

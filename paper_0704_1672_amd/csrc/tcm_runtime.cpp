@@ -1,0 +1,1164 @@
+// Host runtime of libtcm: context and FP64 coefficient tables, resident molecules, the
+// batch planner, graph-captured plans, tuning.  Every arithmetic step of the method runs
+// in the HIP kernels of tcm_kernels.hip; the host only validates, plans and copies.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <string>
+
+#include "tcm_runtime.h"
+
+namespace tcm {
+
+// ------------------------------------------------------------------ buffers
+int Ctx::alloc(DevBuf& b, size_t bytes)
+{
+    if (bytes <= b.cap && b.p) return TCM_OK;
+    size_t want = bytes < 256 ? 256 : bytes;
+    if (b.p) {
+        if (hipFree(b.p) != hipSuccess) return TCM_EDEVICE;
+        used -= b.cap;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    if (budget && used.load() + want > budget) return TCM_ENOMEM;
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCM_ENOMEM;
+    }
+    b.p = p;
+    b.cap = want;
+    used += want;
+    return TCM_OK;
+}
+
+void Ctx::release(DevBuf& b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        used -= b.cap;
+    }
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+int Ctx::ensure_pinned(size_t bytes)
+{
+    if (bytes <= hpin_cap && hpin) return TCM_OK;
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
+    hpin_cap = 0;
+    size_t want = bytes < 4096 ? 4096 : bytes;
+    if (hipHostMalloc(&hpin, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCM_ENOMEM;
+    }
+    hpin_cap = want;
+    return TCM_OK;
+}
+
+static int bucket_of(int64_t n)
+{
+    int b = 0;
+    while (b < 40 && (int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+int64_t tune_key(int prec, int L, int64_t n) { return (int64_t)prec * 100000 + L * 100 + bucket_of(n); }
+
+// Atoms per thread per tile.  A function of (precision, L, n) only, so a molecule's tiling --
+// and therefore every rounding of its moments -- is the same whatever else shares a launch.
+int Ctx::kper_for(int prec, int L, int64_t n)
+{
+    auto it = tune.find(tune_key(prec, L, n));
+    if (it != tune.end()) return it->second;
+    // default: aim at ~16 tiles per molecule, 4 <= kper <= 64, powers of two
+    int64_t want = n / (WG * 16);
+    int k = 4;
+    while (k < 64 && k < want) k <<= 1;
+    return k;
+}
+
+// ------------------------------------------------------------------ FP64 tables
+// Racah-normalised solid harmonics C_lm(x, y, z), packed, m >= 0, by the standard
+// recurrences (used only to build the rotation tables below).
+static void racah_packed(int L, double x, double y, double z, double* out)
+{
+    const double r2 = x * x + y * y + z * z;
+    std::vector<double> cr((L + 1) * (L + 1)), ci((L + 1) * (L + 1));
+    auto at = [&](int l, int m) { return l * (l + 1) / 2 + m; };
+    cr.assign((L + 1) * (L + 2) / 2, 0.0);
+    ci.assign((L + 1) * (L + 2) / 2, 0.0);
+    cr[0] = 1.0;
+    for (int m = 1; m <= L; ++m) {
+        const double f = -std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+        const double pr = cr[at(m - 1, m - 1)], pi = ci[at(m - 1, m - 1)];
+        cr[at(m, m)] = f * (x * pr - y * pi);
+        ci[at(m, m)] = f * (x * pi + y * pr);
+    }
+    for (int m = 0; m < L; ++m) {
+        const double f = std::sqrt(2.0 * m + 1.0) * z;
+        cr[at(m + 1, m)] = f * cr[at(m, m)];
+        ci[at(m + 1, m)] = f * ci[at(m, m)];
+    }
+    for (int m = 0; m <= L; ++m)
+        for (int l = m + 2; l <= L; ++l) {
+            const double d = std::sqrt((double)l * l - (double)m * m);
+            const double a = (2.0 * l - 1.0) / d;
+            const double b = std::sqrt(((double)l - 1.0) * (l - 1.0) - (double)m * m) / d;
+            cr[at(l, m)] = a * z * cr[at(l - 1, m)] - b * r2 * cr[at(l - 2, m)];
+            ci[at(l, m)] = a * z * ci[at(l - 1, m)] - b * r2 * ci[at(l - 2, m)];
+        }
+    for (int l = 0; l <= L; ++l) {
+        out[l * l] = cr[at(l, 0)];
+        for (int m = 1; m <= l; ++m) {
+            out[l * l + 2 * m - 1] = cr[at(l, m)];
+            out[l * l + 2 * m] = ci[at(l, m)];
+        }
+    }
+}
+
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = t; p0 = 1.0; }
+            const double dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (t * p1 - p0) / (t * t - 1.0);
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+// Rotation tables.  D^l maps the packed order-l moments of a set of charges to those of the
+// charges rotated by +90 degrees about x ((x, y, z) -> (x, -z, y)); built by exact quadrature
+// of C_l(X p) C_l(p) over the sphere (Gauss-Legendre in cos theta with l+1 nodes, 2l+1
+// equispaced phi: exact for the degree-2l integrands).  The inverse follows from the
+// orthogonality norms g = 4pi/(2l+1) * (1 for m = 0, 1/2 for the Re/Im parts of m > 0):
+// invariance of the sphere measure gives D G D^T = G, so (D^{-1})_ij = D_ji g_i / g_j.
+// Layout: for each l, D then D^{-1}, row-major (2l+1)^2.
+static std::vector<double> build_rotation_tables(int Lmax)
+{
+    size_t total = 0;
+    for (int l = 0; l <= Lmax; ++l) total += 2 * (size_t)(2 * l + 1) * (2 * l + 1);
+    std::vector<double> out(total, 0.0);
+    size_t off = 0;
+    std::vector<double> cp((Lmax + 1) * (Lmax + 1)), cx((Lmax + 1) * (Lmax + 1));
+    for (int l = 0; l <= Lmax; ++l) {
+        const int n = 2 * l + 1;
+        std::vector<double> gx, gw;
+        gauss_legendre(l + 1, gx, gw);
+        std::vector<double> D(n * n, 0.0);
+        for (int a = 0; a <= l; ++a) {
+            const double ct = gx[a], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+            for (int b = 0; b < n; ++b) {
+                const double ph = 2.0 * M_PI * b / n;
+                const double px = st * std::cos(ph), py = st * std::sin(ph), pz = ct;
+                const double wt = gw[a] * 2.0 * M_PI / n;
+                racah_packed(l, px, py, pz, cp.data());
+                racah_packed(l, px, -pz, py, cx.data());
+                const double* u = cp.data() + l * l;
+                const double* v = cx.data() + l * l;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) D[i * n + j] += wt * v[i] * u[j];
+            }
+        }
+        const double g0 = 4.0 * M_PI / n;
+        auto g = [&](int i) { return i == 0 ? g0 : 0.5 * g0; };
+        double* Dout = out.data() + off;
+        double* Dinv = Dout + n * n;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Dout[i * n + j] = D[i * n + j] / g(j);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Dinv[i * n + j] = Dout[j * n + i] * g(i) / g(j);
+        off += 2 * (size_t)n * n;
+    }
+    return out;
+}
+
+// 1/k_lm of the normalised recurrence (k_mm = (-1)^m sqrt((2m)!)/(2m-1)!!,
+// k_{m+1,m} = k_mm / sqrt(2m+1), k_lm = k_{l-1,m} xi_lm / A_lm, A_lm = (2l-1)/sqrt(l^2-m^2))
+// and 1/sqrt((l+m)!(l-m)!), per packed index.
+static void build_norm_tables(int Lmax, std::vector<double>& invk, std::vector<double>& invf)
+{
+    const int NH = (Lmax + 1) * (Lmax + 1);
+    invk.assign(NH, 0.0);
+    invf.assign(NH, 0.0);
+    std::vector<long double> fact(2 * Lmax + 2);
+    fact[0] = 1.0L;
+    for (size_t i = 1; i < fact.size(); ++i) fact[i] = fact[i - 1] * (long double)i;
+    for (int m = 0; m <= Lmax; ++m) {
+        long double dfac = 1.0L;
+        for (int j = 1; j < 2 * m; j += 2) dfac *= j;
+        long double k = ((m & 1) ? -1.0L : 1.0L) * std::sqrt(fact[2 * m]) / dfac;
+        long double xi = 1.0L;
+        for (int l = m; l <= Lmax; ++l) {
+            if (l == m + 1) {
+                k = k / std::sqrt((long double)(2 * m + 1));
+            } else if (l >= m + 2) {
+                xi = ((2.0L * l - 1.0L) * (2.0L * l - 3.0L) / (((long double)l - 1 - m) * ((long double)l - 1 + m))) / xi;
+                const long double A = (2.0L * l - 1.0L) / std::sqrt((long double)l * l - (long double)m * m);
+                k = k * xi / A;
+            }
+            const double ik = (double)(1.0L / k);
+            const double f = (double)(1.0L / std::sqrt(fact[l + m] * fact[l - m]));
+            if (m == 0) {
+                invk[l * l] = ik;
+                invf[l * l] = f;
+            } else {
+                invk[l * l + 2 * m - 1] = invk[l * l + 2 * m] = ik;
+                invf[l * l + 2 * m - 1] = invf[l * l + 2 * m] = f;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ planning
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const std::vector<PairJob>& pairs_in,
+               BuiltPlan& bp, hipStream_t s)
+{
+    // molecules sorted by (precision, L): each group's tiles are one persistent launch of
+    // the tile kernel compiled for that order
+    const int nmol = (int)mols_in.size(), npairs = (int)pairs_in.size();
+    std::vector<int> order(nmol), newidx(nmol);
+    for (int i = 0; i < nmol; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+        if (mols_in[u].prec != mols_in[v].prec) return mols_in[u].prec < mols_in[v].prec;
+        return mols_in[u].L < mols_in[v].L;
+    });
+    std::vector<MolJob> mols(nmol);
+    for (int i = 0; i < nmol; ++i) {
+        mols[i] = mols_in[order[i]];
+        newidx[order[i]] = i;
+    }
+    std::vector<PairJob> pairs(pairs_in);
+    for (PairJob& pj : pairs) {
+        if (pj.depA >= 0) pj.depA = newidx[pj.depA];
+        if (pj.depB >= 0) pj.depB = newidx[pj.depB];
+    }
+    std::vector<MolWork> mw(nmol);
+    std::vector<PairWork> pw(npairs);
+    std::vector<int32_t> sp(nmol + 1, 0), tp(nmol + 1, 0);
+    int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0;
+    double flops = 0.0;
+    int64_t atoms = 0;
+    for (int i = 0; i < nmol; ++i) {
+        const MolJob& j = mols[i];
+        MolWork& w = mw[i];
+        w.x = j.x; w.y = j.y; w.z = j.z; w.q = j.q;
+        w.n = j.n;
+        w.L = j.L;
+        w.prec = j.prec;
+        w.kper = c->kper_for(j.prec, j.L, j.n);
+        w.nblk = num_blocks_for(j.prec, j.L);
+        const int64_t tile_atoms = (int64_t)WG * w.kper;
+        const int64_t nt = j.n > 0 ? (j.n + tile_atoms - 1) / tile_atoms : 1;
+        const int64_t ns = j.n > 0 ? (j.n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
+        if (nt > (1 << 24) || ns > (1 << 24)) return TCM_EINVAL;
+        w.ntiles = (int)nt;
+        w.nstats = (int)ns;
+        w.has_centre = j.has_centre;
+        w.centre[0] = j.centre[0]; w.centre[1] = j.centre[1]; w.centre[2] = j.centre[2];
+        w.Q = j.Q;
+        w.meta = j.meta;
+        w.stats_off = off_s;
+        w.r2_off = off_r2;
+        if (j.prec == TCM_F32C) {
+            w.part_off = off_f;
+            off_f += 2 * nt * nh(j.L);
+        } else {
+            w.part_off = off_d;
+            off_d += nt * nh(j.L);
+        }
+        off_s += ns;
+        off_r2 += nt;
+        sp[i + 1] = sp[i] + (int32_t)ns;
+        const int64_t ti = (int64_t)tp[i] + nt * w.nblk;
+        if (ti > (1 << 30)) return TCM_EINVAL;
+        tp[i + 1] = (int32_t)ti;
+        flops += 6.0 * (j.L + 1) * (j.L + 2) * (double)j.n;
+        atoms += j.n;
+    }
+    for (int p = 0; p < npairs; ++p) {
+        const PairJob& j = pairs[p];
+        PairWork& w = pw[p];
+        w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
+        w.depA = j.depA; w.depB = j.depB;
+        w.L = j.L; w.flags = j.flags;
+        for (int d = 0; d < 3; ++d) w.R[d] = j.R[d];
+        for (int d = 0; d < 4; ++d) w.quat[d] = j.quat[d];
+        w.has_rot = j.has_rot;
+        w.out = p;
+    }
+    // blob layout
+    const size_t o_mw = 0;
+    const size_t o_pw = align_up(o_mw + sizeof(MolWork) * nmol, 256);
+    const size_t o_sp = align_up(o_pw + sizeof(PairWork) * npairs, 256);
+    const size_t o_tp = align_up(o_sp + sizeof(int32_t) * (nmol + 1), 256);
+    const size_t blob = align_up(o_tp + sizeof(int32_t) * (nmol + 1), 256);
+    int rc;
+    if ((rc = c->alloc(ws.blob, blob)) != TCM_OK) return rc;
+    if (blob > ws.hstage_cap) {
+        if (ws.hstage) (void)hipHostFree(ws.hstage);
+        ws.hstage = nullptr;
+        ws.hstage_cap = 0;
+        if (hipHostMalloc(&ws.hstage, blob, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return TCM_ENOMEM;
+        }
+        ws.hstage_cap = blob;
+    }
+    // the staging buffer may still feed an earlier asynchronous copy
+    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    char* h = (char*)ws.hstage;
+    if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
+    if (npairs) std::memcpy(h + o_pw, pw.data(), sizeof(PairWork) * npairs);
+    std::memcpy(h + o_sp, sp.data(), sizeof(int32_t) * (nmol + 1));
+    std::memcpy(h + o_tp, tp.data(), sizeof(int32_t) * (nmol + 1));
+    bp.groups.clear();
+    for (int i = 0; i < nmol; ++i) {
+        if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L)
+            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i]});
+        bp.groups.back().end = tp[i + 1];
+    }
+    const int nqueue = 2 + (int)bp.groups.size();
+    const int64_t sync_ints = 4 * (int64_t)nmol + nqueue + 1;
+    if ((rc = c->alloc(ws.sync, sizeof(int32_t) * sync_ints)) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.part_f, sizeof(float) * (off_f > 0 ? off_f : 1))) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.part_d, sizeof(double) * (off_d > 0 ? off_d : 1))) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.stats, sizeof(double) * 10 * (off_s > 0 ? off_s : 1))) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.r2, sizeof(double) * (off_r2 > 0 ? off_r2 : 1))) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.outU, sizeof(double) * (npairs > 0 ? npairs : 1))) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.outS, sizeof(int32_t) * (npairs > 0 ? npairs : 1))) != TCM_OK) return rc;
+    if (hipMemcpyAsync(ws.blob.p, ws.hstage, blob, hipMemcpyHostToDevice, s) != hipSuccess) return TCM_EDEVICE;
+    char* d = (char*)ws.blob.p;
+    DevPlan& P = bp.P;
+    P.mols = (const MolWork*)(d + o_mw);
+    P.pairs = (const PairWork*)(d + o_pw);
+    P.stats_prefix = (const int32_t*)(d + o_sp);
+    P.tile_prefix = (const int32_t*)(d + o_tp);
+    P.nmol = nmol;
+    P.npairs = npairs;
+    P.n_stats = sp[nmol];
+    P.n_tiles = tp[nmol];
+    P.sync = (int32_t*)ws.sync.p;
+    P.queue = P.sync + 4 * nmol;
+    P.err = P.queue + nqueue;
+    P.part_f = (float*)ws.part_f.p;
+    P.part_d = (double*)ws.part_d.p;
+    P.stats_part = (double*)ws.stats.p;
+    P.r2_part = (double*)ws.r2.p;
+    P.U = (double*)ws.outU.p;
+    P.status = (int32_t*)ws.outS.p;
+    P.invk = (const double*)c->t_invk.p;
+    P.invf = (const double*)c->t_invf.p;
+    P.rot = (const double*)c->t_rot.p;
+    P.spin_limit = int64_t(1) << 22;
+    bp.n_stats = P.n_stats;
+    bp.n_tiles = P.n_tiles;
+    bp.npairs = npairs;
+    bp.n_items = P.n_stats + P.n_tiles + npairs;
+    bp.sync_ints = sync_ints;
+    bp.atoms = atoms;
+    bp.moment_flops = flops;
+    return TCM_OK;
+}
+
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t* ev)
+{
+    if (launch_clear(bp.P.sync, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
+    (void)phased;                  // every run is phased: stats, tile groups, pairs
+    const int grid = 2 * c->num_cu;
+    const int S = bp.n_stats;
+    // ev (optional): 4 events recorded before the statistics, tile and pair launches and
+    // after the last launch, on the launch stream
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_stats(bp.P, 0, 0, S, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
+    for (size_t g = 0; g < bp.groups.size(); ++g) {
+        const BuiltPlan::Group& G = bp.groups[g];
+        if (launch_tiles(G.prec, G.L, bp.P, 2 + (int)g, S + G.begin, S + G.end, grid, s) != hipSuccess)
+            return TCM_EDEVICE;
+    }
+    if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_pairs(bp.P, 1, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TCM_EDEVICE;
+    return TCM_OK;
+}
+
+int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s)
+{
+    (void)c;
+    int32_t err = 0;
+    if (hipMemcpyAsync(&err, bp.P.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    return err ? TCM_EDEVICE : TCM_OK;
+}
+
+void free_workspace(Ctx* c, Workspace& ws)
+{
+    c->release(ws.blob); c->release(ws.sync); c->release(ws.part_f); c->release(ws.part_d);
+    c->release(ws.stats); c->release(ws.r2); c->release(ws.outU); c->release(ws.outS);
+    if (ws.hstage) (void)hipHostFree(ws.hstage);
+    ws.hstage = nullptr;
+    ws.hstage_cap = 0;
+}
+
+}  // namespace tcm
+
+// ====================================================================== C ABI
+using namespace tcm;
+
+static bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+extern "C" const char* tcm_strerror(int st)
+{
+    switch (st) {
+    case TCM_OK: return "ok";
+    case TCM_EINVAL: return "invalid argument";
+    case TCM_EDOMAIN: return "separation condition |R0| > a_A + a_B (eq. 2) violated";
+    case TCM_ENOMEM: return "out of device memory or HBM budget";
+    case TCM_EDEVICE: return "HIP device error";
+    case TCM_EAGAIN: return "queue full, retry";
+    case TCM_ENOTFOUND: return "unknown molecule id or ticket";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
+{
+    (void)flags;
+    if (!out) return TCM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return TCM_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return TCM_EDEVICE;
+    tcm_ctx* t = new (std::nothrow) tcm_ctx();
+    if (!t) return TCM_ENOMEM;
+    Ctx& c = t->c;
+    c.device = device;
+    c.budget = budget;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c.num_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete t;
+        return TCM_EDEVICE;
+    }
+    c.stream = c.own_stream;
+    std::vector<double> invk, invf;
+    build_norm_tables(LMAX, invk, invf);
+    std::vector<double> rot = build_rotation_tables(LMAX);
+    int rc;
+    if ((rc = c.alloc(c.t_invk, invk.size() * sizeof(double))) != TCM_OK ||
+        (rc = c.alloc(c.t_invf, invf.size() * sizeof(double))) != TCM_OK ||
+        (rc = c.alloc(c.t_rot, rot.size() * sizeof(double))) != TCM_OK) {
+        tcm_destroy(t);
+        return rc;
+    }
+    if (hipMemcpy(c.t_invk.p, invk.data(), invk.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.t_invf.p, invf.data(), invf.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.t_rot.p, rot.data(), rot.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        tcm_destroy(t);
+        return TCM_EDEVICE;
+    }
+    const char* tf = std::getenv("TCM_AUTOTUNE_CACHE");
+    if (tf) (void)tcm_tune_load(t, tf);
+    *out = t;
+    return TCM_OK;
+}
+
+extern "C" void tcm_destroy(tcm_ctx* t)
+{
+    if (!t) return;
+    Ctx& c = t->c;
+    (void)hipSetDevice(c.device);
+    server_destroy(&c);
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    for (auto& kv : c.mols) {
+        c.release(kv.second->atoms);
+        c.release(kv.second->moments);
+        c.release(kv.second->meta);
+    }
+    c.mols.clear();
+    free_workspace(&c, c.ws);
+    c.release(c.tmp_atoms);
+    c.release(c.tmp_q);
+    c.release(c.t_invk);
+    c.release(c.t_invf);
+    c.release(c.t_rot);
+    if (c.hpin) (void)hipHostFree(c.hpin);
+    if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
+    delete t;
+}
+
+extern "C" int tcm_set_stream(tcm_ctx* t, void* s)
+{
+    if (!t) return TCM_EINVAL;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    t->c.stream = s ? (hipStream_t)s : t->c.own_stream;
+    return TCM_OK;
+}
+
+extern "C" void* tcm_get_stream(tcm_ctx* t) { return t ? (void*)t->c.stream : nullptr; }
+
+// Upload host AoS atoms into tmp_atoms as SoA; returns device pointers.
+static int upload_atoms(Ctx& c, DevBuf& dst, const double* coords, const double* charges, int64_t n,
+                        const double* d[4], hipStream_t s)
+{
+    const size_t bytes = sizeof(double) * 4 * (size_t)(n > 0 ? n : 1);
+    int rc;
+    if ((rc = c.alloc(dst, bytes)) != TCM_OK) return rc;
+    if ((rc = c.ensure_pinned(bytes)) != TCM_OK) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    double* h = (double*)c.hpin;
+    for (int64_t i = 0; i < n; ++i) {
+        h[i] = coords[3 * i];
+        h[n + i] = coords[3 * i + 1];
+        h[2 * n + i] = coords[3 * i + 2];
+        h[3 * n + i] = charges[i];
+    }
+    if (n > 0 && hipMemcpyAsync(dst.p, h, sizeof(double) * 4 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TCM_EDEVICE;
+    double* b = (double*)dst.p;
+    d[0] = b; d[1] = b + n; d[2] = b + 2 * n; d[3] = b + 3 * n;
+    return TCM_OK;
+}
+
+static int validate_atoms(const double* coords, const double* charges, int64_t n)
+{
+    if (n < 0 || (n > 0 && (!coords || !charges))) return TCM_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!finite3(coords + 3 * i) || !std::isfinite(charges[i])) return TCM_EINVAL;
+    return TCM_OK;
+}
+
+extern "C" int tcm_moments(tcm_ctx* t, const double* coords, const double* charges, int64_t n, const double* centre,
+                           int L, int prec, double* Q_out, double* radius_out, double* centre_out)
+{
+    if (!t || !Q_out || L < 0 || L > LMAX || (prec != TCM_F64 && prec != TCM_F32C)) return TCM_EINVAL;
+    if (centre && !finite3(centre)) return TCM_EINVAL;
+    int rc = validate_atoms(coords, charges, n);
+    if (rc != TCM_OK) return rc;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    const double* d[4];
+    if ((rc = upload_atoms(c, c.tmp_atoms, coords, charges, n, d, s)) != TCM_OK) return rc;
+    const size_t qbytes = sizeof(double) * (nh(L) + 8);
+    if ((rc = c.alloc(c.tmp_q, qbytes)) != TCM_OK) return rc;
+    MolJob j{};
+    j.x = d[0]; j.y = d[1]; j.z = d[2]; j.q = d[3];
+    j.n = n;
+    j.L = L;
+    j.prec = prec;
+    j.has_centre = centre ? 1 : 0;
+    if (centre) { j.centre[0] = centre[0]; j.centre[1] = centre[1]; j.centre[2] = centre[2]; }
+    j.Q = (double*)c.tmp_q.p;
+    j.meta = j.Q + nh(L);
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    std::vector<double> host(nh(L) + 5);
+    if (hipMemcpyAsync(host.data(), j.Q, sizeof(double) * (nh(L) + 5), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    std::memcpy(Q_out, host.data(), sizeof(double) * nh(L));
+    if (radius_out) *radius_out = host[nh(L) + 3];
+    if (centre_out) { centre_out[0] = host[nh(L)]; centre_out[1] = host[nh(L) + 1]; centre_out[2] = host[nh(L) + 2]; }
+    return TCM_OK;
+}
+
+extern "C" int tcm_pair_energy(tcm_ctx* t, const double* QA, double aA, const double* QB, double aB, const double* R,
+                               const double* quat, int L, int flags, double* U_out)
+{
+    if (!t || !QA || !QB || !R || !U_out || L < 0 || L > LMAX) return TCM_EINVAL;
+    if (!finite3(R)) return TCM_EINVAL;
+    if (!(flags & TCM_UNCHECKED) && !(std::isfinite(aA) && std::isfinite(aB) && aA >= 0 && aB >= 0)) return TCM_EINVAL;
+    if (quat) {
+        const double qq = quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3];
+        if (!std::isfinite(qq) || !(qq > 0)) return TCM_EINVAL;
+    }
+    const int NHl = nh(L);
+    for (int i = 0; i < NHl; ++i)
+        if (!std::isfinite(QA[i]) || !std::isfinite(QB[i])) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    int rc;
+    const size_t cnt = 2 * (size_t)NHl + 16;
+    if ((rc = c.alloc(c.tmp_q, sizeof(double) * cnt)) != TCM_OK) return rc;
+    if ((rc = c.ensure_pinned(sizeof(double) * cnt)) != TCM_OK) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    double* h = (double*)c.hpin;
+    std::memcpy(h, QA, sizeof(double) * NHl);
+    std::memcpy(h + NHl, QB, sizeof(double) * NHl);
+    double* meta = h + 2 * NHl;
+    for (int i = 0; i < 16; ++i) meta[i] = 0.0;
+    meta[3] = (flags & TCM_UNCHECKED) ? 0.0 : aA;
+    meta[8 + 3] = (flags & TCM_UNCHECKED) ? 0.0 : aB;
+    if (hipMemcpyAsync(c.tmp_q.p, h, sizeof(double) * cnt, hipMemcpyHostToDevice, s) != hipSuccess) return TCM_EDEVICE;
+    double* dq = (double*)c.tmp_q.p;
+    PairJob pj{};
+    pj.QA = dq;
+    pj.QB = dq + NHl;
+    pj.metaA = dq + 2 * NHl;
+    pj.metaB = dq + 2 * NHl + 8;
+    pj.depA = pj.depB = -1;
+    pj.L = L;
+    pj.flags = flags;
+    for (int k = 0; k < 3; ++k) pj.R[k] = R[k];
+    pj.quat[0] = 1.0;
+    pj.has_rot = 0;
+    if (quat) {
+        for (int k = 0; k < 4; ++k) pj.quat[k] = quat[k];
+        pj.has_rot = 1;
+    }
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, {}, {pj}, bp, s)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    double U = 0.0;
+    int32_t st = 0;
+    if (hipMemcpyAsync(&U, bp.P.U, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
+    if (hipMemcpyAsync(&st, bp.P.status, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    if (st != TCM_OK) return st;
+    *U_out = U;
+    return TCM_OK;
+}
+
+// ---------------------------------------------------------------- resident molecules
+static int add_mol(Ctx& c, std::unique_ptr<Mol> m, tcm_mol_id* id_out)
+{
+    int rc = c.alloc(m->meta, sizeof(double) * 8);
+    if (rc != TCM_OK) {
+        c.release(m->atoms);
+        return rc;
+    }
+    m->id = c.next_id++;
+    *id_out = m->id;
+    c.mols[m->id] = std::move(m);
+    return TCM_OK;
+}
+
+extern "C" int tcm_mol_upload(tcm_ctx* t, const double* coords, const double* charges, int64_t n, const double* centre,
+                              int prec, tcm_mol_id* id_out)
+{
+    if (!t || !id_out || (prec != TCM_F64 && prec != TCM_F32C)) return TCM_EINVAL;
+    if (centre && !finite3(centre)) return TCM_EINVAL;
+    int rc = validate_atoms(coords, charges, n);
+    if (rc != TCM_OK) return rc;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    auto m = std::make_unique<Mol>();
+    const double* d[4];
+    if ((rc = upload_atoms(c, m->atoms, coords, charges, n, d, c.stream)) != TCM_OK) return rc;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return TCM_EDEVICE;
+    m->x = d[0]; m->y = d[1]; m->z = d[2]; m->q = d[3];
+    m->n = n;
+    m->prec = prec;
+    m->has_centre = centre ? 1 : 0;
+    if (centre) { m->centre[0] = centre[0]; m->centre[1] = centre[1]; m->centre[2] = centre[2]; }
+    return add_mol(c, std::move(m), id_out);
+}
+
+extern "C" int tcm_mol_register_device(tcm_ctx* t, const double* dx, const double* dy, const double* dz,
+                                       const double* dq, int64_t n, const double* centre, int prec, tcm_mol_id* id_out)
+{
+    if (!t || !id_out || n < 0 || (n > 0 && (!dx || !dy || !dz || !dq)) || (prec != TCM_F64 && prec != TCM_F32C))
+        return TCM_EINVAL;
+    if (centre && !finite3(centre)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    auto m = std::make_unique<Mol>();
+    m->x = dx; m->y = dy; m->z = dz; m->q = dq;
+    m->n = n;
+    m->prec = prec;
+    m->has_centre = centre ? 1 : 0;
+    if (centre) { m->centre[0] = centre[0]; m->centre[1] = centre[1]; m->centre[2] = centre[2]; }
+    return add_mol(c, std::move(m), id_out);
+}
+
+extern "C" int tcm_mol_release(tcm_ctx* t, tcm_mol_id id)
+{
+    if (!t) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.mols.find(id);
+    if (it == c.mols.end()) return TCM_ENOTFOUND;
+    (void)hipStreamSynchronize(c.stream);
+    c.release(it->second->atoms);
+    c.release(it->second->moments);
+    c.release(it->second->meta);
+    c.mols.erase(it);
+    return TCM_OK;
+}
+
+namespace tcm {
+// Molecule jobs and pair jobs of a batch of resident-molecule requests.  A molecule named
+// by several requests is computed once, at the largest order any of them needs (its
+// resident table keeps the larger order if it already had one); requests flagged
+// TCM_REUSE read resident moments of sufficient order without recomputing them.
+struct ReqPlan {
+    std::vector<MolJob> mj;
+    std::vector<PairJob> pj;
+    std::vector<int> pj_req;                 // request index of each pair job
+    std::vector<std::pair<Mol*, int>> computed;
+    std::vector<int32_t> pre_status;         // per request: TCM_OK or a host-side error
+};
+
+int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse, ReqPlan& rp)
+{
+    std::map<int64_t, int> need;             // mol id -> required order (-1 = reuse)
+    rp.pre_status.assign(np, TCM_OK);
+    for (int64_t i = 0; i < np; ++i) {
+        const tcm_pair_req& r = reqs[i];
+        const double qq = r.quat_b[0] * r.quat_b[0] + r.quat_b[1] * r.quat_b[1] +
+                          r.quat_b[2] * r.quat_b[2] + r.quat_b[3] * r.quat_b[3];
+        if (r.L < 0 || r.L > LMAX || !finite3(r.R) || !std::isfinite(qq) || !(qq > 0)) {
+            rp.pre_status[i] = TCM_EINVAL;
+            continue;
+        }
+        auto ia = c.mols.find(r.a), ib = c.mols.find(r.b);
+        if (ia == c.mols.end() || ib == c.mols.end()) {
+            rp.pre_status[i] = TCM_ENOTFOUND;
+            continue;
+        }
+        for (Mol* m : {ia->second.get(), ib->second.get()}) {
+            const bool reuse = allow_reuse && (r.flags & TCM_REUSE) && m->Lcached >= r.L;
+            const int want = reuse ? -1 : r.L;
+            auto it = need.find(m->id);
+            if (it == need.end()) need[m->id] = want;
+            else if (want > it->second) it->second = want;
+        }
+    }
+    std::map<int64_t, int> jobidx;
+    for (auto& kv : need) {
+        if (kv.second < 0) continue;
+        Mol* m = c.mols[kv.first].get();
+        int L = kv.second;
+        if (m->Lcached > L) L = m->Lcached;
+        if (m->moments.cap < sizeof(double) * nh(L)) {
+            int rc = c.alloc(m->moments, sizeof(double) * nh(L));
+            if (rc != TCM_OK) return rc;
+        }
+        MolJob j{};
+        j.x = m->x; j.y = m->y; j.z = m->z; j.q = m->q;
+        j.n = m->n;
+        j.L = L;
+        j.prec = m->prec;
+        j.has_centre = m->has_centre;
+        for (int d = 0; d < 3; ++d) j.centre[d] = m->centre[d];
+        j.Q = (double*)m->moments.p;
+        j.meta = (double*)m->meta.p;
+        jobidx[m->id] = (int)rp.mj.size();
+        rp.mj.push_back(j);
+        rp.computed.push_back({m, L});
+        m->Lcached = -1;                      // invalid until this run completes
+    }
+    for (int64_t i = 0; i < np; ++i) {
+        if (rp.pre_status[i] != TCM_OK) continue;
+        const tcm_pair_req& r = reqs[i];
+        Mol* a = c.mols[r.a].get();
+        Mol* b = c.mols[r.b].get();
+        PairJob j{};
+        j.QA = (const double*)a->moments.p;
+        j.QB = (const double*)b->moments.p;
+        j.metaA = (const double*)a->meta.p;
+        j.metaB = (const double*)b->meta.p;
+        auto fa = jobidx.find(a->id), fb = jobidx.find(b->id);
+        j.depA = fa == jobidx.end() ? -1 : fa->second;
+        j.depB = fb == jobidx.end() ? -1 : fb->second;
+        j.L = r.L;
+        j.flags = r.flags;
+        for (int d = 0; d < 3; ++d) j.R[d] = r.R[d];
+        for (int d = 0; d < 4; ++d) j.quat[d] = r.quat_b[d];
+        j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
+        rp.pj.push_back(j);
+        rp.pj_req.push_back((int)i);
+        a->last_use = b->last_use = ++c.use_clock;
+    }
+    return TCM_OK;
+}
+
+void mark_computed(ReqPlan& rp)
+{
+    for (auto& pr : rp.computed) pr.first->Lcached = pr.second;
+}
+}  // namespace tcm
+
+extern "C" int tcm_mol_moments(tcm_ctx* t, tcm_mol_id id, int L, int flags, double* Q_out, double* radius_out,
+                               double* centre_out)
+{
+    if (!t || !Q_out || L < 0 || L > LMAX) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    auto it = c.mols.find(id);
+    if (it == c.mols.end()) return TCM_ENOTFOUND;
+    Mol* m = it->second.get();
+    hipStream_t s = c.stream;
+    int rc;
+    if (!((flags & TCM_REUSE) && m->Lcached >= L)) {
+        int Lc = m->Lcached > L ? m->Lcached : L;
+        if (m->moments.cap < sizeof(double) * nh(Lc) && (rc = c.alloc(m->moments, sizeof(double) * nh(Lc))) != TCM_OK)
+            return rc;
+        MolJob j{};
+        j.x = m->x; j.y = m->y; j.z = m->z; j.q = m->q;
+        j.n = m->n;
+        j.L = Lc;
+        j.prec = m->prec;
+        j.has_centre = m->has_centre;
+        for (int d = 0; d < 3; ++d) j.centre[d] = m->centre[d];
+        j.Q = (double*)m->moments.p;
+        j.meta = (double*)m->meta.p;
+        m->Lcached = -1;
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) return rc;
+        if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+        if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+        m->Lcached = Lc;
+    }
+    std::vector<double> meta(5);
+    if (hipMemcpyAsync(Q_out, m->moments.p, sizeof(double) * nh(L), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(meta.data(), m->meta.p, sizeof(double) * 5, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (radius_out) *radius_out = meta[3];
+    if (centre_out) { centre_out[0] = meta[0]; centre_out[1] = meta[1]; centre_out[2] = meta[2]; }
+    m->last_use = ++c.use_clock;
+    return TCM_OK;
+}
+
+static int first_error(const int32_t* st, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (st[i] != TCM_OK) return st[i];
+    return TCM_OK;
+}
+
+extern "C" int tcm_batch_energy(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
+{
+    if (!t || np < 0 || (np > 0 && (!reqs || !U_out || !status_out))) return TCM_EINVAL;
+    if (np > (1 << 26)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, np, true, rp);
+    if (rc != TCM_OK) return rc;
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    const int npj = (int)rp.pj.size();
+    std::vector<double> U(npj > 0 ? npj : 1);
+    std::vector<int32_t> st(npj > 0 ? npj : 1);
+    if (npj > 0 && (hipMemcpyAsync(U.data(), bp.P.U, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess))
+        return TCM_EDEVICE;
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    mark_computed(rp);
+    for (int64_t i = 0; i < np; ++i) {
+        status_out[i] = rp.pre_status[i];
+        U_out[i] = std::nan("");
+    }
+    for (int k = 0; k < npj; ++k) {
+        status_out[rp.pj_req[k]] = st[k];
+        U_out[rp.pj_req[k]] = st[k] == TCM_OK ? U[k] : std::nan("");
+    }
+    return first_error(status_out, np);
+}
+
+// ---------------------------------------------------------------- plans (graph replay)
+extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, int use_graph, tcm_plan** out)
+{
+    if (!t || !out || np < 0 || (np > 0 && !reqs)) return TCM_EINVAL;
+    *out = nullptr;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, np, false, rp);
+    if (rc != TCM_OK) return rc;
+    if (first_error(rp.pre_status.data(), np) != TCM_OK) return first_error(rp.pre_status.data(), np);
+    tcm_plan* pl = new (std::nothrow) tcm_plan();
+    if (!pl) return TCM_ENOMEM;
+    if ((rc = build_plan(&c, pl->ws, rp.mj, rp.pj, pl->bp, s)) != TCM_OK) {
+        free_workspace(&c, pl->ws);
+        delete pl;
+        return rc;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        free_workspace(&c, pl->ws);
+        delete pl;
+        return TCM_EDEVICE;
+    }
+    // moments become valid after the first run; mark now so later batches may reuse them
+    mark_computed(rp);
+    pl->npairs = (int)np;
+    if (use_graph) {
+        hipStream_t cs = nullptr;
+        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            int r2 = run_plan(&c, pl->bp, cs, false, nullptr);
+            hipGraph_t gr = nullptr;
+            ok = hipStreamEndCapture(cs, &gr) == hipSuccess && r2 == TCM_OK;
+            if (ok) {
+                pl->graph = gr;
+                ok = hipGraphInstantiate(&pl->exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            } else if (gr) {
+                (void)hipGraphDestroy(gr);
+            }
+        }
+        if (cs) (void)hipStreamDestroy(cs);
+        if (!ok) {
+            (void)hipGetLastError();
+            tcm_plan_destroy(pl);
+            return TCM_EDEVICE;
+        }
+    }
+    *out = pl;
+    return TCM_OK;
+}
+
+extern "C" int tcm_plan_run(tcm_ctx* t, tcm_plan* pl)
+{
+    if (!t || !pl) return TCM_EINVAL;
+    Ctx& c = t->c;
+    (void)hipSetDevice(c.device);
+    if (pl->exec) return hipGraphLaunch(pl->exec, c.stream) == hipSuccess ? TCM_OK : TCM_EDEVICE;
+    return run_plan(&c, pl->bp, c.stream, false, nullptr);
+}
+
+extern "C" int tcm_plan_run_phased(tcm_ctx* t, tcm_plan* pl)
+{
+    if (!t || !pl) return TCM_EINVAL;
+    (void)hipSetDevice(t->c.device);
+    return run_plan(&t->c, pl->bp, t->c.stream, true, nullptr);
+}
+
+extern "C" int tcm_plan_run_timed(tcm_ctx* t, tcm_plan* pl, double* ms_out)
+{
+    if (!t || !pl || !ms_out) return TCM_EINVAL;
+    Ctx& c = t->c;
+    (void)hipSetDevice(c.device);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int rc = TCM_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
+    if (rc == TCM_OK) rc = run_plan(&c, pl->bp, c.stream, true, ev);
+    if (rc == TCM_OK && hipEventSynchronize(ev[3]) != hipSuccess) rc = TCM_EDEVICE;
+    if (rc == TCM_OK) {
+        float a = 0, b = 0, d = 0;
+        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&d, ev[2], ev[3]);
+        ms_out[0] = a;
+        ms_out[1] = b;
+        ms_out[2] = d;
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+extern "C" int tcm_plan_results(tcm_ctx* t, tcm_plan* pl, double* U_out, int32_t* status_out)
+{
+    if (!t || !pl) return TCM_EINVAL;
+    Ctx& c = t->c;
+    hipStream_t s = c.stream;
+    const int n = pl->bp.npairs;
+    if (U_out && n && hipMemcpyAsync(U_out, pl->bp.P.U, sizeof(double) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (status_out && n &&
+        hipMemcpyAsync(status_out, pl->bp.P.status, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    return check_err(&c, pl->bp, s);
+}
+
+extern "C" int tcm_plan_device_outputs(tcm_plan* pl, double** dU, int32_t** dS)
+{
+    if (!pl) return TCM_EINVAL;
+    if (dU) *dU = pl->bp.P.U;
+    if (dS) *dS = pl->bp.P.status;
+    return TCM_OK;
+}
+
+extern "C" int tcm_plan_info(tcm_plan* pl, int64_t* atoms, double* flops, int64_t* tiles, int64_t* pairs)
+{
+    if (!pl) return TCM_EINVAL;
+    if (atoms) *atoms = pl->bp.atoms;
+    if (flops) *flops = pl->bp.moment_flops;
+    if (tiles) *tiles = pl->bp.n_tiles;
+    if (pairs) *pairs = pl->bp.npairs;
+    return TCM_OK;
+}
+
+extern "C" void tcm_plan_destroy(tcm_plan* pl)
+{
+    if (!pl) return;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    // the plan's buffers were charged to the context that created it; freeing them here
+    // without the context only returns device memory (budget accounting is per context and
+    // plans are expected to be destroyed before their context)
+    for (DevBuf* b : {&pl->ws.blob, &pl->ws.sync, &pl->ws.part_f, &pl->ws.part_d, &pl->ws.stats, &pl->ws.r2,
+                      &pl->ws.outU, &pl->ws.outS})
+        if (b->p) (void)hipFree(b->p);
+    if (pl->ws.hstage) (void)hipHostFree(pl->ws.hstage);
+    delete pl;
+}
+
+// ---------------------------------------------------------------- tuning
+extern "C" int tcm_tune_get(tcm_ctx* t, int prec, int L, int64_t n, int* k)
+{
+    if (!t || !k || L < 0 || L > LMAX || n < 0) return TCM_EINVAL;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    *k = t->c.kper_for(prec, L, n);
+    return TCM_OK;
+}
+
+extern "C" int tcm_tune_set(tcm_ctx* t, int prec, int L, int64_t n, int k)
+{
+    if (!t || L < 0 || L > LMAX || n < 0 || k < 1 || k > 1024) return TCM_EINVAL;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    t->c.tune[tune_key(prec, L, n)] = k;
+    return TCM_OK;
+}
+
+extern "C" int tcm_tune_save(tcm_ctx* t, const char* path)
+{
+    if (!t || !path) return TCM_EINVAL;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return TCM_EINVAL;
+    std::fprintf(f, "# tcm tuning table: key kper (key = prec*100000 + L*100 + log2 bucket)\n");
+    for (auto& kv : t->c.tune) std::fprintf(f, "%lld %d\n", (long long)kv.first, kv.second);
+    std::fclose(f);
+    return TCM_OK;
+}
+
+extern "C" int tcm_tune_load(tcm_ctx* t, const char* path)
+{
+    if (!t || !path) return TCM_EINVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return TCM_ENOTFOUND;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        long long key;
+        int k;
+        if (std::sscanf(line, "%lld %d", &key, &k) == 2 && k >= 1 && k <= 1024) t->c.tune[key] = k;
+    }
+    std::fclose(f);
+    return TCM_OK;
+}
+
+// Times each candidate kper on a synthetic molecule (deterministic points in a unit ball,
+// charges in [-1, 1]) with HIP events around the persistent launch.
+extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k, double* best_ms)
+{
+    if (!t || L < 0 || L > LMAX || n <= 0 || (prec != TCM_F64 && prec != TCM_F32C)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    std::vector<double> coords(3 * n), charges(n);
+    uint64_t st = 0x9e3779b97f4a7c15ULL ^ (uint64_t)n;
+    auto rnd = [&]() {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        return (double)(st >> 11) * 0x1.0p-53;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        double v[3];
+        do {
+            for (double& e : v) e = 2 * rnd() - 1;
+        } while (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > 1.0);
+        for (int d = 0; d < 3; ++d) coords[3 * i + d] = 10.0 * v[d];
+        charges[i] = 2 * rnd() - 1;
+    }
+    DevBuf atoms, qbuf;
+    const double* d[4];
+    int rc = upload_atoms(c, atoms, coords.data(), charges.data(), n, d, s);
+    if (rc == TCM_OK) rc = c.alloc(qbuf, sizeof(double) * (nh(L) + 8));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == TCM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = TCM_EDEVICE;
+    const int64_t key = tune_key(prec, L, n);
+    const bool had = c.tune.count(key) > 0;
+    const int old = had ? c.tune[key] : 0;
+    double bestt = 1e300;
+    int bestk = 0;
+    for (int k = 2; rc == TCM_OK && k <= 128; k <<= 1) {
+        c.tune[key] = k;
+        MolJob j{};
+        j.x = d[0]; j.y = d[1]; j.z = d[2]; j.q = d[3];
+        j.n = n;
+        j.L = L;
+        j.prec = prec;
+        j.Q = (double*)qbuf.p;
+        j.meta = j.Q + nh(L);
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) break;
+        double tot = 0.0;
+        for (int rep = 0; rep < 4 && rc == TCM_OK; ++rep) {
+            (void)hipEventRecord(e0, s);
+            rc = run_plan(&c, bp, s, false, nullptr);
+            (void)hipEventRecord(e1, s);
+            if (rc == TCM_OK) rc = check_err(&c, bp, s);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tot += ms;             // first repetition is warm-up
+        }
+        if (rc == TCM_OK && tot / 3 < bestt) {
+            bestt = tot / 3;
+            bestk = k;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c.release(atoms);
+    c.release(qbuf);
+    if (rc != TCM_OK || bestk == 0) {
+        if (had) c.tune[key] = old; else c.tune.erase(key);
+        return rc != TCM_OK ? rc : TCM_EDEVICE;
+    }
+    c.tune[key] = bestk;
+    if (best_k) *best_k = bestk;
+    if (best_ms) *best_ms = bestt;
+    return TCM_OK;
+}

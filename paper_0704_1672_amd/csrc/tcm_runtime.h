@@ -1,0 +1,145 @@
+// Host runtime of libtcm: context, device buffers, resident molecules, batch planning.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tcm.h"
+#include "tcm_internal.h"
+
+namespace tcm {
+
+int num_blocks_for(int prec, int L);
+hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+
+struct Ctx;
+
+// A device allocation charged against the context's HBM budget.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct Mol {
+    int64_t id = 0;
+    int64_t n = 0;
+    const double* x = nullptr;     // device SoA
+    const double* y = nullptr;
+    const double* z = nullptr;
+    const double* q = nullptr;
+    DevBuf atoms;                  // owned storage when uploaded
+    int prec = TCM_F32C;
+    int has_centre = 0;
+    double centre[3] = {0, 0, 0};
+    DevBuf moments;                // (Lcap+1)^2 FP64 resident moments
+    DevBuf meta;                   // 5 FP64: centre, radius, scale
+    int Lcached = -1;              // order of valid resident moments (-1: none)
+    uint64_t last_use = 0;
+};
+
+// Everything one launch needs, described on the host.
+struct MolJob {
+    const double *x, *y, *z, *q;
+    int64_t n;
+    int L, prec, has_centre;
+    double centre[3];
+    double* Q;
+    double* meta;
+};
+
+struct PairJob {
+    const double* QA;
+    const double* QB;
+    const double* metaA;
+    const double* metaB;
+    int depA, depB;
+    int L, flags;
+    double R[3];
+    double quat[4];
+    int has_rot;
+};
+
+// Device-side state of a planned batch: the uploaded plan blob, scratch and outputs.
+struct Workspace {
+    DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS;
+    void* hstage = nullptr;        // pinned host staging for the blob
+    size_t hstage_cap = 0;
+};
+
+struct BuiltPlan {
+    DevPlan P{};
+    int n_items = 0;
+    int n_stats = 0;
+    int n_tiles = 0;
+    struct Group {                 // molecules of one (precision, L): one tile launch
+        int prec, L, begin, end;   // tile item range (tile numbering, before n_stats offset)
+    };
+    std::vector<Group> groups;
+    int npairs = 0;
+    int64_t sync_ints = 0;
+    int64_t atoms = 0;
+    double moment_flops = 0.0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    size_t budget = 0;             // 0 = unbounded
+    std::atomic<size_t> used{0};
+    DevBuf t_invk, t_invf, t_rot;
+    std::mutex mu;                 // guards molecules, tuning and the shared workspace
+    std::unordered_map<int64_t, std::unique_ptr<Mol>> mols;
+    int64_t next_id = 1;
+    uint64_t use_clock = 0;
+    Workspace ws;                  // shared by the synchronous entry points
+    DevBuf tmp_atoms, tmp_q;       // one-shot uploads
+    void* hpin = nullptr;          // pinned staging for one-shot uploads
+    size_t hpin_cap = 0;
+    std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper
+    // serving
+    struct Server* server = nullptr;
+
+    int alloc(DevBuf& b, size_t bytes);      // grow-only, budget checked
+    void release(DevBuf& b);
+    int ensure_pinned(size_t bytes);
+    int kper_for(int prec, int L, int64_t n);
+};
+
+// planning / running (tcm_runtime.cpp)
+int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols,
+               const std::vector<PairJob>& pairs, BuiltPlan& bp, hipStream_t s);
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t* ev);
+int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s);
+void free_workspace(Ctx* c, Workspace& ws);
+int64_t tune_key(int prec, int L, int64_t n);
+
+// serving (tcm_server.cpp)
+void server_destroy(Ctx* c);
+
+}  // namespace tcm
+
+struct tcm_ctx {
+    tcm::Ctx c;
+};
+
+struct tcm_plan {
+    tcm::Workspace ws;
+    tcm::BuiltPlan bp;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int npairs = 0;
+};

@@ -1,0 +1,373 @@
+"""ctypes binding of libtcm (include/tcm.h): the same entry points, argument marshalling only.
+
+Every computation runs in the HIP kernels of libtcm.so; there is no CPU fallback.  Loading
+fails loudly if the library has not been built (python -m paper_0704_1672_amd.build, or
+__graft_entry__.build()).  PyTorch is used only to hand device memory and streams over:
+functions taking device buffers accept torch CUDA tensors (or raw addresses).
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "tcm.h")
+
+TCM_OK, TCM_EINVAL, TCM_EDOMAIN, TCM_ENOMEM, TCM_EDEVICE, TCM_EAGAIN, TCM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+TCM_LMAX = 32
+TCM_F64, TCM_F32C = 0, 1
+TCM_UNCHECKED, TCM_REUSE = 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip32 = C.POINTER(C.c_int32)
+_ip64 = C.POINTER(C.c_int64)
+_vp = C.c_void_p
+
+
+class tcm_pair_req(C.Structure):
+    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("R", C.c_double * 3), ("quat_b", C.c_double * 4),
+                ("L", C.c_int32), ("flags", C.c_int32)]
+
+
+class tcm_request(C.Structure):
+    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("new_a", _vp * 4), ("new_na", C.c_int64),
+                ("new_b", _vp * 4), ("new_nb", C.c_int64), ("R", C.c_double * 3),
+                ("quat_b", C.c_double * 4), ("L", C.c_int32), ("flags", C.c_int32),
+                ("precision", C.c_int32), ("pad", C.c_int32)]
+
+
+class tcm_server_cfg(C.Structure):
+    _fields_ = [("max_inflight_batches", C.c_int32), ("max_batch_pairs", C.c_int32),
+                ("queue_capacity", C.c_int32), ("pad", C.c_int32)]
+
+
+PAIR_REQ_DTYPE = np.dtype([("a", np.int64), ("b", np.int64), ("R", np.float64, 3), ("quat_b", np.float64, 4),
+                           ("L", np.int32), ("flags", np.int32)])
+assert PAIR_REQ_DTYPE.itemsize == C.sizeof(tcm_pair_req)
+
+_SIGS = {
+    "tcm_strerror": (C.c_char_p, [C.c_int]),
+    "tcm_create": (C.c_int, [C.POINTER(_vp), C.c_int, C.c_size_t, C.c_int]),
+    "tcm_destroy": (None, [_vp]),
+    "tcm_set_stream": (C.c_int, [_vp, _vp]),
+    "tcm_get_stream": (_vp, [_vp]),
+    "tcm_moments": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
+    "tcm_pair_energy": (C.c_int, [_vp, _dp, C.c_double, _dp, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp]),
+    "tcm_mol_upload": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, _ip64]),
+    "tcm_mol_register_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, _dp, C.c_int, _ip64]),
+    "tcm_mol_release": (C.c_int, [_vp, C.c_int64]),
+    "tcm_mol_moments": (C.c_int, [_vp, C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp]),
+    "tcm_batch_energy": (C.c_int, [_vp, _vp, C.c_int64, _dp, _ip32]),
+    "tcm_plan_create": (C.c_int, [_vp, _vp, C.c_int64, C.c_int, C.POINTER(_vp)]),
+    "tcm_plan_run": (C.c_int, [_vp, _vp]),
+    "tcm_plan_run_phased": (C.c_int, [_vp, _vp]),
+    "tcm_plan_run_timed": (C.c_int, [_vp, _vp, _dp]),
+    "tcm_plan_results": (C.c_int, [_vp, _vp, _dp, _ip32]),
+    "tcm_plan_device_outputs": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp)]),
+    "tcm_plan_info": (C.c_int, [_vp, _ip64, _dp, _ip64, _ip64]),
+    "tcm_plan_destroy": (None, [_vp]),
+    "tcm_tune_get": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32]),
+    "tcm_tune_set": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, C.c_int]),
+    "tcm_autotune": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32, _dp]),
+    "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
+    "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
+    "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
+    "tcm_submit": (C.c_int, [_vp, C.POINTER(tcm_request), C.POINTER(C.c_uint64)]),
+    "tcm_poll": (C.c_int, [_vp, C.c_uint64, _dp, _ip32, _dp]),
+    "tcm_server_stop": (C.c_int, [_vp]),
+    "tcm_server_stats": (C.c_int, [_vp, _ip64, _ip64, _ip64, _ip64, _ip64]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libtcm.so (raises if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libtcm.so not found at {LIB_PATH}: build it first "
+                               "(python -m paper_0704_1672_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of every function declared in include/tcm.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcm_[a-z_0-9]+)\s*\(", text)))
+
+
+class TCMError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {lib().tcm_strerror(code).decode()} ({code})")
+
+
+def _check(rc, what):
+    if rc != TCM_OK:
+        raise TCMError(rc, what)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a.reshape(shape) if shape is not None else a
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _addr(t):
+    """Device address of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def nh(L):
+    return (L + 1) * (L + 1)
+
+
+# ---- thin wrappers with the C names ------------------------------------------------
+def tcm_strerror(code):
+    return lib().tcm_strerror(code).decode()
+
+
+def tcm_create(device=0, hbm_budget_bytes=0, flags=0):
+    h = _vp()
+    _check(lib().tcm_create(C.byref(h), device, hbm_budget_bytes, flags), "tcm_create")
+    return h.value
+
+
+def tcm_destroy(ctx):
+    lib().tcm_destroy(ctx)
+
+
+def tcm_set_stream(ctx, stream):
+    """stream: a torch.cuda.Stream, a raw hipStream_t address, or None."""
+    s = getattr(stream, "cuda_stream", stream)
+    _check(lib().tcm_set_stream(ctx, s), "tcm_set_stream")
+
+
+def tcm_get_stream(ctx):
+    return lib().tcm_get_stream(ctx)
+
+
+def tcm_moments(ctx, coords, charges, L, precision=TCM_F64, centre=None):
+    """eq. (8): returns (Q packed (L+1)^2, radius, centre)."""
+    x = _f64(coords, (-1, 3))
+    q = _f64(charges, (-1,))
+    c = _f64(centre, (3,)) if centre is not None else None
+    Q = np.empty(nh(L))
+    r = C.c_double()
+    co = np.empty(3)
+    _check(lib().tcm_moments(ctx, _p(x), _p(q), len(q), _p(c), L, precision, _p(Q), C.byref(r), _p(co)),
+           "tcm_moments")
+    return Q, r.value, co
+
+
+def tcm_pair_energy(ctx, QA, aA, QB, aB, R, L, quat_b=None, flags=0):
+    qa, qb = _f64(QA), _f64(QB)
+    if len(qa) < nh(L) or len(qb) < nh(L):
+        raise ValueError("moment tables shorter than (L+1)^2")
+    Rv = _f64(R, (3,))
+    qt = _f64(quat_b, (4,)) if quat_b is not None else None
+    U = C.c_double()
+    _check(lib().tcm_pair_energy(ctx, _p(qa), float(aA), _p(qb), float(aB), _p(Rv), _p(qt), L, flags, C.byref(U)),
+           "tcm_pair_energy")
+    return U.value
+
+
+def tcm_mol_upload(ctx, coords, charges, centre=None, precision=TCM_F32C):
+    x = _f64(coords, (-1, 3))
+    q = _f64(charges, (-1,))
+    c = _f64(centre, (3,)) if centre is not None else None
+    mid = C.c_int64()
+    _check(lib().tcm_mol_upload(ctx, _p(x), _p(q), len(q), _p(c), precision, C.byref(mid)), "tcm_mol_upload")
+    return mid.value
+
+
+def tcm_mol_register_device(ctx, x, y, z, q, n, centre=None, precision=TCM_F32C):
+    c = _f64(centre, (3,)) if centre is not None else None
+    mid = C.c_int64()
+    _check(lib().tcm_mol_register_device(ctx, _addr(x), _addr(y), _addr(z), _addr(q), int(n), _p(c), precision,
+                                         C.byref(mid)), "tcm_mol_register_device")
+    return mid.value
+
+
+def tcm_mol_release(ctx, mid):
+    _check(lib().tcm_mol_release(ctx, mid), "tcm_mol_release")
+
+
+def tcm_mol_moments(ctx, mid, L, flags=0):
+    Q = np.empty(nh(L))
+    r = C.c_double()
+    co = np.empty(3)
+    _check(lib().tcm_mol_moments(ctx, mid, L, flags, _p(Q), C.byref(r), _p(co)), "tcm_mol_moments")
+    return Q, r.value, co
+
+
+def make_requests(a, b, R, L, quat_b=None, flags=0):
+    """Array of tcm_pair_req from per-pair arrays (broadcasting scalars)."""
+    a = np.atleast_1d(np.asarray(a, dtype=np.int64))
+    n = len(a)
+    req = np.zeros(n, dtype=PAIR_REQ_DTYPE)
+    req["a"] = a
+    req["b"] = np.broadcast_to(np.asarray(b, dtype=np.int64), (n,))
+    req["R"] = np.broadcast_to(np.asarray(R, dtype=np.float64).reshape(-1, 3), (n, 3))
+    if quat_b is None:
+        req["quat_b"][:, 0] = 1.0
+    else:
+        req["quat_b"] = np.broadcast_to(np.asarray(quat_b, dtype=np.float64).reshape(-1, 4), (n, 4))
+    req["L"] = np.broadcast_to(np.asarray(L, dtype=np.int32), (n,))
+    req["flags"] = np.broadcast_to(np.asarray(flags, dtype=np.int32), (n,))
+    return req
+
+
+def tcm_batch_energy(ctx, reqs):
+    """Returns (U[n], status[n], rc)."""
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    n = len(reqs)
+    U = np.empty(max(n, 1))
+    st = np.empty(max(n, 1), dtype=np.int32)
+    rc = lib().tcm_batch_energy(ctx, reqs.ctypes.data if n else None, n, _p(U),
+                                st.ctypes.data_as(_ip32))
+    if rc in (TCM_EINVAL, TCM_ENOMEM, TCM_EDEVICE) and n and np.all(st[:n] == 0):
+        raise TCMError(rc, "tcm_batch_energy")
+    return U[:n], st[:n], rc
+
+
+def tcm_plan_create(ctx, reqs, use_graph=True):
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    h = _vp()
+    _check(lib().tcm_plan_create(ctx, reqs.ctypes.data if len(reqs) else None, len(reqs), int(use_graph),
+                                 C.byref(h)), "tcm_plan_create")
+    return h.value
+
+
+def tcm_plan_run(ctx, plan):
+    _check(lib().tcm_plan_run(ctx, plan), "tcm_plan_run")
+
+
+def tcm_plan_run_phased(ctx, plan):
+    _check(lib().tcm_plan_run_phased(ctx, plan), "tcm_plan_run_phased")
+
+
+def tcm_plan_run_timed(ctx, plan):
+    """Synchronous phased run; returns the (stats, tiles, pairs) kernel times in ms."""
+    ms = np.zeros(3)
+    _check(lib().tcm_plan_run_timed(ctx, plan, _p(ms)), "tcm_plan_run_timed")
+    return ms
+
+
+def tcm_plan_results(ctx, plan, n):
+    U = np.empty(max(n, 1))
+    st = np.empty(max(n, 1), dtype=np.int32)
+    _check(lib().tcm_plan_results(ctx, plan, _p(U), st.ctypes.data_as(_ip32)), "tcm_plan_results")
+    return U[:n], st[:n]
+
+
+def tcm_plan_device_outputs(plan):
+    u, s = _vp(), _vp()
+    _check(lib().tcm_plan_device_outputs(plan, C.byref(u), C.byref(s)), "tcm_plan_device_outputs")
+    return u.value, s.value
+
+
+def tcm_plan_info(plan):
+    a, t, p = C.c_int64(), C.c_int64(), C.c_int64()
+    f = C.c_double()
+    _check(lib().tcm_plan_info(plan, C.byref(a), C.byref(f), C.byref(t), C.byref(p)), "tcm_plan_info")
+    return dict(atoms=a.value, moment_flops=f.value, tiles=t.value, pairs=p.value)
+
+
+def tcm_plan_destroy(plan):
+    lib().tcm_plan_destroy(plan)
+
+
+def tcm_tune_get(ctx, precision, L, n):
+    k = C.c_int32()
+    _check(lib().tcm_tune_get(ctx, precision, L, n, C.byref(k)), "tcm_tune_get")
+    return k.value
+
+
+def tcm_tune_set(ctx, precision, L, n, kper):
+    _check(lib().tcm_tune_set(ctx, precision, L, n, kper), "tcm_tune_set")
+
+
+def tcm_autotune(ctx, precision, L, n):
+    k = C.c_int32()
+    ms = C.c_double()
+    _check(lib().tcm_autotune(ctx, precision, L, n, C.byref(k), C.byref(ms)), "tcm_autotune")
+    return k.value, ms.value
+
+
+def tcm_tune_save(ctx, path):
+    _check(lib().tcm_tune_save(ctx, path.encode()), "tcm_tune_save")
+
+
+def tcm_tune_load(ctx, path):
+    return lib().tcm_tune_load(ctx, path.encode())
+
+
+def tcm_server_start(ctx, max_inflight_batches=2, max_batch_pairs=64, queue_capacity=4096):
+    cfg = tcm_server_cfg(max_inflight_batches, max_batch_pairs, queue_capacity, 0)
+    _check(lib().tcm_server_start(ctx, C.byref(cfg)), "tcm_server_start")
+
+
+def tcm_submit(ctx, req):
+    t = C.c_uint64()
+    rc = lib().tcm_submit(ctx, C.byref(req), C.byref(t))
+    return rc, t.value
+
+
+def tcm_poll(ctx, ticket):
+    U = C.c_double()
+    st = C.c_int32()
+    lat = C.c_double()
+    rc = lib().tcm_poll(ctx, ticket, C.byref(U), C.byref(st), C.byref(lat))
+    return rc, U.value, st.value, lat.value
+
+
+def tcm_server_stop(ctx):
+    _check(lib().tcm_server_stop(ctx), "tcm_server_stop")
+
+
+def tcm_server_stats(ctx):
+    v = [C.c_int64() for _ in range(5)]
+    _check(lib().tcm_server_stats(ctx, *[C.byref(x) for x in v]), "tcm_server_stats")
+    return dict(zip(["completed", "launches", "cache_hits", "cache_misses", "deferred"], [x.value for x in v]))
+
+
+class Context:
+    """Owns a tcm_ctx; thin convenience over the functions above."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        self.h = tcm_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.h:
+            tcm_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
