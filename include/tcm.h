@@ -149,12 +149,12 @@ int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, dou
 int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
                     tcm_plan **plan_out);
 int tcm_plan_run(tcm_ctx *ctx, tcm_plan *plan);
-/* Same work split into three launches (statistics, moment tiles, pairs) so that each
- * phase can be timed; results are identical bit for bit. */
+/* The same launches issued directly instead of through the graph; results are identical
+ * bit for bit. */
 int tcm_plan_run_phased(tcm_ctx *ctx, tcm_plan *plan);
-/* One synchronous phased run with HIP events recorded on the launch stream around the
- * statistics launch, the tile launches and the pair launch; ms_out[3] receives the three
- * elapsed times in milliseconds (measurement of the per-kernel durations). */
+/* One synchronous run with HIP events recorded on the launch stream between its steps;
+ * ms_out[4] receives the elapsed milliseconds of (statistics + centre/scale), (moment
+ * tiles), (moment finalisation), (pair rotation + contraction). */
 int tcm_plan_run_timed(tcm_ctx *ctx, tcm_plan *plan, double *ms_out);
 /* Wait for the last run and copy U/status to the host (either may be NULL). */
 int tcm_plan_results(tcm_ctx *ctx, tcm_plan *plan, double *U_out, int32_t *status_out);
@@ -181,44 +181,57 @@ int tcm_tune_load(tcm_ctx *ctx, const char *path);
 
 /* ---- serving ----------------------------------------------------------------------- */
 
-/* A served request: either resident molecules (ids) or new atoms given by device pointers
- * (FP64 SoA, borrowed until the request completes).  New molecules become resident and
- * are kept in an LRU cache bounded by the context's HBM budget. */
+/* A served pair-energy request.  Fragments are named by caller-chosen keys.  A fragment the
+ * server already holds (atoms and moments resident in its cache) is reused: its moments are
+ * computed once per order and kept for later poses and partners.  A fragment that is not
+ * resident must come with its atoms (FP64 structure of arrays x, y, z, q; device pointers,
+ * or host pointers with TCM_HOST_ATOMS), which the server copies into memory it owns, so the
+ * caller may reuse the arrays once the request completes.  New fragments become resident
+ * under an LRU policy bounded by the context's HBM budget. */
+#define TCM_HOST_ATOMS 4    /* request flag: atoms_a / atoms_b are host pointers */
+
 typedef struct {
-    tcm_mol_id a;                  /* resident id, or -1 to use new_a */
-    tcm_mol_id b;
-    const double *new_a[4];        /* d_x, d_y, d_z, d_q when a == -1 */
-    int64_t new_na;
-    const double *new_b[4];
-    int64_t new_nb;
-    double R[3];
-    double quat_b[4];
+    int64_t key_a;
+    int64_t key_b;
+    const double *atoms_a[4];      /* x, y, z, q of fragment a when not resident, else NULL */
+    int64_t n_a;
+    const double *atoms_b[4];
+    int64_t n_b;
+    double R[3];                   /* c_b - c_a (centres are the fragments' centroids)       */
+    double quat_b[4];              /* pose of b, unit quaternion (w, x, y, z)                */
     int32_t L;
-    int32_t flags;
-    int32_t precision;
+    int32_t flags;                 /* TCM_UNCHECKED, TCM_HOST_ATOMS                          */
+    int32_t precision;             /* moment pass of new fragments (TCM_F32C or TCM_F64)     */
     int32_t pad;
 } tcm_request;
 
 typedef struct {
-    int32_t max_inflight_batches;  /* launches in flight at once (>= 1)                    */
-    int32_t max_batch_pairs;       /* pairs admitted into one launch                        */
-    int32_t queue_capacity;        /* pending requests before tcm_submit returns TCM_EAGAIN */
+    int32_t max_inflight_batches;  /* launches in flight at once, each on its own stream      */
+    int32_t max_batch_pairs;       /* requests admitted into one launch                       */
+    int32_t queue_capacity;        /* pending requests before tcm_submit returns TCM_EAGAIN   */
     int32_t pad;
 } tcm_server_cfg;
 
+/* Start the serving thread (one per context).  Requests that arrive while launches are in
+ * flight are admitted into the next launch as soon as a launch slot and memory are free, so
+ * the work of several batches overlaps on the device.  A request whose fragment is still
+ * being computed by an in-flight launch waits for it and then reuses the result. */
 int tcm_server_start(tcm_ctx *ctx, const tcm_server_cfg *cfg);
-/* Enqueue a request; returns a ticket.  TCM_EAGAIN when the queue is full. */
+/* Enqueue a request; returns a ticket.  TCM_EAGAIN when the queue is full, TCM_EINVAL for a
+ * malformed request.  Thread-safe with respect to tcm_poll and other submitters. */
 int tcm_submit(tcm_ctx *ctx, const tcm_request *req, uint64_t *ticket_out);
-/* Non-blocking: TCM_EAGAIN while pending; on completion writes U, the item status and the
- * latency (seconds from submit to completion) and forgets the ticket. */
+/* Non-blocking: TCM_EAGAIN while pending; on completion writes U (NaN on failure), the item
+ * status and the latency (seconds from submit to completion observed by the server) and
+ * forgets the ticket.  TCM_ENOTFOUND for an unknown ticket. */
 int tcm_poll(tcm_ctx *ctx, uint64_t ticket, double *U_out, int32_t *status_out,
              double *latency_s_out);
-/* Stop accepting requests, finish the ones admitted, join the serving thread. */
+/* Stop accepting requests, finish the ones admitted or pending, join the serving thread and
+ * free the server's cache. */
 int tcm_server_stop(tcm_ctx *ctx);
-/* Counters since start: completed requests, launches, molecule cache hits/misses,
- * admissions deferred for memory. */
+/* Counters since start: completed requests, launches, fragment cache hits / misses,
+ * admissions deferred (memory, or a fragment still in flight), evictions. */
 int tcm_server_stats(tcm_ctx *ctx, int64_t *completed, int64_t *launches, int64_t *cache_hits,
-                     int64_t *cache_misses, int64_t *deferred);
+                     int64_t *cache_misses, int64_t *deferred, int64_t *evictions);
 
 #ifdef __cplusplus
 }

@@ -62,27 +62,6 @@ __device__ __forceinline__ int atomic_add_acqrel(int* p, int v)
     return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 waits (bounded) until *flag != 0; the result is shared with the workgroup.
-// Returns false if the wait expired or another workgroup already reported an error.
-__device__ inline bool wg_wait_flag(int* flag, const DevPlan& P, int* s_ok)
-{
-    if (threadIdx.x == 0) {
-        int ok = 0;
-        for (int64_t it = 0; it < P.spin_limit; ++it) {
-            if (atomic_load_acq(flag)) { ok = 1; break; }
-            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(2);
-        }
-        if (!ok) atomic_store_rel(P.err, 1);
-        *s_ok = ok;
-    }
-    __syncthreads();
-    int ok = *s_ok;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    __syncthreads();
-    return ok != 0;
-}
-
 // ------------------------------------------------------------------ recurrence constants
 __host__ __device__ constexpr double xi_lm(int l, int m)
 {
@@ -411,15 +390,14 @@ __device__ inline void finalize_moments(const DevPlan& P, int mol, char* smem)
         mw.Q[h] = v * P.invk[h] * spow[l_of(h)];
     }
     if (tid == 0) mw.meta[3] = sqrt(red[0]);
-    __threadfence();                 // every thread publishes its writes before the flag
     __syncthreads();
 }
 
 template <typename F, int L>
-__device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j, char* smem, int* s_misc)
+__device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j, char* smem)
 {
+    // the statistics launch that precedes this one has written the centre and scale
     const MolWork& mw = P.mols[mol];
-    if (!wg_wait_flag(&P.sync[4 * mol + 1], P, s_misc)) return;
     TileCtx tc;
     tc.mw = &mw;
     tc.tile = j / mw.nblk;
@@ -429,15 +407,6 @@ __device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j
     tc.cz = mw.meta[2];
     tc.inv_s = 1.0 / mw.meta[4];
     dispatch_block<F, L, 0>(tc, P, smem);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_misc[0] = atomic_add_acqrel(&P.sync[4 * mol + 2], 1);
-    __syncthreads();
-    if (s_misc[0] != mw.ntiles * mw.nblk - 1) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    finalize_moments(P, mol, smem);
-    if (threadIdx.x == 0) atomic_store_rel(&P.sync[4 * mol + 3], 1);
-    __syncthreads();
 }
 
 __device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int item)
@@ -457,21 +426,16 @@ __global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int slot, int begin, 
 {
     __shared__ __align__(16) char smem[TILE_SMEM_BYTES];
     __shared__ int s_item;
-    __shared__ int s_misc[4];
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) {
-            int it = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = end;
-            s_item = it;
-        }
+        if (tid == 0) s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
         if (item >= end) break;
         const int j = item - P.n_stats;
         const int mol = find_owner(P.tile_prefix, P.nmol, j);
-        tile_item_entry<F, L>(P, mol, j - P.tile_prefix[mol], smem, s_misc);
+        tile_item_entry<F, L>(P, mol, j - P.tile_prefix[mol], smem);
         __syncthreads();
     }
 }

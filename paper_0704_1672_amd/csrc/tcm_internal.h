@@ -1,14 +1,13 @@
 // Internal definitions shared by the HIP kernels and the host runtime of libtcm.
 //
-// Work decomposition of one batch (one launch of the persistent kernel):
-//   item kinds, in queue order
-//     STATS  (molecule, chunk)          centroid sums + bounding box of a chunk of atoms
-//     TILE   (molecule, tile, m-block)  eq. (8) moments of 256*kper atoms for one m-block
-//     PAIR   (pair)                     pose rotation, geometric factors, eq. (9) contraction
-//   the last STATS item of a molecule finalises its centre and scale; the last TILE item
-//   finalises its moments (fixed-order merge of the tile partials); PAIR items wait on both
-//   molecules.  Dependencies always point to earlier queue positions, which running
-//   workgroups have already claimed, so every wait ends.
+// Work decomposition of one batch: a sequence of launches, ordered by launch boundaries
+//   a0 STATS      (molecule, chunk)         centroid sums + bounding box of a chunk of atoms
+//      STATS_FIN  (molecule)                centre and scale of each molecule
+//   a1 TILE       (molecule, tile, m-block) eq. (8) moments of 256*kper atoms for one m-block;
+//                                            one persistent launch per (precision, L) group
+//   a2 MOM_FIN    (molecule)                fixed-order merge of the tile partials, unscaling
+//   a3-a5 PAIR    (pair)                    rotation, geometric factors, eq. (9) contraction
+// The launches of a batch are captured once into a HIP graph and replayed.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -70,10 +69,9 @@ struct DevPlan {
     int32_t npairs;
     int32_t n_stats;
     int32_t n_tiles;
-    // synchronisation state, cleared before each run by a fill kernel
-    int32_t* sync;                 // [4*nmol] stats_cnt, stats_done, tile_cnt, mom_done
-    int32_t* queue;                // one claim counter per launch of the run
-    int32_t* err;                  // [1] set when a bounded wait expires
+    // claim counters of the run's launches, cleared before each run by a fill kernel
+    int32_t* queue;                // one counter per launch
+    int32_t* err;                  // [1] device-side error flag (reserved)
     // scratch
     float* part_f;                 // FP32 path tile partials (hi block, then lo block)
     double* part_d;                // FP64 path tile partials

@@ -4,19 +4,35 @@
 namespace tcm {
 
 // ------------------------------------------------------------------ STATS items
-__device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk, char* smem, int* s_misc)
+// Partial sums of x, y, z and the bounding box of one chunk of atoms (HBM bound: 24 B/atom).
+// Loads are issued STATS_UNROLL at a time so that each thread keeps several in flight.
+constexpr int STATS_UNROLL = 8;
+
+__device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk, char* smem)
 {
     const MolWork& mw = P.mols[mol];
     const int tid = threadIdx.x;
     double v[9] = {0, 0, 0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    const int64_t base = (int64_t)chunk * STATS_CHUNK;
-    for (int i = 0; i < STATS_PER_THREAD; ++i) {
-        const int64_t a = base + tid + (int64_t)i * WG;
-        if (a >= mw.n) break;
-        const double x = mw.x[a], y = mw.y[a], z = mw.z[a];
-        v[0] += x; v[1] += y; v[2] += z;
-        v[3] = fmin(v[3], x); v[4] = fmin(v[4], y); v[5] = fmin(v[5], z);
-        v[6] = fmax(v[6], x); v[7] = fmax(v[7], y); v[8] = fmax(v[8], z);
+    const int64_t base = (int64_t)chunk * STATS_CHUNK + tid;
+    const int64_t n = mw.n;
+    for (int i0 = 0; i0 < STATS_PER_THREAD; i0 += STATS_UNROLL) {
+        double x[STATS_UNROLL], y[STATS_UNROLL], z[STATS_UNROLL];
+        bool ok[STATS_UNROLL];
+#pragma unroll
+        for (int j = 0; j < STATS_UNROLL; ++j) {
+            const int64_t a = base + (int64_t)(i0 + j) * WG;
+            ok[j] = a < n;
+            x[j] = ok[j] ? gload(mw.x, a) : 0.0;
+            y[j] = ok[j] ? gload(mw.y, a) : 0.0;
+            z[j] = ok[j] ? gload(mw.z, a) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < STATS_UNROLL; ++j) {
+            if (!ok[j]) continue;
+            v[0] += x[j]; v[1] += y[j]; v[2] += z[j];
+            v[3] = fmin(v[3], x[j]); v[4] = fmin(v[4], y[j]); v[5] = fmin(v[5], z[j]);
+            v[6] = fmax(v[6], x[j]); v[7] = fmax(v[7], y[j]); v[8] = fmax(v[8], z[j]);
+        }
     }
     double* red = reinterpret_cast<double*>(smem);   // [9][WG]
     for (int k = 0; k < 9; ++k) red[k * WG + tid] = v[k];
@@ -31,41 +47,37 @@ __device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk,
     }
     double* rec = P.stats_part + (mw.stats_off + chunk) * 10;
     if (tid < 9) rec[tid] = red[tid * WG];
-    __threadfence();
     __syncthreads();
-    if (tid == 0) s_misc[0] = atomic_add_acqrel(&P.sync[4 * mol + 0], 1);
-    __syncthreads();
-    if (s_misc[0] != mw.nstats - 1) return;
-    // last chunk of this molecule: merge chunk records in order
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    if (tid == 0) {
-        double sx = 0, sy = 0, sz = 0;
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int c = 0; c < mw.nstats; ++c) {
-            const double* r = P.stats_part + (mw.stats_off + c) * 10;
-            sx += r[0]; sy += r[1]; sz += r[2];
-            for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], r[3 + d]); hi[d] = fmax(hi[d], r[6 + d]); }
-        }
-        double c[3];
-        if (mw.has_centre || mw.n == 0) {
-            c[0] = mw.centre[0]; c[1] = mw.centre[1]; c[2] = mw.centre[2];
-        } else {
-            c[0] = sx / (double)mw.n; c[1] = sy / (double)mw.n; c[2] = sz / (double)mw.n;
-        }
-        double s2 = 0.0;
-        if (mw.n > 0)
-            for (int d = 0; d < 3; ++d) {
-                const double e = fmax(fabs(hi[d] - c[d]), fabs(c[d] - lo[d]));
-                s2 += e * e;
-            }
-        double s = sqrt(s2);
-        if (!(s > 0.0)) s = 1.0;
-        mw.meta[0] = c[0]; mw.meta[1] = c[1]; mw.meta[2] = c[2];
-        mw.meta[4] = s;
-        __threadfence();
-        atomic_store_rel(&P.sync[4 * mol + 1], 1);
+}
+
+// Centre (the given one, else the centroid) and scale s >= max |r_i - c| of one molecule from
+// its chunk records, merged in chunk order.
+__device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol)
+{
+    const MolWork& mw = P.mols[mol];
+    double sx = 0, sy = 0, sz = 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < mw.nstats; ++c) {
+        const double* r = P.stats_part + (mw.stats_off + c) * 10;
+        sx += r[0]; sy += r[1]; sz += r[2];
+        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], r[3 + d]); hi[d] = fmax(hi[d], r[6 + d]); }
     }
-    __syncthreads();
+    double c[3];
+    if (mw.has_centre || mw.n == 0) {
+        c[0] = mw.centre[0]; c[1] = mw.centre[1]; c[2] = mw.centre[2];
+    } else {
+        c[0] = sx / (double)mw.n; c[1] = sy / (double)mw.n; c[2] = sz / (double)mw.n;
+    }
+    double s2 = 0.0;
+    if (mw.n > 0)
+        for (int d = 0; d < 3; ++d) {
+            const double e = fmax(fabs(hi[d] - c[d]), fabs(c[d] - lo[d]));
+            s2 += e * e;
+        }
+    double s = sqrt(s2);
+    if (!(s > 0.0)) s = 1.0;
+    mw.meta[0] = c[0]; mw.meta[1] = c[1]; mw.meta[2] = c[2];
+    mw.meta[4] = s;
 }
 
 // ------------------------------------------------------------------ PAIR items
@@ -103,12 +115,11 @@ __device__ void rot_matvec(const double* tab, const double* in, double* out, int
     }
 }
 
-__device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem, int* s_misc)
+__device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
 {
+    // the moment launches that precede this one have finalised every table it reads
     const PairWork& pw = P.pairs[p];
     const int tid = threadIdx.x;
-    if (pw.depA >= 0 && !wg_wait_flag(&P.sync[4 * pw.depA + 3], P, s_misc)) return;
-    if (pw.depB >= 0 && !wg_wait_flag(&P.sync[4 * pw.depB + 3], P, s_misc)) return;
     const int L = pw.L, NHl = nh(L);
     const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
     const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
@@ -258,20 +269,40 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem, i
 }
 
 // ------------------------------------------------------------------ kernels
+// Every kernel claims items from its own queue counter until [begin, end) is exhausted;
+// the steps of a run are ordered by launch boundaries only (no device-side waits).
+__device__ __forceinline__ int claim(const DevPlan& P, int slot, int begin, int* s_item)
+{
+    if (threadIdx.x == 0) *s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int item = *s_item;
+    __syncthreads();
+    return item;
+}
+
 __global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int slot, int begin, int end)
 {
     __shared__ __align__(16) char smem[9 * WG * sizeof(double)];
     __shared__ int s_item;
-    __shared__ int s_misc[4];
-    const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
+        const int item = claim(P, slot, begin, &s_item);
         if (item >= end) break;
         const int mol = find_owner(P.stats_prefix, P.nmol, item);
-        stats_item(P, mol, item - P.stats_prefix[mol], smem, s_misc);
+        stats_item(P, mol, item - P.stats_prefix[mol], smem);
+    }
+}
+
+__global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P)
+{
+    for (int mol = blockIdx.x * blockDim.x + threadIdx.x; mol < P.nmol; mol += gridDim.x * blockDim.x)
+        stats_finalize(P, mol);
+}
+
+__global__ __launch_bounds__(WG) void tcm_moments_finalize(DevPlan P)
+{
+    __shared__ __align__(16) double smem[(LMAX + 2) + WG];
+    for (int mol = blockIdx.x; mol < P.nmol; mol += gridDim.x) {
+        finalize_moments(P, mol, reinterpret_cast<char*>(smem));
         __syncthreads();
     }
 }
@@ -280,25 +311,16 @@ __global__ __launch_bounds__(WG) void tcm_pairs(DevPlan P, int slot, int begin, 
 {
     __shared__ __align__(16) char smem[SMEM_BYTES];
     __shared__ int s_item;
-    __shared__ int s_misc[4];
-    const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) {
-            int it = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = end;
-            s_item = it;
-        }
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
+        const int item = claim(P, slot, begin, &s_item);
         if (item >= end) break;
-        pair_item(P, item, smem, s_misc);
+        pair_item(P, item, smem);
         __syncthreads();
     }
 }
 
-// Clears the synchronisation state of a run (a kernel, not a memset, so that it can sit
-// in a captured graph).
+// Clears the queue counters of a run (a kernel, not a memset, so that it can sit in a
+// captured graph).
 __global__ void tcm_clear(int32_t* p, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -336,6 +358,18 @@ hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid
     if (end <= begin) return hipSuccess;
     if (grid > end - begin) grid = end - begin;
     hipLaunchKernelGGL(tcm_stats, dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevPlan& P, bool moments, int grid, hipStream_t s)
+{
+    if (P.nmol <= 0) return hipSuccess;
+    if (moments) {
+        if (grid > P.nmol) grid = P.nmol;
+        hipLaunchKernelGGL(tcm_moments_finalize, dim3(grid), dim3(WG), 0, s, P);
+    } else {
+        hipLaunchKernelGGL(tcm_stats_finalize, dim3((P.nmol + WG - 1) / WG), dim3(WG), 0, s, P);
+    }
     return hipGetLastError();
 }
 

@@ -347,7 +347,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         bp.groups.back().end = tp[i + 1];
     }
     const int nqueue = 2 + (int)bp.groups.size();
-    const int64_t sync_ints = 4 * (int64_t)nmol + nqueue + 1;
+    const int64_t sync_ints = nqueue + 1;
     if ((rc = c->alloc(ws.sync, sizeof(int32_t) * sync_ints)) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.part_f, sizeof(float) * (off_f > 0 ? off_f : 1))) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.part_d, sizeof(double) * (off_d > 0 ? off_d : 1))) != TCM_OK) return rc;
@@ -366,8 +366,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.npairs = npairs;
     P.n_stats = sp[nmol];
     P.n_tiles = tp[nmol];
-    P.sync = (int32_t*)ws.sync.p;
-    P.queue = P.sync + 4 * nmol;
+    P.queue = (int32_t*)ws.sync.p;
     P.err = P.queue + nqueue;
     P.part_f = (float*)ws.part_f.p;
     P.part_d = (double*)ws.part_d.p;
@@ -391,14 +390,15 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
 
 int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t* ev)
 {
-    if (launch_clear(bp.P.sync, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_clear(bp.P.queue, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
     (void)phased;                  // every run is phased: stats, tile groups, pairs
     const int grid = 2 * c->num_cu;
     const int S = bp.n_stats;
-    // ev (optional): 4 events recorded before the statistics, tile and pair launches and
-    // after the last launch, on the launch stream
+    // ev (optional): 5 events on the launch stream -- before the statistics launches, before
+    // the tile launches, before the moment finalisation, before the pair launch, at the end
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_stats(bp.P, 0, 0, S, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_stats(bp.P, 0, 0, S, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_finalize(bp.P, false, grid, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
     for (size_t g = 0; g < bp.groups.size(); ++g) {
         const BuiltPlan::Group& G = bp.groups[g];
@@ -406,8 +406,10 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t
             return TCM_EDEVICE;
     }
     if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_pairs(bp.P, 1, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_finalize(bp.P, true, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_pairs(bp.P, 1, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (ev && hipEventRecord(ev[4], s) != hipSuccess) return TCM_EDEVICE;
     return TCM_OK;
 }
 
@@ -977,20 +979,16 @@ extern "C" int tcm_plan_run_timed(tcm_ctx* t, tcm_plan* pl, double* ms_out)
     if (!t || !pl || !ms_out) return TCM_EINVAL;
     Ctx& c = t->c;
     (void)hipSetDevice(c.device);
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int rc = TCM_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
     if (rc == TCM_OK) rc = run_plan(&c, pl->bp, c.stream, true, ev);
-    if (rc == TCM_OK && hipEventSynchronize(ev[3]) != hipSuccess) rc = TCM_EDEVICE;
-    if (rc == TCM_OK) {
-        float a = 0, b = 0, d = 0;
-        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-        (void)hipEventElapsedTime(&d, ev[2], ev[3]);
-        ms_out[0] = a;
-        ms_out[1] = b;
-        ms_out[2] = d;
+    if (rc == TCM_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = TCM_EDEVICE;
+    for (int k = 0; rc == TCM_OK && k < 4; ++k) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        ms_out[k] = ms;
     }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);

@@ -22,6 +22,7 @@ int num_blocks_for(int prec, int L);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_finalize(const DevPlan& P, bool moments, int grid, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
 
 struct Ctx;

@@ -1,33 +1,500 @@
-// Serving loop of libtcm (continuous batching).  Placeholder until the serving thread lands:
-// the entry points validate their arguments and report that no server is running.
+// Serving loop of libtcm: continuous batching of pair-energy requests.
+//
+// One host thread per context runs the loop
+//   1. retire finished launches (HIP event query): publish U / status / latency per ticket,
+//      mark the moments they computed as resident, release fragment references;
+//   2. while a launch slot is free and requests are pending: admit requests in arrival order
+//      into a batch -- a fragment that is resident is a cache hit; a new fragment is copied
+//      into server-owned device memory after HBM admission (LRU eviction of idle fragments
+//      when the context's budget would be exceeded; requests that still do not fit wait);
+//      a request whose fragment is being computed by an in-flight launch waits for it;
+//   3. launch the batch on the slot's own stream (statistics, per-order tile kernels, pair
+//      kernel -- the same kernels as tcm_batch_energy) followed by asynchronous copies of the
+//      results into the slot's pinned buffers and an event.
+// With several slots the launches of consecutive batches run concurrently on the device.
+// Each fragment's moments are computed with a tiling that depends only on (precision, L,
+// n), so a result does not depend on which other requests shared its launch.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <list>
+
 #include "tcm_runtime.h"
 
 namespace tcm {
-void server_destroy(Ctx* c) { (void)c; }
+
+using clock_t_ = std::chrono::steady_clock;
+
+struct SMol {
+    int64_t key = 0;
+    int64_t n = 0;
+    int prec = TCM_F32C;
+    DevBuf atoms;                  // FP64 SoA, owned
+    DevBuf moments;
+    DevBuf meta;
+    int Lcached = -1;              // valid resident order
+    int busy = 0;                  // being computed by an in-flight launch
+    int refs = 0;                  // referenced by in-flight launches
+    std::list<int64_t>::iterator lru;
+};
+
+struct SReq {
+    uint64_t ticket;
+    tcm_request r;
+    clock_t_::time_point t_submit;
+};
+
+struct SResult {
+    double U;
+    int32_t status;
+    double latency;
+};
+
+struct Slot {
+    bool busy = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    Workspace ws;
+    BuiltPlan bp;
+    void* hpin = nullptr;          // U[cap] doubles, status[cap] ints, err int
+    int cap = 0;
+    int npairs = 0;                // pair jobs launched
+    std::vector<SReq> reqs;        // requests of the batch (in order)
+    std::vector<int> job_of;       // pair job index of each request, -1 = failed before launch
+    std::vector<int32_t> pre_status;
+    std::vector<std::pair<SMol*, int>> computed;
+    std::vector<SMol*> refd;
+};
+
+struct Server {
+    Ctx* c = nullptr;
+    tcm_server_cfg cfg{};
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    std::deque<SReq> pending;
+    std::unordered_map<uint64_t, SResult> done;
+    std::unordered_map<uint64_t, int> live;    // submitted, not yet polled
+    std::unordered_map<int64_t, std::unique_ptr<SMol>> cache;
+    std::list<int64_t> lru;        // front = most recently used
+    std::vector<Slot> slots;
+    uint64_t next_ticket = 1;
+    int64_t completed = 0, launches = 0, hits = 0, misses = 0, deferred = 0, evictions = 0;
+    int inflight = 0;
+};
+
+static double seconds_since(clock_t_::time_point t)
+{
+    return std::chrono::duration<double>(clock_t_::now() - t).count();
+}
+
+static void free_mol(Ctx* c, SMol* m)
+{
+    c->release(m->atoms);
+    c->release(m->moments);
+    c->release(m->meta);
+}
+
+// Bytes a new fragment needs: atoms, a moment table of order L, metadata.
+static size_t mol_bytes(int64_t n, int L)
+{
+    return sizeof(double) * (4 * (size_t)(n > 0 ? n : 1) + nh(L) + 8);
+}
+
+// Evict idle fragments (least recently used first) until `need` more bytes fit the budget.
+static bool make_room(Server* S, size_t need)
+{
+    Ctx* c = S->c;
+    if (!c->budget) return true;
+    auto it = S->lru.end();
+    while (c->used.load() + need > c->budget && it != S->lru.begin()) {
+        --it;
+        auto f = S->cache.find(*it);
+        SMol* m = f->second.get();
+        if (m->refs == 0 && !m->busy) {
+            free_mol(c, m);
+            it = S->lru.erase(it);
+            S->cache.erase(f);
+            ++S->evictions;
+        }
+    }
+    return c->used.load() + need <= c->budget;
+}
+
+static void touch(Server* S, SMol* m)
+{
+    S->lru.erase(m->lru);
+    S->lru.push_front(m->key);
+    m->lru = S->lru.begin();
+}
+
+static int copy_atoms(SMol* m, const double* const src[4], bool host, hipStream_t s)
+{
+    if (m->n == 0) return TCM_OK;
+    double* d = (double*)m->atoms.p;
+    for (int k = 0; k < 4; ++k)
+        if (hipMemcpyAsync(d + k * m->n, src[k], sizeof(double) * m->n,
+                           host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return TCM_EDEVICE;
+    return TCM_OK;
+}
+
+// Finish a completed launch (called with S->mu held).
+static void retire(Server* S, Slot& sl)
+{
+    const double* U = (const double*)sl.hpin;
+    const int32_t* st = (const int32_t*)(U + sl.cap);
+    const int32_t err = st[sl.cap];
+    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+        SResult r;
+        const int j = sl.job_of[i];
+        if (j < 0) {
+            r.status = sl.pre_status[i];
+            r.U = std::nan("");
+        } else {
+            r.status = err ? TCM_EDEVICE : st[j];
+            r.U = (r.status == TCM_OK) ? U[j] : std::nan("");
+        }
+        r.latency = seconds_since(sl.reqs[i].t_submit);
+        S->done[sl.reqs[i].ticket] = r;
+    }
+    for (auto& pr : sl.computed) {
+        pr.first->busy = 0;
+        if (!err) pr.first->Lcached = pr.second;
+    }
+    for (SMol* m : sl.refd) --m->refs;
+    S->completed += (int64_t)sl.reqs.size();
+    sl.reqs.clear();
+    sl.busy = false;
+    --S->inflight;
+}
+
+// Admit pending requests into slot `sl` and launch them (called with S->mu held).
+static void admit_and_launch(Server* S, Slot& sl)
+{
+    Ctx* c = S->c;
+    std::map<SMol*, int> need;             // fragment -> order to compute in this launch
+    std::vector<SMol*> refd;
+    std::vector<SReq> batch;
+    std::vector<int32_t> pre;
+    std::deque<SReq> keep;
+    auto get = [&](int64_t key, const double* const atoms[4], int64_t n, int L, int prec, bool host,
+                   int* status) -> SMol* {
+        auto f = S->cache.find(key);
+        if (f != S->cache.end()) {
+            SMol* m = f->second.get();
+            if (m->busy) { *status = TCM_EAGAIN; return nullptr; }       // wait for the launch
+            auto nd = need.find(m);
+            const bool recompute = m->Lcached < L && (nd == need.end() || nd->second < L);
+            // an in-flight launch still reads this table: do not rewrite or reallocate it
+            if (recompute && m->refs > 0) { *status = TCM_EAGAIN; return nullptr; }
+            if (!recompute) ++S->hits; else ++S->misses;
+            if (m->moments.cap < sizeof(double) * nh(L)) {
+                if (!make_room(S, sizeof(double) * nh(L))) { *status = TCM_EAGAIN; return nullptr; }
+                if (c->alloc(m->moments, sizeof(double) * nh(L)) != TCM_OK) { *status = TCM_EAGAIN; return nullptr; }
+                m->Lcached = -1;
+            }
+            return m;
+        }
+        if (!atoms[0] || !atoms[1] || !atoms[2] || !atoms[3] || n < 0) {
+            if (n == 0 && atoms[0] == nullptr) { /* empty fragment without arrays is fine */ }
+            else { *status = TCM_ENOTFOUND; return nullptr; }
+        }
+        const size_t bytes = mol_bytes(n, L);
+        if (!make_room(S, bytes)) { *status = TCM_EAGAIN; return nullptr; }
+        auto m = std::make_unique<SMol>();
+        m->key = key;
+        m->n = n;
+        m->prec = prec;
+        if (c->alloc(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1)) != TCM_OK ||
+            c->alloc(m->moments, sizeof(double) * nh(L)) != TCM_OK || c->alloc(m->meta, sizeof(double) * 8) != TCM_OK) {
+            free_mol(c, m.get());
+            *status = TCM_EAGAIN;
+            return nullptr;
+        }
+        if (copy_atoms(m.get(), atoms, host, sl.stream) != TCM_OK) {
+            free_mol(c, m.get());
+            *status = TCM_EDEVICE;
+            return nullptr;
+        }
+        ++S->misses;
+        S->lru.push_front(key);
+        m->lru = S->lru.begin();
+        SMol* raw = m.get();
+        S->cache[key] = std::move(m);
+        return raw;
+    };
+    const int maxp = S->cfg.max_batch_pairs > 0 ? S->cfg.max_batch_pairs : 64;
+    while (!S->pending.empty() && (int)batch.size() < maxp) {
+        SReq q = S->pending.front();
+        S->pending.pop_front();
+        const tcm_request& r = q.r;
+        const bool host = (r.flags & TCM_HOST_ATOMS) != 0;
+        int sa = TCM_OK, sb = TCM_OK;
+        SMol* a = get(r.key_a, r.atoms_a, r.n_a, r.L, r.precision, host, &sa);
+        SMol* b = a ? get(r.key_b, r.atoms_b, r.n_b, r.L, r.precision, host, &sb) : nullptr;
+        if (!a || !b) {
+            const int st = !a ? sa : sb;
+            if (st == TCM_EAGAIN) {
+                ++S->deferred;
+                keep.push_back(q);
+                continue;
+            }
+            batch.push_back(q);
+            pre.push_back(st);
+            continue;
+        }
+        for (SMol* m : {a, b}) {
+            if (m->Lcached < r.L) {
+                auto it = need.find(m);
+                if (it == need.end()) need[m] = r.L;
+                else if (r.L > it->second) it->second = r.L;
+            }
+            touch(S, m);
+        }
+        batch.push_back(q);
+        pre.push_back(TCM_OK);
+    }
+    if (batch.empty() && S->inflight == 0 && !keep.empty()) {
+        // nothing in flight can free memory or finish a fragment: the oldest deferred
+        // request can never be admitted
+        batch.push_back(keep.front());
+        pre.push_back(TCM_ENOMEM);
+        keep.pop_front();
+    }
+    for (auto it = keep.rbegin(); it != keep.rend(); ++it) S->pending.push_front(*it);
+    if (batch.empty()) return;
+    // jobs
+    std::vector<MolJob> mj;
+    std::map<SMol*, int> jobidx;
+    sl.computed.clear();
+    for (auto& kv : need) {
+        SMol* m = kv.first;
+        const int L = std::max(kv.second, m->Lcached);
+        if (m->moments.cap < sizeof(double) * nh(L)) continue;   // cannot happen: allocated at admission
+        MolJob j{};
+        const double* d = (const double*)m->atoms.p;
+        j.x = d; j.y = d + m->n; j.z = d + 2 * m->n; j.q = d + 3 * m->n;
+        j.n = m->n;
+        j.L = L;
+        j.prec = m->prec;
+        j.Q = (double*)m->moments.p;
+        j.meta = (double*)m->meta.p;
+        jobidx[m] = (int)mj.size();
+        mj.push_back(j);
+        m->busy = 1;
+        m->Lcached = -1;
+        sl.computed.push_back({m, L});
+    }
+    std::vector<PairJob> pj;
+    sl.job_of.assign(batch.size(), -1);
+    sl.refd.clear();
+    for (size_t i = 0; i < batch.size(); ++i) {
+        if (pre[i] != TCM_OK) continue;
+        const tcm_request& r = batch[i].r;
+        SMol* a = S->cache[r.key_a].get();
+        SMol* b = S->cache[r.key_b].get();
+        PairJob j{};
+        j.QA = (const double*)a->moments.p;
+        j.QB = (const double*)b->moments.p;
+        j.metaA = (const double*)a->meta.p;
+        j.metaB = (const double*)b->meta.p;
+        auto fa = jobidx.find(a), fb = jobidx.find(b);
+        j.depA = fa == jobidx.end() ? -1 : fa->second;
+        j.depB = fb == jobidx.end() ? -1 : fb->second;
+        j.L = r.L;
+        j.flags = r.flags & TCM_UNCHECKED;
+        for (int d = 0; d < 3; ++d) j.R[d] = r.R[d];
+        for (int d = 0; d < 4; ++d) j.quat[d] = r.quat_b[d];
+        j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
+        sl.job_of[i] = (int)pj.size();
+        pj.push_back(j);
+        ++a->refs;
+        ++b->refs;
+        sl.refd.push_back(a);
+        sl.refd.push_back(b);
+    }
+    sl.reqs = batch;
+    sl.pre_status = pre;
+    sl.npairs = (int)pj.size();
+    // pinned result buffer
+    const int cap = (int)batch.size();
+    if (cap > sl.cap) {
+        if (sl.hpin) (void)hipHostFree(sl.hpin);
+        sl.hpin = nullptr;
+        sl.cap = 0;
+        if (hipHostMalloc(&sl.hpin, (sizeof(double) + sizeof(int32_t)) * cap + 64, hipHostMallocDefault) == hipSuccess)
+            sl.cap = cap;
+    }
+    int rc = sl.cap >= cap ? TCM_OK : TCM_ENOMEM;
+    if (rc == TCM_OK) rc = build_plan(c, sl.ws, mj, pj, sl.bp, sl.stream);
+    if (rc == TCM_OK) rc = run_plan(c, sl.bp, sl.stream, false, nullptr);
+    double* hU = (double*)sl.hpin;
+    int32_t* hS = (int32_t*)(hU + sl.cap);
+    if (rc == TCM_OK && sl.npairs > 0) {
+        if (hipMemcpyAsync(hU, sl.bp.P.U, sizeof(double) * sl.npairs, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
+            hipMemcpyAsync(hS, sl.bp.P.status, sizeof(int32_t) * sl.npairs, hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
+            rc = TCM_EDEVICE;
+    }
+    if (rc == TCM_OK && hipMemcpyAsync(hS + sl.cap, sl.bp.P.err, sizeof(int32_t), hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
+        rc = TCM_EDEVICE;
+    if (rc == TCM_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) rc = TCM_EDEVICE;
+    sl.busy = true;
+    ++S->inflight;
+    ++S->launches;
+    if (rc != TCM_OK) {
+        // the launch failed on the host side: fail its requests, keep the server running
+        (void)hipStreamSynchronize(sl.stream);
+        for (size_t i = 0; i < batch.size(); ++i)
+            if (sl.job_of[i] >= 0) { sl.job_of[i] = -1; sl.pre_status[i] = rc; }
+        for (auto& pr : sl.computed) pr.first->Lcached = -1;
+        retire(S, sl);
+    }
+}
+
+static void server_loop(Server* S)
+{
+    (void)hipSetDevice(S->c->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        bool progress = false;
+        for (Slot& sl : S->slots) {
+            if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
+                retire(S, sl);
+                progress = true;
+            }
+        }
+        if (S->stop && S->pending.empty() && S->inflight == 0) break;
+        for (Slot& sl : S->slots) {
+            if (!sl.busy && !S->pending.empty()) {
+                const size_t before = S->pending.size();
+                admit_and_launch(S, sl);
+                if (sl.busy || S->pending.size() != before) progress = true;
+            }
+        }
+        if (!progress) {
+            if (S->inflight > 0) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(10));
+                lk.lock();
+            } else {
+                S->cv.wait_for(lk, std::chrono::milliseconds(5));
+            }
+        }
+    }
+}
+
+void server_destroy(Ctx* c)
+{
+    Server* S = c->server;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    for (Slot& sl : S->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        free_workspace(c, sl.ws);
+        if (sl.hpin) (void)hipHostFree(sl.hpin);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto& kv : S->cache) free_mol(c, kv.second.get());
+    delete S;
+    c->server = nullptr;
+}
+
 }  // namespace tcm
+
+using namespace tcm;
 
 extern "C" int tcm_server_start(tcm_ctx* t, const tcm_server_cfg* cfg)
 {
-    (void)t; (void)cfg;
-    return TCM_EINVAL;
+    if (!t || !cfg || cfg->max_inflight_batches < 1 || cfg->max_inflight_batches > 16 || cfg->max_batch_pairs < 1 ||
+        cfg->queue_capacity < 1)
+        return TCM_EINVAL;
+    Ctx& c = t->c;
+    if (c.server) return TCM_EINVAL;
+    (void)hipSetDevice(c.device);
+    Server* S = new (std::nothrow) Server();
+    if (!S) return TCM_ENOMEM;
+    S->c = &c;
+    S->cfg = *cfg;
+    S->slots.resize(cfg->max_inflight_batches);
+    for (Slot& sl : S->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+            c.server = S;
+            server_destroy(&c);
+            return TCM_EDEVICE;
+        }
+    }
+    c.server = S;
+    S->th = std::thread(server_loop, S);
+    return TCM_OK;
 }
-extern "C" int tcm_submit(tcm_ctx* t, const tcm_request* r, uint64_t* tk)
+
+extern "C" int tcm_submit(tcm_ctx* t, const tcm_request* r, uint64_t* ticket)
 {
-    (void)t; (void)r; (void)tk;
-    return TCM_EINVAL;
+    if (!t || !r || !ticket || !t->c.server) return TCM_EINVAL;
+    if (r->L < 0 || r->L > LMAX || (r->precision != TCM_F64 && r->precision != TCM_F32C)) return TCM_EINVAL;
+    if (!std::isfinite(r->R[0]) || !std::isfinite(r->R[1]) || !std::isfinite(r->R[2])) return TCM_EINVAL;
+    const double qq = r->quat_b[0] * r->quat_b[0] + r->quat_b[1] * r->quat_b[1] + r->quat_b[2] * r->quat_b[2] +
+                      r->quat_b[3] * r->quat_b[3];
+    if (!std::isfinite(qq) || !(qq > 0) || r->n_a < 0 || r->n_b < 0) return TCM_EINVAL;
+    Server* S = t->c.server;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        if (S->stop) return TCM_EINVAL;
+        if ((int)S->pending.size() >= S->cfg.queue_capacity) return TCM_EAGAIN;
+        SReq q;
+        q.ticket = S->next_ticket++;
+        q.r = *r;
+        q.t_submit = clock_t_::now();
+        S->pending.push_back(q);
+        S->live[q.ticket] = 1;
+        *ticket = q.ticket;
+    }
+    S->cv.notify_one();
+    return TCM_OK;
 }
-extern "C" int tcm_poll(tcm_ctx* t, uint64_t tk, double* U, int32_t* st, double* lat)
+
+extern "C" int tcm_poll(tcm_ctx* t, uint64_t ticket, double* U, int32_t* st, double* lat)
 {
-    (void)t; (void)tk; (void)U; (void)st; (void)lat;
-    return TCM_ENOTFOUND;
+    if (!t || !t->c.server) return TCM_EINVAL;
+    Server* S = t->c.server;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->done.find(ticket);
+    if (it == S->done.end()) return S->live.count(ticket) ? TCM_EAGAIN : TCM_ENOTFOUND;
+    if (U) *U = it->second.U;
+    if (st) *st = it->second.status;
+    if (lat) *lat = it->second.latency;
+    S->done.erase(it);
+    S->live.erase(ticket);
+    return TCM_OK;
 }
+
 extern "C" int tcm_server_stop(tcm_ctx* t)
 {
-    (void)t;
-    return TCM_EINVAL;
+    if (!t || !t->c.server) return TCM_EINVAL;
+    server_destroy(&t->c);
+    return TCM_OK;
 }
-extern "C" int tcm_server_stats(tcm_ctx* t, int64_t* a, int64_t* b, int64_t* c, int64_t* d, int64_t* e)
+
+extern "C" int tcm_server_stats(tcm_ctx* t, int64_t* completed, int64_t* launches, int64_t* hits, int64_t* misses,
+                                int64_t* deferred, int64_t* evictions)
 {
-    (void)t; (void)a; (void)b; (void)c; (void)d; (void)e;
-    return TCM_EINVAL;
+    if (!t || !t->c.server) return TCM_EINVAL;
+    Server* S = t->c.server;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (completed) *completed = S->completed;
+    if (launches) *launches = S->launches;
+    if (hits) *hits = S->hits;
+    if (misses) *misses = S->misses;
+    if (deferred) *deferred = S->deferred;
+    if (evictions) *evictions = S->evictions;
+    return TCM_OK;
 }

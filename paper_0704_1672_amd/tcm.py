@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tcm.h")
 TCM_OK, TCM_EINVAL, TCM_EDOMAIN, TCM_ENOMEM, TCM_EDEVICE, TCM_EAGAIN, TCM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 TCM_LMAX = 32
 TCM_F64, TCM_F32C = 0, 1
-TCM_UNCHECKED, TCM_REUSE = 1, 2
+TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS = 1, 2, 4
 
 _dp = C.POINTER(C.c_double)
 _ip32 = C.POINTER(C.c_int32)
@@ -32,8 +32,8 @@ class tcm_pair_req(C.Structure):
 
 
 class tcm_request(C.Structure):
-    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("new_a", _vp * 4), ("new_na", C.c_int64),
-                ("new_b", _vp * 4), ("new_nb", C.c_int64), ("R", C.c_double * 3),
+    _fields_ = [("key_a", C.c_int64), ("key_b", C.c_int64), ("atoms_a", _vp * 4), ("n_a", C.c_int64),
+                ("atoms_b", _vp * 4), ("n_b", C.c_int64), ("R", C.c_double * 3),
                 ("quat_b", C.c_double * 4), ("L", C.c_int32), ("flags", C.c_int32),
                 ("precision", C.c_int32), ("pad", C.c_int32)]
 
@@ -77,7 +77,7 @@ _SIGS = {
     "tcm_submit": (C.c_int, [_vp, C.POINTER(tcm_request), C.POINTER(C.c_uint64)]),
     "tcm_poll": (C.c_int, [_vp, C.c_uint64, _dp, _ip32, _dp]),
     "tcm_server_stop": (C.c_int, [_vp]),
-    "tcm_server_stats": (C.c_int, [_vp, _ip64, _ip64, _ip64, _ip64, _ip64]),
+    "tcm_server_stats": (C.c_int, [_vp, _ip64, _ip64, _ip64, _ip64, _ip64, _ip64]),
 }
 
 _lib = None
@@ -87,6 +87,12 @@ def lib():
     """The loaded libtcm.so (raises if it was never built)."""
     global _lib
     if _lib is None:
+        try:
+            # one HIP runtime per process: importing torch first loads its runtime, which the
+            # library then binds to (same soname) instead of loading a second copy
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libtcm.so not found at {LIB_PATH}: build it first "
                                "(python -m paper_0704_1672_amd.build)")
@@ -265,8 +271,8 @@ def tcm_plan_run_phased(ctx, plan):
 
 
 def tcm_plan_run_timed(ctx, plan):
-    """Synchronous phased run; returns the (stats, tiles, pairs) kernel times in ms."""
-    ms = np.zeros(3)
+    """Synchronous run; returns the (stats, tiles, finalise, pairs) kernel times in ms."""
+    ms = np.zeros(4)
     _check(lib().tcm_plan_run_timed(ctx, plan, _p(ms)), "tcm_plan_run_timed")
     return ms
 
@@ -344,9 +350,31 @@ def tcm_server_stop(ctx):
 
 
 def tcm_server_stats(ctx):
-    v = [C.c_int64() for _ in range(5)]
+    v = [C.c_int64() for _ in range(6)]
     _check(lib().tcm_server_stats(ctx, *[C.byref(x) for x in v]), "tcm_server_stats")
-    return dict(zip(["completed", "launches", "cache_hits", "cache_misses", "deferred"], [x.value for x in v]))
+    return dict(zip(["completed", "launches", "cache_hits", "cache_misses", "deferred", "evictions"],
+                    [x.value for x in v]))
+
+
+def make_request(key_a, key_b, R, L, quat_b=(1.0, 0.0, 0.0, 0.0), atoms_a=None, n_a=0, atoms_b=None, n_b=0,
+                 flags=0, precision=TCM_F32C):
+    """tcm_request; atoms_* are 4 device addresses (x, y, z, q) or None for a resident fragment."""
+    r = tcm_request()
+    r.key_a, r.key_b = int(key_a), int(key_b)
+    if atoms_a is not None:
+        for i in range(4):
+            r.atoms_a[i] = int(atoms_a[i])
+    r.n_a = int(n_a)
+    if atoms_b is not None:
+        for i in range(4):
+            r.atoms_b[i] = int(atoms_b[i])
+    r.n_b = int(n_b)
+    for i in range(3):
+        r.R[i] = float(R[i])
+    for i in range(4):
+        r.quat_b[i] = float(quat_b[i])
+    r.L, r.flags, r.precision = int(L), int(flags), int(precision)
+    return r
 
 
 class Context:

@@ -182,8 +182,10 @@ def test_domain_and_flags(ctx, orc, synth):
     for bad in (dict(R=[0.0, 0.0, 0.0]), dict(quat_b=[0, 0, 0, 0])):
         with pytest.raises(tcm.TCMError):
             tcm.tcm_pair_energy(ctx, pA, 1, pB, 1, bad.get("R", R), L, quat_b=bad.get("quat_b"))
-    with pytest.raises(tcm.TCMError):
-        tcm.tcm_pair_energy(ctx, pA, 1, pB, 1, R, 33)
+    big = np.zeros(34 * 34)
+    with pytest.raises(tcm.TCMError) as e:
+        tcm.tcm_pair_energy(ctx, big, 1, big, 1, R, 33)
+    assert e.value.code == tcm.TCM_EINVAL
 
 
 def test_ball_pair_end_to_end_fp64(ctx, orc, synth):
