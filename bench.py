@@ -31,6 +31,160 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, fractions=(0.5, 0.9)):
+    """Serving workload: a pool of chain fragments (log-uniform 1e3..1e6 atoms) resident in HBM,
+    a trace of nreq pair requests with L ~ U{8..24}; 70% name two new fragments (new keys, atoms
+    referenced in place), 30% reuse the fragments of an earlier request with a new pose and
+    distance.  Saturation throughput from a closed burst; then Poisson arrivals at fractions of
+    it, with p50/p99 of (completion - submission); the plain synchronous single-pair path
+    (tcm_batch_energy on one request at a time) is timed on the same trace and its FIFO
+    latencies computed for the same arrival times."""
+    w = synth.serving_trace(seed=5, pool=pool, nreq=nreq, nmin=1_000, nmax=1_000_000, Lmin=8, Lmax=24,
+                            reuse=0.3, qps=1.0, nthreads=min(16, os.cpu_count() or 1))
+    ntot = int(w["offsets"][-1])
+    dev = torch.device("cuda:0")
+    soa = torch.empty((4, ntot), dtype=torch.float64, device=dev)
+    soa[0:3] = torch.from_numpy(np.ascontiguousarray(w["xyz"].T)).to(dev)
+    soa[3] = torch.from_numpy(w["q"]).to(dev)
+    torch.cuda.synchronize()
+    base, row = soa.data_ptr(), ntot * 8
+
+    def ptrs(f):
+        off = int(w["offsets"][f]) * 8
+        return [base + k * row + off for k in range(4)]
+
+    # request records: (key_a, frag_a, key_b, frag_b, new)
+    recs = []
+    news = []
+    for i in range(nreq):
+        if w["reuse"][i] and news:
+            j = news[int(w["a"][i]) % len(news)]
+            recs.append((recs[j][0], recs[j][1], recs[j][2], recs[j][3], False))
+        else:
+            recs.append((2 * i, int(w["a"][i]), 2 * i + 1, int(w["b"][i]), True))
+            news.append(i)
+    ext = w["extent"]
+    dirs = w["R"] / np.linalg.norm(w["R"], axis=1)[:, None]
+
+    def make(i):
+        ka, fa, kb, fb, new = recs[i]
+        R = 1.5 * (ext[fa] + ext[fb]) * dirs[i]
+        return tcm.make_request(ka, kb, R, int(w["L"][i]), w["quats"][i],
+                                atoms_a=ptrs(fa) if new else None, n_a=int(w["counts"][fa]),
+                                atoms_b=ptrs(fb) if new else None, n_b=int(w["counts"][fb]),
+                                flags=tcm.TCM_BORROW_ATOMS)
+
+    reqs = [make(i) for i in range(nreq)]
+
+    def run(ctx, arrivals):
+        tcm.tcm_server_start(ctx.h, max_inflight_batches=3, max_batch_pairs=64, queue_capacity=nreq + 16)
+        tickets = [None] * nreq
+        lat = np.zeros(nreq)
+        U = np.zeros(nreq)
+        st = np.zeros(nreq, dtype=np.int32)
+        done = 0
+        t0 = time.perf_counter()
+        i = 0
+        pending = []
+        while done < nreq:
+            now = time.perf_counter() - t0
+            while i < nreq and (arrivals is None or arrivals[i] <= now):
+                rc, tk = tcm.tcm_submit(ctx.h, reqs[i])
+                assert rc == 0
+                tickets[i] = tk
+                pending.append(i)
+                i += 1
+            keep = []
+            for k in pending:
+                rc, u, s_, l_ = tcm.tcm_poll(ctx.h, tickets[k])
+                if rc == 0:
+                    U[k], st[k], lat[k] = u, s_, l_
+                    done += 1
+                else:
+                    keep.append(k)
+            pending = keep
+        elapsed = time.perf_counter() - t0
+        stats = tcm.tcm_server_stats(ctx.h)
+        tcm.tcm_server_stop(ctx.h)
+        return U, st, lat, elapsed, stats
+
+    ctx = tcm.Context(0)
+    run(ctx, None)                                            # warm-up (allocations, code load)
+    U, st, lat, elapsed, stats = run(ctx, None)
+    sat = nreq / elapsed
+    out = {"workload": f"serving trace: {nreq} requests, pool of {pool} chain fragments ({ntot} atoms), "
+                       "log-uniform 1e3..1e6 atoms, L ~ U{8..24}, 30% reuse of resident fragments, "
+                       "R0 = 1.5(a_A+a_B), random poses; inputs resident in HBM (borrowed)",
+           "saturation_pairs_per_s": sat, "burst_stats": stats, "statuses_ok": int(np.sum(st == 0))}
+    rng = np.random.default_rng(55)
+    gaps = rng.exponential(1.0, nreq)
+    loads = {}
+    for f in fractions:
+        arr = np.cumsum(gaps) / (f * sat)
+        Uf, stf, latf, el, sts = run(ctx, arr)
+        loads[str(f)] = {"qps": f * sat, "pairs_per_s": nreq / el, "p50_ms": 1e3 * float(np.percentile(latf, 50)),
+                         "p99_ms": 1e3 * float(np.percentile(latf, 99)), "launches": sts["launches"],
+                         "cache_hits": sts["cache_hits"], "cache_misses": sts["cache_misses"]}
+    out["open_loop"] = loads
+    # alone vs in the mix: every served result equals the burst's bit for bit
+    out["alone_vs_mix_bitwise_equal"] = bool(np.array_equal(Uf, U))
+    # plain single-pair GPU path on the same trace
+    ids = {}
+    for f in range(pool):
+        ids[f] = tcm.tcm_mol_register_device(ctx.h, *ptrs(f), int(w["counts"][f]))
+    service = np.zeros(nreq)
+    Up = np.zeros(nreq)
+    for i in range(nreq):
+        ka, fa, kb, fb, new = recs[i]
+        r = reqs[i]
+        rq = tcm.make_requests(ids[fa], ids[fb], list(r.R), int(r.L), list(r.quat_b),
+                               flags=0 if new else tcm.TCM_REUSE)
+        t1 = time.perf_counter()
+        u, s_, _ = tcm.tcm_batch_energy(ctx.h, rq)
+        service[i] = time.perf_counter() - t1
+        Up[i] = u[0]
+    out["plain_single_pair"] = {"pairs_per_s": nreq / service.sum(), "mean_service_ms": 1e3 * service.mean()}
+    for f in fractions:
+        arr = np.cumsum(gaps) / (f * sat)
+        fin = np.zeros(nreq)
+        tprev = 0.0
+        for i in range(nreq):
+            tprev = max(arr[i], tprev) + service[i]
+            fin[i] = tprev
+        l = fin - arr
+        out["plain_single_pair"][str(f)] = {"p50_ms": 1e3 * float(np.percentile(l, 50)),
+                                            "p99_ms": 1e3 * float(np.percentile(l, 99))}
+    out["served_vs_plain_max_rel_diff"] = float(np.max(np.abs(U - Up) / np.maximum(np.abs(Up), 1e-300)))
+    # relative error vs the FP64 oracle on a sample (smallest requests first, bounded time)
+    import oracle
+    order = np.argsort([w["counts"][r[1]] + w["counts"][r[3]] for r in recs])
+    rel, t_cpu, k = [], 0.0, 0
+    for i in order:
+        if t_cpu > oracle_seconds:
+            break
+        ka, fa, kb, fb, new = recs[i]
+        xa = w["xyz"][w["offsets"][fa]:w["offsets"][fa + 1]]
+        qa = w["q"][w["offsets"][fa]:w["offsets"][fa + 1]]
+        xb = w["xyz"][w["offsets"][fb]:w["offsets"][fb + 1]]
+        qb = w["q"][w["offsets"][fb]:w["offsets"][fb + 1]]
+        L = int(w["L"][i])
+        ts = time.perf_counter()
+        cA, cB = oracle.centroid(xa), oracle.centroid(xb)
+        d = oracle.energy(oracle.moments(xa, qa, cA, L),
+                          oracle.moments(oracle.pose(xb, cB, w["quats"][i], cB), qb, cB, L),
+                          np.array(list(reqs[i].R)), L, full=True)
+        t_cpu += time.perf_counter() - ts
+        k += 1
+        rel.append((abs(U[i] - d["U"]) / abs(d["U"]), abs(U[i] - d["U"]) / d["abs_sum"]))
+    rel = np.array(rel)
+    out["rel_err"] = {"sample_requests": k, "max_rel": float(rel[:, 0].max()), "median_rel": float(np.median(rel[:, 0])),
+                      "max_err_over_abs_terms": float(rel[:, 1].max())}
+    ctx.close()
+    del soa
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +193,8 @@ def main():
     ap.add_argument("--npairs", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
@@ -69,6 +225,16 @@ def main():
         n = int(w["counts"][f])
         ids.append(tcm.tcm_mol_register_device(ctx.h, base + off, base + row + off, base + 2 * row + off,
                                                base + 3 * row + off, n, precision=tcm.TCM_F32C))
+    # autotuned tile shapes: atoms per thread for every (L, size bucket) in the batch
+    t_tune = time.time()
+    tuned = {}
+    for L in sorted(set(int(x) for x in w["L"])):
+        sizes = np.concatenate([w["counts"][0::2][w["L"] == L], w["counts"][1::2][w["L"] == L]])
+        for b in sorted(set(int(np.log2(n)) for n in sizes)):
+            rep = int(np.median(sizes[(np.log2(sizes)).astype(int) == b]))
+            k, _ = tcm.tcm_autotune(ctx.h, tcm.TCM_F32C, L, rep)
+            tuned[f"L{L}/2^{b}"] = k
+    log(f"bench: autotuned {len(tuned)} (L, size) buckets in {time.time() - t_tune:.1f}s: {tuned}")
     req = tcm.make_requests(ids[0::2], ids[1::2], w["R"], w["L"], w["quats"])
     plan = tcm.tcm_plan_create(ctx.h, req, use_graph=True)
     info = tcm.tcm_plan_info(plan)
@@ -136,6 +302,17 @@ def main():
                "definition": "|U_gpu - U_oracle| / |U_oracle| (FP64 oracle, same centres and poses)"}
         log(f"bench: oracle sample {k} pairs in {t_cpu:.1f}s; max rel err {err['max_rel']:.2e}")
 
+    tcm.tcm_plan_destroy(plan)
+    ctx.close()
+    del soa
+    torch.cuda.empty_cache()
+    serving = None
+    if not args.no_serve:
+        t_s = time.time()
+        serving = serving_section(tcm, synth, torch, nreq=args.serve_requests)
+        log(f"bench: serving section in {time.time() - t_s:.1f}s: "
+            f"saturation {serving['saturation_pairs_per_s']:.0f} pairs/s, open loop {serving['open_loop']}")
+
     out = {
         "metric": "pair energies/s & p50/p99 latency at stated rel. err vs FP64 oracle",
         "value": args.npairs / (ms_step * 1e-3),
@@ -154,7 +331,9 @@ def main():
                    "geometry": "excluded-volume random-walk chains, q~N(0,0.3) zero net charge, "
                                "R0 = 1.5(a_A+a_B), random pose of B",
                    "precision": "moments FP32 compensated; rotation, geometric factors, contraction FP64",
-                   "execution": "one HIP graph replay per step (stats, per-L tile kernels, pair kernel)",
+                   "execution": "one HIP graph replay per step: per-L (statistics -> tiles) branches on "
+                                "forked streams, moment finalisation, pair kernel",
+                   "tile_autotune": tuned,
                    "parallelism": "single GPU", "seed": 4},
         "latency_ms": {"p50": ms_step, "p99": ms_step,
                        "note": "all pairs of a batch complete together at the end of the replay"},
@@ -164,10 +343,9 @@ def main():
                      "unit": "TFLOP/s", "frac": moment_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "moment-pass tile kernels (FP32), 6(L+1)(L+2) flops per atom"},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    tcm.tcm_plan_destroy(plan)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -84,6 +84,12 @@ void tcm_destroy(tcm_ctx *ctx);
 int tcm_set_stream(tcm_ctx *ctx, void *hip_stream);
 void *tcm_get_stream(tcm_ctx *ctx);
 
+/* Device bytes the context currently holds (tables, workspaces, resident molecules, the
+ * serving cache) and its HBM budget; tcm_set_budget changes the budget (0 = unbounded) for
+ * later allocations. */
+int tcm_mem_info(tcm_ctx *ctx, size_t *used_out, size_t *budget_out);
+int tcm_set_budget(tcm_ctx *ctx, size_t hbm_budget_bytes);
+
 /* eq. 8 for one molecule.  coords [n][3], charges [n] (host FP64); centre FP64[3] or NULL
  * (centroid); 0 <= L <= TCM_LMAX; precision TCM_F64 or TCM_F32C.  Q_out: (L+1)^2 FP64
  * (packed layout above).  radius_out (a = max |R_i - centre|) and centre_out (FP64[3])
@@ -171,8 +177,10 @@ void tcm_plan_destroy(tcm_plan *plan);
 /* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */
 int tcm_tune_get(tcm_ctx *ctx, int precision, int L, int64_t n, int *kper_out);
 int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);
-/* Time every candidate kper for (precision, L) on a synthetic molecule of n atoms and keep
- * the fastest for n's size bucket.  best_ms_out may be NULL. */
+/* Autotuner: time the moment-tile kernels for every candidate kper (4..128) on a synthetic
+ * batch of copies of an n-atom molecule large enough to fill the device, and keep the
+ * fastest for (precision, L, n's power-of-two size bucket).  best_ms_out (may be NULL): the
+ * winner's tile time per molecule, in ms. */
 int tcm_autotune(tcm_ctx *ctx, int precision, int L, int64_t n, int *best_kper_out,
                  double *best_ms_out);
 /* Persist / restore the tuning table (text file). */
@@ -186,9 +194,13 @@ int tcm_tune_load(tcm_ctx *ctx, const char *path);
  * computed once per order and kept for later poses and partners.  A fragment that is not
  * resident must come with its atoms (FP64 structure of arrays x, y, z, q; device pointers,
  * or host pointers with TCM_HOST_ATOMS), which the server copies into memory it owns, so the
- * caller may reuse the arrays once the request completes.  New fragments become resident
- * under an LRU policy bounded by the context's HBM budget. */
-#define TCM_HOST_ATOMS 4    /* request flag: atoms_a / atoms_b are host pointers */
+ * caller may reuse the arrays once the request completes (or, with TCM_BORROW_ATOMS,
+ * references in place).  New fragments become resident under an LRU policy bounded by the
+ * context's HBM budget; their moment tables live in fixed-size slots of a device arena. */
+#define TCM_HOST_ATOMS   4  /* request flag: atoms_a / atoms_b are host pointers (copied)    */
+#define TCM_BORROW_ATOMS 8  /* request flag: device atoms are referenced, not copied; they   */
+                            /* must stay valid while the fragment is resident (until it is  */
+                            /* evicted or the server stops)                                 */
 
 typedef struct {
     int64_t key_a;

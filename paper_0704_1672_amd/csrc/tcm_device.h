@@ -293,28 +293,35 @@ __device__ __forceinline__ void tile_item(const TileCtx& tc, const DevPlan& P, c
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)tc.tile * WG * mw.kper + tid;
     double r2max = 0.0;
-    int64_t a = base;
-    AtomIn nxt;
-    bool have = a < mw.n;
-    if (have) nxt = load_atom(mw, a);
-    for (int i = 0; i < mw.kper && have; ++i) {
-        const AtomIn cur = nxt;
-        a += WG;
-        have = (i + 1 < mw.kper) && (a < mw.n);
-        if (have) nxt = load_atom(mw, a);
-        const double dx = cur.x - tc.cx, dy = cur.y - tc.cy, dz = cur.z - tc.cz;
-        r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
-        const F px = (F)(dx * tc.inv_s), py = (F)(dy * tc.inv_s), pz = (F)(dz * tc.inv_s);
-        const F r2 = px * px + py * py + pz * pz;
-        F ir, r;
-        if constexpr (sizeof(F) == 4) {
-            ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-            r = r2 * ir;
-        } else {
-            r = sqrt(r2);
-            ir = r > 0.0 ? 1.0 / r : 0.0;
+    // atoms of this thread: base, base + WG, ... (at most kper, all < n)
+    const int64_t left = mw.n - base;
+    const int cnt = left <= 0 ? 0 : (int)min((int64_t)mw.kper, (left + WG - 1) / WG);
+    if (cnt > 0) {
+        // two atoms in flight ahead of the one being evaluated; indices past the thread's
+        // last atom are clamped to it (valid memory, values unused)
+        const int64_t last = base + (int64_t)(cnt - 1) * WG;
+        AtomIn n0 = load_atom(mw, base);
+        AtomIn n1 = load_atom(mw, min(base + WG, last));
+        int64_t a2 = base + 2 * WG;
+        for (int i = 0; i < cnt; ++i) {
+            const AtomIn cur = n0;
+            n0 = n1;
+            n1 = load_atom(mw, min(a2, last));
+            a2 += WG;
+            const double dx = cur.x - tc.cx, dy = cur.y - tc.cy, dz = cur.z - tc.cz;
+            r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
+            const F px = (F)(dx * tc.inv_s), py = (F)(dy * tc.inv_s), pz = (F)(dz * tc.inv_s);
+            const F r2 = px * px + py * py + pz * pz;
+            F ir, r;
+            if constexpr (sizeof(F) == 4) {
+                ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+                r = r2 * ir;
+            } else {
+                r = sqrt(r2);
+                ir = r > 0.0 ? 1.0 / r : 0.0;
+            }
+            atom_block<F, L, M0, M1>(acc, pz * ir, px * ir, py * ir, r, (F)cur.q);
         }
-        atom_block<F, L, M0, M1>(acc, pz * ir, px * ir, py * ir, r, (F)cur.q);
     }
     const int64_t nt = mw.ntiles;
     if constexpr (sizeof(F) == 4) {

@@ -292,9 +292,9 @@ __global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int slot, int begin, 
     }
 }
 
-__global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P)
+__global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P, int mol_begin, int mol_end)
 {
-    for (int mol = blockIdx.x * blockDim.x + threadIdx.x; mol < P.nmol; mol += gridDim.x * blockDim.x)
+    for (int mol = mol_begin + blockIdx.x * blockDim.x + threadIdx.x; mol < mol_end; mol += gridDim.x * blockDim.x)
         stats_finalize(P, mol);
 }
 
@@ -361,15 +361,19 @@ hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DevPlan& P, bool moments, int grid, hipStream_t s)
+hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s)
+{
+    if (mol_end <= mol_begin) return hipSuccess;
+    hipLaunchKernelGGL(tcm_stats_finalize, dim3((mol_end - mol_begin + WG - 1) / WG), dim3(WG), 0, s, P, mol_begin,
+                       mol_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_finalize(const DevPlan& P, int grid, hipStream_t s)
 {
     if (P.nmol <= 0) return hipSuccess;
-    if (moments) {
-        if (grid > P.nmol) grid = P.nmol;
-        hipLaunchKernelGGL(tcm_moments_finalize, dim3(grid), dim3(WG), 0, s, P);
-    } else {
-        hipLaunchKernelGGL(tcm_stats_finalize, dim3((P.nmol + WG - 1) / WG), dim3(WG), 0, s, P);
-    }
+    if (grid > P.nmol) grid = P.nmol;
+    hipLaunchKernelGGL(tcm_moments_finalize, dim3(grid), dim3(WG), 0, s, P);
     return hipGetLastError();
 }
 

@@ -239,6 +239,39 @@ static void build_norm_tables(int Lmax, std::vector<double>& invk, std::vector<d
 // ------------------------------------------------------------------ planning
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Device bytes build_plan would add to ws for these jobs (growth of each buffer beyond its
+// current capacity), so that a caller can make room under its HBM budget first.
+size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols, const std::vector<PairJob>& pairs)
+{
+    int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0;
+    std::vector<std::pair<int, int>> groups;
+    for (const MolJob& j : mols) {
+        const int kper = c->kper_for(j.prec, j.L, j.n);
+        const int64_t ta = (int64_t)WG * kper;
+        const int64_t nt = j.n > 0 ? (j.n + ta - 1) / ta : 1;
+        const int64_t ns = j.n > 0 ? (j.n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
+        if (j.prec == TCM_F32C) off_f += 2 * nt * nh(j.L); else off_d += nt * nh(j.L);
+        off_s += ns;
+        off_r2 += nt;
+        groups.push_back({j.prec, j.L});
+    }
+    std::sort(groups.begin(), groups.end());
+    const int ng = (int)(std::unique(groups.begin(), groups.end()) - groups.begin());
+    const size_t nmol = mols.size(), np = pairs.size();
+    const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (nmol + 1) + 1024;
+    const size_t need[8] = {blob, sizeof(int32_t) * (2 + 2 * (size_t)ng),
+                            sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
+                            sizeof(double) * 10 * (size_t)(off_s > 0 ? off_s : 1), sizeof(double) * (size_t)(off_r2 > 0 ? off_r2 : 1),
+                            sizeof(double) * (np > 0 ? np : 1), sizeof(int32_t) * (np > 0 ? np : 1)};
+    const DevBuf* have[8] = {&ws.blob, &ws.sync, &ws.part_f, &ws.part_d, &ws.stats, &ws.r2, &ws.outU, &ws.outS};
+    size_t grow = 0;
+    for (int i = 0; i < 8; ++i) {
+        const size_t want = need[i] < 256 ? 256 : need[i];
+        if (want > have[i]->cap) grow += want;
+    }
+    return grow;
+}
+
 int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const std::vector<PairJob>& pairs_in,
                BuiltPlan& bp, hipStream_t s)
 {
@@ -343,10 +376,14 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     bp.groups.clear();
     for (int i = 0; i < nmol; ++i) {
         if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L)
-            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i]});
-        bp.groups.back().end = tp[i + 1];
+            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i], i, i, sp[i], sp[i]});
+        BuiltPlan::Group& G = bp.groups.back();
+        G.end = tp[i + 1];
+        G.mol_end = i + 1;
+        G.stats_end = sp[i + 1];
     }
-    const int nqueue = 2 + (int)bp.groups.size();
+    bp.ws = &ws;
+    const int nqueue = 1 + 2 * (int)bp.groups.size();
     const int64_t sync_ints = nqueue + 1;
     if ((rc = c->alloc(ws.sync, sizeof(int32_t) * sync_ints)) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.part_f, sizeof(float) * (off_f > 0 ? off_f : 1))) != TCM_OK) return rc;
@@ -388,27 +425,66 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     return TCM_OK;
 }
 
-int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t* ev)
+static int ensure_aux(Workspace& ws)
 {
-    if (launch_clear(bp.P.queue, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
-    (void)phased;                  // every run is phased: stats, tile groups, pairs
-    const int grid = 2 * c->num_cu;
-    const int S = bp.n_stats;
-    // ev (optional): 5 events on the launch stream -- before the statistics launches, before
-    // the tile launches, before the moment finalisation, before the pair launch, at the end
-    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_stats(bp.P, 0, 0, S, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_finalize(bp.P, false, grid, s) != hipSuccess) return TCM_EDEVICE;
-    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
-    for (size_t g = 0; g < bp.groups.size(); ++g) {
-        const BuiltPlan::Group& G = bp.groups[g];
-        if (launch_tiles(G.prec, G.L, bp.P, 2 + (int)g, S + G.begin, S + G.end, grid, s) != hipSuccess)
+    if (ws.fork) return TCM_OK;
+    for (int k = 0; k < NAUX; ++k) {
+        if (hipStreamCreateWithFlags(&ws.aux[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ws.join[k], hipEventDisableTiming) != hipSuccess)
             return TCM_EDEVICE;
     }
-    if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_finalize(bp.P, true, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming) != hipSuccess) return TCM_EDEVICE;
+    return TCM_OK;
+}
+
+// Issue the launches of one run.  Queue slots: 0 pairs, 1 + 2g statistics of group g,
+// 2 + 2g tiles of group g.
+//   concurrent (serial = false): each (precision, L) group runs statistics -> centre/scale
+//     -> tiles on its own forked stream, so the HBM-bound statistics of one group overlap
+//     the ALU-bound tiles of another; the moment finalisation and the pairs follow the join.
+//   serial (serial = true): all statistics, then all tiles, on s; with ev (5 events) the
+//     elapsed time of each step is measured on the launch stream.
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev)
+{
+    const int grid = 2 * c->num_cu;
+    const int S = bp.n_stats;
+    const int ng = (int)bp.groups.size();
+    if (launch_clear(bp.P.queue, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
+    auto group_stats = [&](int g, hipStream_t st) {
+        const BuiltPlan::Group& G = bp.groups[g];
+        if (launch_stats(bp.P, 1 + 2 * g, G.stats_begin, G.stats_end, 4 * grid, st) != hipSuccess) return false;
+        return launch_stats_finalize(bp.P, G.mol_begin, G.mol_end, st) == hipSuccess;
+    };
+    auto group_tiles = [&](int g, hipStream_t st) {
+        const BuiltPlan::Group& G = bp.groups[g];
+        return launch_tiles(G.prec, G.L, bp.P, 2 + 2 * g, S + G.begin, S + G.end, grid, st) == hipSuccess;
+    };
+    if (!serial && ng > 1 && bp.ws && ensure_aux(*bp.ws) == TCM_OK) {
+        Workspace& ws = *bp.ws;
+        if (hipEventRecord(ws.fork, s) != hipSuccess) return TCM_EDEVICE;
+        const int nuse = ng < NAUX ? ng : NAUX;
+        for (int k = 0; k < nuse; ++k)
+            if (hipStreamWaitEvent(ws.aux[k], ws.fork, 0) != hipSuccess) return TCM_EDEVICE;
+        for (int g = 0; g < ng; ++g) {
+            hipStream_t st = ws.aux[g % NAUX];
+            if (!group_stats(g, st) || !group_tiles(g, st)) return TCM_EDEVICE;
+        }
+        for (int k = 0; k < nuse; ++k) {
+            if (hipEventRecord(ws.join[k], ws.aux[k]) != hipSuccess) return TCM_EDEVICE;
+            if (hipStreamWaitEvent(s, ws.join[k], 0) != hipSuccess) return TCM_EDEVICE;
+        }
+    } else {
+        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
+        for (int g = 0; g < ng; ++g)
+            if (!group_stats(g, s)) return TCM_EDEVICE;
+        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
+        for (int g = 0; g < ng; ++g)
+            if (!group_tiles(g, s)) return TCM_EDEVICE;
+        if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
+    }
+    if (launch_moments_finalize(bp.P, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_pairs(bp.P, 1, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_pairs(bp.P, 0, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[4], s) != hipSuccess) return TCM_EDEVICE;
     return TCM_OK;
 }
@@ -424,6 +500,14 @@ int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s)
 
 void free_workspace(Ctx* c, Workspace& ws)
 {
+    for (int k = 0; k < NAUX; ++k) {
+        if (ws.aux[k]) (void)hipStreamDestroy(ws.aux[k]);
+        if (ws.join[k]) (void)hipEventDestroy(ws.join[k]);
+        ws.aux[k] = nullptr;
+        ws.join[k] = nullptr;
+    }
+    if (ws.fork) (void)hipEventDestroy(ws.fork);
+    ws.fork = nullptr;
     c->release(ws.blob); c->release(ws.sync); c->release(ws.part_f); c->release(ws.part_d);
     c->release(ws.stats); c->release(ws.r2); c->release(ws.outU); c->release(ws.outS);
     if (ws.hstage) (void)hipHostFree(ws.hstage);
@@ -531,6 +615,21 @@ extern "C" int tcm_set_stream(tcm_ctx* t, void* s)
 }
 
 extern "C" void* tcm_get_stream(tcm_ctx* t) { return t ? (void*)t->c.stream : nullptr; }
+
+extern "C" int tcm_mem_info(tcm_ctx* t, size_t* used, size_t* budget)
+{
+    if (!t) return TCM_EINVAL;
+    if (used) *used = t->c.used.load();
+    if (budget) *budget = t->c.budget;
+    return TCM_OK;
+}
+
+extern "C" int tcm_set_budget(tcm_ctx* t, size_t budget)
+{
+    if (!t) return TCM_EINVAL;
+    t->c.budget = budget;
+    return TCM_OK;
+}
 
 // Upload host AoS atoms into tmp_atoms as SoA; returns device pointers.
 static int upload_atoms(Ctx& c, DevBuf& dst, const double* coords, const double* charges, int64_t n,
@@ -1039,6 +1138,11 @@ extern "C" void tcm_plan_destroy(tcm_plan* pl)
                       &pl->ws.outU, &pl->ws.outS})
         if (b->p) (void)hipFree(b->p);
     if (pl->ws.hstage) (void)hipHostFree(pl->ws.hstage);
+    for (int k = 0; k < NAUX; ++k) {
+        if (pl->ws.aux[k]) (void)hipStreamDestroy(pl->ws.aux[k]);
+        if (pl->ws.join[k]) (void)hipEventDestroy(pl->ws.join[k]);
+    }
+    if (pl->ws.fork) (void)hipEventDestroy(pl->ws.fork);
     delete pl;
 }
 
@@ -1087,11 +1191,14 @@ extern "C" int tcm_tune_load(tcm_ctx* t, const char* path)
     return TCM_OK;
 }
 
-// Times each candidate kper on a synthetic molecule (deterministic points in a unit ball,
-// charges in [-1, 1]) with HIP events around the persistent launch.
+// Times each candidate kper for (precision, L, n's size bucket) with HIP events around the
+// tile launches of a synthetic batch: copies of one molecule of n atoms (points in a ball,
+// charges in [-1, 1]), enough copies to fill the device, so the measurement reflects batched
+// throughput rather than launch latency.
 extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k, double* best_ms)
 {
-    if (!t || L < 0 || L > LMAX || n <= 0 || (prec != TCM_F64 && prec != TCM_F32C)) return TCM_EINVAL;
+    if (!t || L < 0 || L > LMAX || n <= 0 || n > (int64_t(1) << 30) || (prec != TCM_F64 && prec != TCM_F32C))
+        return TCM_EINVAL;
     Ctx& c = t->c;
     std::lock_guard<std::mutex> g(c.mu);
     (void)hipSetDevice(c.device);
@@ -1110,36 +1217,42 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
         for (int d = 0; d < 3; ++d) coords[3 * i + d] = 10.0 * v[d];
         charges[i] = 2 * rnd() - 1;
     }
+    int64_t reps = (int64_t(4) << 20) / n;
+    if (reps < 1) reps = 1;
+    if (reps > 4096) reps = 4096;
     DevBuf atoms, qbuf;
     const double* d[4];
     int rc = upload_atoms(c, atoms, coords.data(), charges.data(), n, d, s);
-    if (rc == TCM_OK) rc = c.alloc(qbuf, sizeof(double) * (nh(L) + 8));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == TCM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = TCM_EDEVICE;
+    if (rc == TCM_OK) rc = c.alloc(qbuf, sizeof(double) * (nh(L) + 8) * reps);
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (auto& e : ev)
+        if (rc == TCM_OK && hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
     const int64_t key = tune_key(prec, L, n);
     const bool had = c.tune.count(key) > 0;
     const int old = had ? c.tune[key] : 0;
     double bestt = 1e300;
     int bestk = 0;
-    for (int k = 2; rc == TCM_OK && k <= 128; k <<= 1) {
+    for (int k = 4; rc == TCM_OK && k <= 128; k <<= 1) {
         c.tune[key] = k;
-        MolJob j{};
-        j.x = d[0]; j.y = d[1]; j.z = d[2]; j.q = d[3];
-        j.n = n;
-        j.L = L;
-        j.prec = prec;
-        j.Q = (double*)qbuf.p;
-        j.meta = j.Q + nh(L);
+        std::vector<MolJob> jobs(reps);
+        for (int64_t r = 0; r < reps; ++r) {
+            MolJob& j = jobs[r];
+            j = MolJob{};
+            j.x = d[0]; j.y = d[1]; j.z = d[2]; j.q = d[3];
+            j.n = n;
+            j.L = L;
+            j.prec = prec;
+            j.Q = (double*)qbuf.p + r * (nh(L) + 8);
+            j.meta = j.Q + nh(L);
+        }
         BuiltPlan bp;
-        if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) break;
+        if ((rc = build_plan(&c, c.ws, jobs, {}, bp, s)) != TCM_OK) break;
         double tot = 0.0;
         for (int rep = 0; rep < 4 && rc == TCM_OK; ++rep) {
-            (void)hipEventRecord(e0, s);
-            rc = run_plan(&c, bp, s, false, nullptr);
-            (void)hipEventRecord(e1, s);
+            rc = run_plan(&c, bp, s, true, ev);
             if (rc == TCM_OK) rc = check_err(&c, bp, s);
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
             if (rep > 0) tot += ms;             // first repetition is warm-up
         }
         if (rc == TCM_OK && tot / 3 < bestt) {
@@ -1147,8 +1260,8 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
             bestk = k;
         }
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     c.release(atoms);
     c.release(qbuf);
     if (rc != TCM_OK || bestk == 0) {
@@ -1157,6 +1270,6 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
     }
     c.tune[key] = bestk;
     if (best_k) *best_k = bestk;
-    if (best_ms) *best_ms = bestt;
+    if (best_ms) *best_ms = bestt / (double)reps;
     return TCM_OK;
 }

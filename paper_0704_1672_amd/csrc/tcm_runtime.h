@@ -22,7 +22,8 @@ int num_blocks_for(int prec, int L);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_finalize(const DevPlan& P, bool moments, int grid, hipStream_t s);
+hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
+hipError_t launch_moments_finalize(const DevPlan& P, int grid, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
 
 struct Ctx;
@@ -72,11 +73,17 @@ struct PairJob {
     int has_rot;
 };
 
-// Device-side state of a planned batch: the uploaded plan blob, scratch and outputs.
+constexpr int NAUX = 4;            // forked streams for concurrent (precision, L) groups
+
+// Device-side state of a planned batch: the uploaded plan blob, scratch and outputs, and
+// the streams and events its launches fork onto.
 struct Workspace {
     DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS;
     void* hstage = nullptr;        // pinned host staging for the blob
     size_t hstage_cap = 0;
+    hipStream_t aux[NAUX] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[NAUX] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct BuiltPlan {
@@ -86,7 +93,10 @@ struct BuiltPlan {
     int n_tiles = 0;
     struct Group {                 // molecules of one (precision, L): one tile launch
         int prec, L, begin, end;   // tile item range (tile numbering, before n_stats offset)
+        int mol_begin, mol_end;    // molecule range
+        int stats_begin, stats_end;
     };
+    Workspace* ws = nullptr;
     std::vector<Group> groups;
     int npairs = 0;
     int64_t sync_ints = 0;
@@ -99,7 +109,7 @@ struct Ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     int num_cu = 256;
-    size_t budget = 0;             // 0 = unbounded
+    std::atomic<size_t> budget{0}; // 0 = unbounded
     std::atomic<size_t> used{0};
     DevBuf t_invk, t_invf, t_rot;
     std::mutex mu;                 // guards molecules, tuning and the shared workspace
@@ -123,7 +133,9 @@ struct Ctx {
 // planning / running (tcm_runtime.cpp)
 int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols,
                const std::vector<PairJob>& pairs, BuiltPlan& bp, hipStream_t s);
-int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool phased, hipEvent_t* ev);
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev);
+size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols,
+                        const std::vector<PairJob>& pairs);
 int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s);
 void free_workspace(Ctx* c, Workspace& ws);
 int64_t tune_key(int prec, int L, int64_t n);

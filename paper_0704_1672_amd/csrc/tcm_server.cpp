@@ -29,12 +29,14 @@ struct SMol {
     int64_t key = 0;
     int64_t n = 0;
     int prec = TCM_F32C;
-    DevBuf atoms;                  // FP64 SoA, owned
-    DevBuf moments;
-    DevBuf meta;
+    DevBuf atoms;                  // FP64 SoA, owned (copy mode)
+    const double* src[4] = {nullptr, nullptr, nullptr, nullptr};   // borrowed atoms
+    double* moments = nullptr;     // slot of the moment arena: (LMAX+1)^2 table + 8 meta
+    int slot = -1;
     int Lcached = -1;              // valid resident order
     int busy = 0;                  // being computed by an in-flight launch
     int refs = 0;                  // referenced by in-flight launches
+    int pin = 0;                   // referenced by the batch being formed (not evictable)
     std::list<int64_t>::iterator lru;
 };
 
@@ -66,8 +68,15 @@ struct Slot {
     std::vector<SMol*> refd;
 };
 
+// Fixed-size slots for resident moment tables ((LMAX+1)^2 + 8 doubles each), carved from
+// device chunks allocated once, so admission never calls the device allocator for moments.
+constexpr int ARENA_SLOT = (LMAX + 1) * (LMAX + 1) + 8;
+constexpr int ARENA_CHUNK = 64;
+
 struct Server {
     Ctx* c = nullptr;
+    std::vector<DevBuf> arena;
+    std::vector<int> free_slots;
     tcm_server_cfg cfg{};
     std::thread th;
     std::mutex mu;
@@ -89,17 +98,34 @@ static double seconds_since(clock_t_::time_point t)
     return std::chrono::duration<double>(clock_t_::now() - t).count();
 }
 
-static void free_mol(Ctx* c, SMol* m)
+static void free_mol(Server* S, SMol* m)
 {
-    c->release(m->atoms);
-    c->release(m->moments);
-    c->release(m->meta);
+    S->c->release(m->atoms);
+    if (m->slot >= 0) S->free_slots.push_back(m->slot);
+    m->slot = -1;
+    m->moments = nullptr;
 }
 
-// Bytes a new fragment needs: atoms, a moment table of order L, metadata.
-static size_t mol_bytes(int64_t n, int L)
+static bool take_slot(Server* S, SMol* m)
 {
-    return sizeof(double) * (4 * (size_t)(n > 0 ? n : 1) + nh(L) + 8);
+    if (S->free_slots.empty()) {
+        DevBuf b;
+        if (S->c->alloc(b, sizeof(double) * ARENA_SLOT * ARENA_CHUNK) != TCM_OK) return false;
+        const int base = (int)S->arena.size() * ARENA_CHUNK;
+        S->arena.push_back(b);
+        for (int i = ARENA_CHUNK - 1; i >= 0; --i) S->free_slots.push_back(base + i);
+    }
+    m->slot = S->free_slots.back();
+    S->free_slots.pop_back();
+    m->moments = (double*)S->arena[m->slot / ARENA_CHUNK].p + (size_t)(m->slot % ARENA_CHUNK) * ARENA_SLOT;
+    return true;
+}
+
+// Device bytes a new fragment needs from the budget: its atoms when copied (moment slots
+// come from the arena, charged when a chunk is added).
+static size_t mol_bytes(int64_t n, bool borrow)
+{
+    return borrow ? 0 : sizeof(double) * 4 * (size_t)(n > 0 ? n : 1) + sizeof(double) * ARENA_SLOT;
 }
 
 // Evict idle fragments (least recently used first) until `need` more bytes fit the budget.
@@ -112,8 +138,8 @@ static bool make_room(Server* S, size_t need)
         --it;
         auto f = S->cache.find(*it);
         SMol* m = f->second.get();
-        if (m->refs == 0 && !m->busy) {
-            free_mol(c, m);
+        if (m->refs == 0 && m->pin == 0 && !m->busy) {
+            free_mol(S, m);
             it = S->lru.erase(it);
             S->cache.erase(f);
             ++S->evictions;
@@ -140,12 +166,14 @@ static int copy_atoms(SMol* m, const double* const src[4], bool host, hipStream_
     return TCM_OK;
 }
 
-// Finish a completed launch (called with S->mu held).
-static void retire(Server* S, Slot& sl)
+// Finish a launch (called with S->mu held).  failed: the launch never ran (host-side
+// error); its requests already carry their status and nothing it would have computed is
+// marked resident.
+static void retire(Server* S, Slot& sl, bool failed)
 {
     const double* U = (const double*)sl.hpin;
     const int32_t* st = (const int32_t*)(U + sl.cap);
-    const int32_t err = st[sl.cap];
+    const int32_t err = failed ? 1 : st[sl.cap];
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
         SResult r;
         const int j = sl.job_of[i];
@@ -179,7 +207,7 @@ static void admit_and_launch(Server* S, Slot& sl)
     std::vector<SReq> batch;
     std::vector<int32_t> pre;
     std::deque<SReq> keep;
-    auto get = [&](int64_t key, const double* const atoms[4], int64_t n, int L, int prec, bool host,
+    auto get = [&](int64_t key, const double* const atoms[4], int64_t n, int L, int prec, int flags,
                    int* status) -> SMol* {
         auto f = S->cache.find(key);
         if (f != S->cache.end()) {
@@ -187,38 +215,35 @@ static void admit_and_launch(Server* S, Slot& sl)
             if (m->busy) { *status = TCM_EAGAIN; return nullptr; }       // wait for the launch
             auto nd = need.find(m);
             const bool recompute = m->Lcached < L && (nd == need.end() || nd->second < L);
-            // an in-flight launch still reads this table: do not rewrite or reallocate it
+            // an in-flight launch still reads this table: do not rewrite it
             if (recompute && m->refs > 0) { *status = TCM_EAGAIN; return nullptr; }
-            if (!recompute) ++S->hits; else ++S->misses;
-            if (m->moments.cap < sizeof(double) * nh(L)) {
-                if (!make_room(S, sizeof(double) * nh(L))) { *status = TCM_EAGAIN; return nullptr; }
-                if (c->alloc(m->moments, sizeof(double) * nh(L)) != TCM_OK) { *status = TCM_EAGAIN; return nullptr; }
-                m->Lcached = -1;
-            }
             return m;
         }
-        if (!atoms[0] || !atoms[1] || !atoms[2] || !atoms[3] || n < 0) {
-            if (n == 0 && atoms[0] == nullptr) { /* empty fragment without arrays is fine */ }
-            else { *status = TCM_ENOTFOUND; return nullptr; }
-        }
-        const size_t bytes = mol_bytes(n, L);
-        if (!make_room(S, bytes)) { *status = TCM_EAGAIN; return nullptr; }
+        const bool has = atoms[0] && atoms[1] && atoms[2] && atoms[3];
+        if (!(has || n == 0)) { *status = TCM_ENOTFOUND; return nullptr; }
+        const bool borrow = (flags & TCM_BORROW_ATOMS) != 0;
+        if (!make_room(S, mol_bytes(n, borrow))) { *status = TCM_EAGAIN; return nullptr; }
         auto m = std::make_unique<SMol>();
         m->key = key;
         m->n = n;
         m->prec = prec;
-        if (c->alloc(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1)) != TCM_OK ||
-            c->alloc(m->moments, sizeof(double) * nh(L)) != TCM_OK || c->alloc(m->meta, sizeof(double) * 8) != TCM_OK) {
-            free_mol(c, m.get());
-            *status = TCM_EAGAIN;
-            return nullptr;
+        if (!take_slot(S, m.get())) { *status = TCM_EAGAIN; return nullptr; }
+        if (borrow) {
+            for (int k = 0; k < 4; ++k) m->src[k] = atoms[k];
+        } else {
+            if (c->alloc(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1)) != TCM_OK) {
+                free_mol(S, m.get());
+                *status = TCM_EAGAIN;
+                return nullptr;
+            }
+            if (copy_atoms(m.get(), atoms, (flags & TCM_HOST_ATOMS) != 0, sl.stream) != TCM_OK) {
+                free_mol(S, m.get());
+                *status = TCM_EDEVICE;
+                return nullptr;
+            }
+            const double* d = (const double*)m->atoms.p;
+            for (int k = 0; k < 4; ++k) m->src[k] = d + k * n;
         }
-        if (copy_atoms(m.get(), atoms, host, sl.stream) != TCM_OK) {
-            free_mol(c, m.get());
-            *status = TCM_EDEVICE;
-            return nullptr;
-        }
-        ++S->misses;
         S->lru.push_front(key);
         m->lru = S->lru.begin();
         SMol* raw = m.get();
@@ -230,10 +255,11 @@ static void admit_and_launch(Server* S, Slot& sl)
         SReq q = S->pending.front();
         S->pending.pop_front();
         const tcm_request& r = q.r;
-        const bool host = (r.flags & TCM_HOST_ATOMS) != 0;
         int sa = TCM_OK, sb = TCM_OK;
-        SMol* a = get(r.key_a, r.atoms_a, r.n_a, r.L, r.precision, host, &sa);
-        SMol* b = a ? get(r.key_b, r.atoms_b, r.n_b, r.L, r.precision, host, &sb) : nullptr;
+        SMol* a = get(r.key_a, r.atoms_a, r.n_a, r.L, r.precision, r.flags, &sa);
+        if (a) ++a->pin;                   // fetching b must not evict a
+        SMol* b = a ? get(r.key_b, r.atoms_b, r.n_b, r.L, r.precision, r.flags, &sb) : nullptr;
+        if (a) --a->pin;
         if (!a || !b) {
             const int st = !a ? sa : sb;
             if (st == TCM_EAGAIN) {
@@ -246,12 +272,16 @@ static void admit_and_launch(Server* S, Slot& sl)
             continue;
         }
         for (SMol* m : {a, b}) {
+            auto nd = need.find(m);
+            if (m->Lcached >= r.L || (nd != need.end() && nd->second >= r.L)) ++S->hits; else ++S->misses;
             if (m->Lcached < r.L) {
                 auto it = need.find(m);
                 if (it == need.end()) need[m] = r.L;
                 else if (r.L > it->second) it->second = r.L;
             }
             touch(S, m);
+            ++m->pin;                      // later admissions in this pass must not evict it
+            refd.push_back(m);
         }
         batch.push_back(q);
         pre.push_back(TCM_OK);
@@ -272,15 +302,13 @@ static void admit_and_launch(Server* S, Slot& sl)
     for (auto& kv : need) {
         SMol* m = kv.first;
         const int L = std::max(kv.second, m->Lcached);
-        if (m->moments.cap < sizeof(double) * nh(L)) continue;   // cannot happen: allocated at admission
         MolJob j{};
-        const double* d = (const double*)m->atoms.p;
-        j.x = d; j.y = d + m->n; j.z = d + 2 * m->n; j.q = d + 3 * m->n;
+        j.x = m->src[0]; j.y = m->src[1]; j.z = m->src[2]; j.q = m->src[3];
         j.n = m->n;
         j.L = L;
         j.prec = m->prec;
-        j.Q = (double*)m->moments.p;
-        j.meta = (double*)m->meta.p;
+        j.Q = m->moments;
+        j.meta = m->moments + (ARENA_SLOT - 8);
         jobidx[m] = (int)mj.size();
         mj.push_back(j);
         m->busy = 1;
@@ -289,17 +317,22 @@ static void admit_and_launch(Server* S, Slot& sl)
     }
     std::vector<PairJob> pj;
     sl.job_of.assign(batch.size(), -1);
-    sl.refd.clear();
+    // the batch's pins become in-flight references (released when the launch retires)
+    for (SMol* m : refd) {
+        --m->pin;
+        ++m->refs;
+    }
+    sl.refd = refd;
     for (size_t i = 0; i < batch.size(); ++i) {
         if (pre[i] != TCM_OK) continue;
         const tcm_request& r = batch[i].r;
-        SMol* a = S->cache[r.key_a].get();
-        SMol* b = S->cache[r.key_b].get();
+        SMol* a = S->cache.find(r.key_a)->second.get();
+        SMol* b = S->cache.find(r.key_b)->second.get();
         PairJob j{};
-        j.QA = (const double*)a->moments.p;
-        j.QB = (const double*)b->moments.p;
-        j.metaA = (const double*)a->meta.p;
-        j.metaB = (const double*)b->meta.p;
+        j.QA = a->moments;
+        j.QB = b->moments;
+        j.metaA = a->moments + (ARENA_SLOT - 8);
+        j.metaB = b->moments + (ARENA_SLOT - 8);
         auto fa = jobidx.find(a), fb = jobidx.find(b);
         j.depA = fa == jobidx.end() ? -1 : fa->second;
         j.depB = fb == jobidx.end() ? -1 : fb->second;
@@ -310,10 +343,6 @@ static void admit_and_launch(Server* S, Slot& sl)
         j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
         sl.job_of[i] = (int)pj.size();
         pj.push_back(j);
-        ++a->refs;
-        ++b->refs;
-        sl.refd.push_back(a);
-        sl.refd.push_back(b);
     }
     sl.reqs = batch;
     sl.pre_status = pre;
@@ -328,6 +357,8 @@ static void admit_and_launch(Server* S, Slot& sl)
             sl.cap = cap;
     }
     int rc = sl.cap >= cap ? TCM_OK : TCM_ENOMEM;
+    // the launch's workspace comes out of the same budget: evict idle fragments first
+    if (rc == TCM_OK) (void)make_room(S, workspace_growth(c, sl.ws, mj, pj));
     if (rc == TCM_OK) rc = build_plan(c, sl.ws, mj, pj, sl.bp, sl.stream);
     if (rc == TCM_OK) rc = run_plan(c, sl.bp, sl.stream, false, nullptr);
     double* hU = (double*)sl.hpin;
@@ -348,8 +379,7 @@ static void admit_and_launch(Server* S, Slot& sl)
         (void)hipStreamSynchronize(sl.stream);
         for (size_t i = 0; i < batch.size(); ++i)
             if (sl.job_of[i] >= 0) { sl.job_of[i] = -1; sl.pre_status[i] = rc; }
-        for (auto& pr : sl.computed) pr.first->Lcached = -1;
-        retire(S, sl);
+        retire(S, sl, true);
     }
 }
 
@@ -361,7 +391,7 @@ static void server_loop(Server* S)
         bool progress = false;
         for (Slot& sl : S->slots) {
             if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
-                retire(S, sl);
+                retire(S, sl, false);
                 progress = true;
             }
         }
@@ -402,7 +432,8 @@ void server_destroy(Ctx* c)
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
-    for (auto& kv : S->cache) free_mol(c, kv.second.get());
+    for (auto& kv : S->cache) free_mol(S, kv.second.get());
+    for (DevBuf& b : S->arena) c->release(b);
     delete S;
     c->server = nullptr;
 }

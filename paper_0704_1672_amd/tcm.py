@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tcm.h")
 TCM_OK, TCM_EINVAL, TCM_EDOMAIN, TCM_ENOMEM, TCM_EDEVICE, TCM_EAGAIN, TCM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 TCM_LMAX = 32
 TCM_F64, TCM_F32C = 0, 1
-TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS = 1, 2, 4
+TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS, TCM_BORROW_ATOMS = 1, 2, 4, 8
 
 _dp = C.POINTER(C.c_double)
 _ip32 = C.POINTER(C.c_int32)
@@ -53,6 +53,8 @@ _SIGS = {
     "tcm_destroy": (None, [_vp]),
     "tcm_set_stream": (C.c_int, [_vp, _vp]),
     "tcm_get_stream": (_vp, [_vp]),
+    "tcm_mem_info": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "tcm_set_budget": (C.c_int, [_vp, C.c_size_t]),
     "tcm_moments": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
     "tcm_pair_energy": (C.c_int, [_vp, _dp, C.c_double, _dp, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp]),
     "tcm_mol_upload": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, _ip64]),
@@ -168,6 +170,16 @@ def tcm_set_stream(ctx, stream):
 
 def tcm_get_stream(ctx):
     return lib().tcm_get_stream(ctx)
+
+
+def tcm_mem_info(ctx):
+    u, b = C.c_size_t(), C.c_size_t()
+    _check(lib().tcm_mem_info(ctx, C.byref(u), C.byref(b)), "tcm_mem_info")
+    return u.value, b.value
+
+
+def tcm_set_budget(ctx, budget):
+    _check(lib().tcm_set_budget(ctx, int(budget)), "tcm_set_budget")
 
 
 def tcm_moments(ctx, coords, charges, L, precision=TCM_F64, centre=None):

@@ -1,0 +1,52 @@
+// Host-only stand-in for the subset of the HIP runtime that libtcm's host code calls, so that
+// the planner and the serving loop can be compiled for the CPU and exercised under
+// AddressSanitizer / ThreadSanitizer without a GPU.  Device memory is host memory, copies
+// are memcpy, events complete after a few queries (so launches stay "in flight" for a while),
+// graphs are no-ops.  Test infrastructure only.
+#pragma once
+#include <cstdlib>
+#include <cstring>
+#include <cstdint>
+#include <cstdio>
+#define __host__
+#define __device__
+#define __global__
+#define __forceinline__ inline
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorNotReady = 600, hipErrorInvalidValue = 1 };
+typedef struct ihipStream_t* hipStream_t;
+typedef struct ihipEvent_t* hipEvent_t;
+typedef struct ihipGraph_t* hipGraph_t;
+typedef struct ihipGraphExec_t* hipGraphExec_t;
+typedef struct { int multiProcessorCount; } hipDeviceProp_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
+enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0, hipEventDisableTiming = 2, hipStreamCaptureModeThreadLocal = 1 };
+extern "C" {
+hipError_t hipMalloc(void** p, size_t n);
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t n, unsigned f);
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st);
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k);
+hipError_t hipStreamSynchronize(hipStream_t);
+hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
+hipError_t hipStreamDestroy(hipStream_t);
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned);
+hipError_t hipEventCreate(hipEvent_t*);
+hipError_t hipEventCreateWithFlags(hipEvent_t*, unsigned);
+hipError_t hipEventDestroy(hipEvent_t);
+hipError_t hipEventRecord(hipEvent_t, hipStream_t);
+hipError_t hipEventQuery(hipEvent_t);
+hipError_t hipEventSynchronize(hipEvent_t);
+hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
+hipError_t hipGetLastError();
+hipError_t hipSetDevice(int);
+hipError_t hipGetDeviceCount(int*);
+hipError_t hipGetDeviceProperties(hipDeviceProp_t*, int);
+hipError_t hipStreamBeginCapture(hipStream_t, int);
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t*);
+hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, void*, size_t);
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGraphExecDestroy(hipGraphExec_t);
+hipError_t hipGraphDestroy(hipGraph_t);
+}

@@ -1,0 +1,62 @@
+// Definitions of the HIP stand-in (tests/host/hip/hip_runtime.h) and of kernel launchers
+// that imitate the kernels' effect on the data the host reads back: moment tables are filled
+// with the molecule's atom count, a pair's energy is Q_A[0] + 1e-3 Q_B[0] (so every result
+// names the two fragments it was computed from), the eq. 2 test uses the radius the
+// statistics step reports.  Test infrastructure only.
+#include "hip/hip_runtime.h"
+#include <atomic>
+#include <random>
+#include <mutex>
+#include "tcm_runtime.h"
+static std::mutex g_mu;
+static std::mt19937 g_rng(1);
+extern "C" {
+hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); if (*p) memset(*p, 0xAB, n); return *p ? 0 : 2; }
+hipError_t hipFree(void* p) { free(p); return 0; }
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = malloc(n); return *p ? 0 : 2; }
+hipError_t hipHostFree(void* p) { free(p); return 0; }
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { memcpy(d, s, n); return 0; }
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { memcpy(d, s, n); return 0; }
+hipError_t hipStreamSynchronize(hipStream_t) { return 0; }
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = (hipStream_t)malloc(8); return 0; }
+hipError_t hipStreamDestroy(hipStream_t s) { free(s); return 0; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return 0; }
+hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t)calloc(1, 8); return 0; }
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)calloc(1, 8); return 0; }
+hipError_t hipEventDestroy(hipEvent_t e) { free(e); return 0; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { *(int*)e = 3; return 0; }
+// an event completes after a few queries: launches stay "in flight" for a while
+hipError_t hipEventQuery(hipEvent_t e) { std::lock_guard<std::mutex> g(g_mu); int* c = (int*)e; if (*c > 0 && (g_rng() % 2)) --*c; return *c > 0 ? hipErrorNotReady : 0; }
+hipError_t hipEventSynchronize(hipEvent_t e) { *(int*)e = 0; return 0; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.f; return 0; }
+hipError_t hipGetLastError() { return 0; }
+hipError_t hipSetDevice(int) { return 0; }
+hipError_t hipGetDeviceCount(int* n) { *n = 1; return 0; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) { p->multiProcessorCount = 4; return 0; }
+hipError_t hipStreamBeginCapture(hipStream_t, int) { return 0; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = (hipGraph_t)malloc(8); return 0; }
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t, void*, void*, size_t) { *e = (hipGraphExec_t)malloc(8); return 0; }
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return 0; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) { free(e); return 0; }
+hipError_t hipGraphDestroy(hipGraph_t g) { free(g); return 0; }
+}
+namespace tcm {
+// kernels: pairs write U = 1 + index and status OK; everything else is a no-op on data
+int num_blocks_for(int prec, int L) { return prec == TCM_F32C ? num_blocks(L, BUDGET_F32) : num_blocks(L, BUDGET_F64); }
+hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t) { memset(p, 0, n * 4); return 0; }
+hipError_t launch_stats(const DevPlan&, int, int, int, int, hipStream_t) { return 0; }
+hipError_t launch_stats_finalize(const DevPlan& P, int b, int e, hipStream_t) {
+    for (int m = b; m < e; ++m) { P.mols[m].meta[3] = 1.0; }
+    return 0; }
+hipError_t launch_moments_finalize(const DevPlan& P, int, hipStream_t) {
+    for (int m = 0; m < P.nmol; ++m) { const MolWork& w = P.mols[m];
+        for (int h = 0; h < nh(w.L); ++h) w.Q[h] = w.n; w.meta[3] = 0.5; }
+    return 0; }
+hipError_t launch_tiles(int, int, const DevPlan&, int, int, int, int, hipStream_t) { return 0; }
+hipError_t launch_pairs(const DevPlan& P, int, int b, int e, int, hipStream_t) {
+    for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; double s = w.QA[0] + 1e-3 * w.QB[0];
+        double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
+        if (!(w.flags & TCM_UNCHECKED) && !(R > w.metaA[3] + w.metaB[3])) { P.status[w.out] = TCM_EDOMAIN; P.U[w.out] = 0; }
+        else { P.status[w.out] = 0; P.U[w.out] = s; } }
+    return 0; }
+}

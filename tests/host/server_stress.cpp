@@ -1,0 +1,66 @@
+// Random request streams against the serving loop (compiled for the CPU with the HIP
+// stand-in) under tight HBM budgets: every ticket completes, every successful result names
+// the two fragments of its request, device memory never exceeds the budget.
+#include "tcm.h"
+#include <vector>
+#include <random>
+#include <cstdio>
+#include <thread>
+#include <chrono>
+#include <cmath>
+#include <map>
+int main(int argc, char** argv) {
+    int seeds = argc > 1 ? atoi(argv[1]) : 20;
+    for (int seed = 0; seed < seeds; ++seed) {
+        std::mt19937 rng(seed);
+        tcm_ctx* ctx; if (tcm_create(&ctx, 0, 0, 0)) return 1;
+        size_t used; tcm_mem_info(ctx, &used, nullptr);
+        int nfr = 12 + seed % 10;
+        std::vector<std::vector<double>> fr(nfr);
+        std::vector<int64_t> nat(nfr);
+        for (int f = 0; f < nfr; ++f) { nat[f] = 1 + rng() % 20000; fr[f].assign(4 * nat[f], 1.0); }
+        tcm_server_cfg cfg{1 + (int)(rng() % 4), 1 + (int)(rng() % 8), 64, 0};
+        if (tcm_server_start(ctx, &cfg)) return 2;
+        tcm_set_budget(ctx, used + 600000 + rng() % 2000000);
+        std::vector<uint64_t> tk; std::vector<int> fa, fb, Ls;
+        std::map<int64_t, int> seen;
+        int nreq = 300;
+        for (int i = 0; i < nreq; ++i) {
+            tcm_request r{}; int a = rng() % nfr, b = rng() % nfr;
+            r.key_a = a; r.key_b = b;
+            bool with_atoms = (rng() % 4) != 0;
+            for (int k = 0; k < 4; ++k) { r.atoms_a[k] = with_atoms ? fr[a].data() + k * nat[a] : nullptr; r.atoms_b[k] = with_atoms ? fr[b].data() + k * nat[b] : nullptr; }
+            r.n_a = nat[a]; r.n_b = nat[b];
+            r.R[0] = (rng() % 10 == 0) ? 0.1 : 100.0; r.quat_b[0] = 1; r.L = rng() % 33; r.precision = rng() % 2;
+            r.flags = (rng() % 3 == 0) ? TCM_BORROW_ATOMS : 0;
+            uint64_t t; int rc;
+            while ((rc = tcm_submit(ctx, &r, &t)) == TCM_EAGAIN) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            if (rc) { printf("submit rc %d\n", rc); return 3; }
+            tk.push_back(t); fa.push_back(a); fb.push_back(b); Ls.push_back(r.L);
+        }
+        int done = 0, bad = 0, nomem = 0, nf = 0, dom = 0;
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<char> got(nreq, 0);
+        while (done < nreq) {
+            for (int i = 0; i < nreq; ++i) {
+                if (got[i]) continue;
+                double U, lat; int32_t st;
+                int rc = tcm_poll(ctx, tk[i], &U, &st, &lat);
+                if (rc == TCM_OK) {
+                    got[i] = 1; ++done;
+                    if (st == TCM_OK) { double want = nat[fa[i]] + 1e-3 * nat[fb[i]]; if (std::fabs(U - want) > 1e-9 * want) { ++bad; if (bad < 5) printf("bad i=%d a=%d(n=%ld) b=%d(n=%ld) U=%.6f want=%.6f L=%d\n", i, fa[i], (long)nat[fa[i]], fb[i], (long)nat[fb[i]], U, want, Ls[i]); } }
+                    else if (st == TCM_ENOMEM) ++nomem; else if (st == TCM_ENOTFOUND) ++nf; else if (st == TCM_EDOMAIN) ++dom; else ++bad;
+                } else if (rc != TCM_EAGAIN) { printf("poll rc %d\n", rc); return 4; }
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(20)) { printf("seed %d: stuck at %d/%d\n", seed, done, nreq); return 5; }
+        }
+        int64_t c, l, h, m, d, e; tcm_server_stats(ctx, &c, &l, &h, &m, &d, &e);
+        size_t u2, b2; tcm_mem_info(ctx, &u2, &b2);
+        printf("seed %d: done %d bad %d nomem %d notfound %d edomain %d | launches %lld hits %lld misses %lld deferred %lld evictions %lld | used %zu <= budget %zu %s\n",
+               seed, done, bad, nomem, nf, dom, (long long)l, (long long)h, (long long)m, (long long)d, (long long)e, u2, b2, u2 <= b2 ? "ok" : "OVER");
+        tcm_server_stop(ctx);
+        tcm_destroy(ctx);
+        if (bad) return 6;
+    }
+    return 0;
+}

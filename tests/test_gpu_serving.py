@@ -93,15 +93,21 @@ def test_alone_vs_mix(synth):
 
 def test_admission_under_small_budget(synth, orc):
     F = frags(synth)
-    big = max(f["n"] for f in F)
-    # room for roughly three of the larger fragments plus workspaces
-    budget = 16 * 2**20 + 3 * 40 * big
-    with tcm.Context(0, hbm_budget_bytes=budget) as c:
+    total_atoms = 32 * sum(f["n"] for f in F)
+    largest_pair = 32 * (F[5]["n"] + F[3]["n"])
+    with tcm.Context(0) as c:
         tcm.tcm_server_start(c.h, max_inflight_batches=2, max_batch_pairs=2, queue_capacity=64)
+        run_all(c.h, [request(F, 2, 6, 8, with_atoms=True)])            # arena and workspaces
+        used, _ = tcm.tcm_mem_info(c.h)
+        # room for the largest pair plus a little, well below all fragments together
+        budget = used + largest_pair + (total_atoms - largest_pair) // 4
+        tcm.tcm_set_budget(c.h, budget)
         pairs = [(i % 8, (i * 3 + 1) % 8, 8 + (i % 3) * 4) for i in range(16)]
         out = run_all(c.h, [request(F, a, b, L) for a, b, L in pairs])
         stats = tcm.tcm_server_stats(c.h)
+        used_after, _ = tcm.tcm_mem_info(c.h)
         tcm.tcm_server_stop(c.h)
+    assert used_after <= budget
     assert all(st == 0 for _, st, _ in out), [st for _, st, _ in out]
     assert stats["evictions"] > 0
     # spot-check one result against the oracle
@@ -115,8 +121,11 @@ def test_admission_under_small_budget(synth, orc):
 
 def test_request_larger_than_budget_fails_alone(synth):
     F = frags(synth)
-    with tcm.Context(0, hbm_budget_bytes=8 * 2**20) as c:
+    with tcm.Context(0) as c:
         tcm.tcm_server_start(c.h, max_inflight_batches=1, max_batch_pairs=4, queue_capacity=16)
+        run_all(c.h, [request(F, 2, 6, 8)])
+        used, _ = tcm.tcm_mem_info(c.h)
+        tcm.tcm_set_budget(c.h, used + 4 * 2**20)
         import torch
         xyz, q, _ = synth.chain(1, 1, 300_000)                 # 9.6 MB of atoms: cannot fit
         t = torch.tensor(np.vstack([xyz.T, q[None, :]]), dtype=torch.float64, device="cuda").contiguous()
