@@ -241,7 +241,10 @@ int tcm_poll(tcm_ctx *ctx, uint64_t ticket, double *U_out, int32_t *status_out,
  * free the server's cache. */
 int tcm_server_stop(tcm_ctx *ctx);
 /* Counters since start: completed requests, launches, fragment cache hits / misses,
- * admissions deferred (memory, or a fragment still in flight), evictions. */
+ * requests that had to wait at least once (memory, or a fragment still in flight), fragments
+ * evicted.  A request is admitted with both of its fragments or waits without fetching
+ * either, so every evicted fragment had been fetched by an admitted request
+ * (evictions <= cache_misses). */
 int tcm_server_stats(tcm_ctx *ctx, int64_t *completed, int64_t *launches, int64_t *cache_hits,
                      int64_t *cache_misses, int64_t *deferred, int64_t *evictions);
 

@@ -6,7 +6,8 @@
 //   2. while a launch slot is free and requests are pending: admit requests in arrival order
 //      into a batch -- a fragment that is resident is a cache hit; a new fragment is copied
 //      into server-owned device memory after HBM admission (LRU eviction of idle fragments
-//      when the context's budget would be exceeded; requests that still do not fit wait);
+//      when the context's budget would be exceeded; a request is admitted whole -- both of
+//      its fragments -- or waits, and a waiting request fetches nothing);
 //      a request whose fragment is being computed by an in-flight launch waits for it;
 //   3. launch the batch on the slot's own stream (statistics, per-order tile kernels, pair
 //      kernel -- the same kernels as tcm_batch_energy) followed by asynchronous copies of the
@@ -44,6 +45,7 @@ struct SReq {
     uint64_t ticket;
     tcm_request r;
     clock_t_::time_point t_submit;
+    bool waited = false;           // counted once in the deferred statistic
 };
 
 struct SResult {
@@ -121,31 +123,52 @@ static bool take_slot(Server* S, SMol* m)
     return true;
 }
 
-// Device bytes a new fragment needs from the budget: its atoms when copied (moment slots
-// come from the arena, charged when a chunk is added).
+// Device bytes a new fragment takes from the budget: its copied atoms (moment tables live in
+// the arena, charged when a chunk is added).
 static size_t mol_bytes(int64_t n, bool borrow)
 {
-    return borrow ? 0 : sizeof(double) * 4 * (size_t)(n > 0 ? n : 1) + sizeof(double) * ARENA_SLOT;
+    if (borrow) return 0;
+    const size_t b = sizeof(double) * 4 * (size_t)(n > 0 ? n : 1);
+    return b < 256 ? 256 : b;      // the allocator's minimum
 }
 
+static bool evictable(const SMol* m) { return m->refs == 0 && m->pin == 0 && !m->busy; }
+
 // Evict idle fragments (least recently used first) until `need` more bytes fit the budget.
+// Evicts nothing when even evicting every idle fragment would not make enough room.
 static bool make_room(Server* S, size_t need)
 {
     Ctx* c = S->c;
-    if (!c->budget) return true;
+    const size_t budget = c->budget;
+    if (!budget) return true;
+    if (c->used.load() + need <= budget) return true;
+    size_t idle = 0;
+    for (auto& kv : S->cache)
+        if (evictable(kv.second.get())) idle += kv.second->atoms.cap;
+    const size_t used = c->used.load();
+    if (used + need > budget + idle) return false;
     auto it = S->lru.end();
-    while (c->used.load() + need > c->budget && it != S->lru.begin()) {
+    while (c->used.load() + need > budget && it != S->lru.begin()) {
         --it;
         auto f = S->cache.find(*it);
         SMol* m = f->second.get();
-        if (m->refs == 0 && m->pin == 0 && !m->busy) {
+        if (evictable(m)) {
             free_mol(S, m);
             it = S->lru.erase(it);
             S->cache.erase(f);
             ++S->evictions;
         }
     }
-    return c->used.load() + need <= c->budget;
+    return c->used.load() + need <= budget;
+}
+
+// Remove a fragment created by the current admission pass that will not be used.
+static void destroy_mol(Server* S, SMol* m)
+{
+    const int64_t key = m->key;
+    free_mol(S, m);
+    S->lru.erase(m->lru);
+    S->cache.erase(key);
 }
 
 static void touch(Server* S, SMol* m)
@@ -207,28 +230,41 @@ static void admit_and_launch(Server* S, Slot& sl)
     std::vector<SReq> batch;
     std::vector<int32_t> pre;
     std::deque<SReq> keep;
-    auto get = [&](int64_t key, const double* const atoms[4], int64_t n, int L, int prec, int flags,
-                   int* status) -> SMol* {
+    // Resolve one side of a request without side effects: a resident fragment, a new one to
+    // fetch (fresh), or a status (TCM_EAGAIN: wait for an in-flight launch; TCM_ENOTFOUND).
+    struct Side {
+        SMol* m = nullptr;
+        bool fresh = false;
+        int status = TCM_OK;
+    };
+    auto look = [&](int64_t key, const double* const atoms[4], int64_t n, int L) -> Side {
+        Side sd;
         auto f = S->cache.find(key);
         if (f != S->cache.end()) {
             SMol* m = f->second.get();
-            if (m->busy) { *status = TCM_EAGAIN; return nullptr; }       // wait for the launch
+            if (m->busy) { sd.status = TCM_EAGAIN; return sd; }          // being computed
             auto nd = need.find(m);
             const bool recompute = m->Lcached < L && (nd == need.end() || nd->second < L);
             // an in-flight launch still reads this table: do not rewrite it
-            if (recompute && m->refs > 0) { *status = TCM_EAGAIN; return nullptr; }
-            return m;
+            if (recompute && m->refs > 0) { sd.status = TCM_EAGAIN; return sd; }
+            sd.m = m;
+            return sd;
         }
         const bool has = atoms[0] && atoms[1] && atoms[2] && atoms[3];
-        if (!(has || n == 0)) { *status = TCM_ENOTFOUND; return nullptr; }
-        const bool borrow = (flags & TCM_BORROW_ATOMS) != 0;
-        if (!make_room(S, mol_bytes(n, borrow))) { *status = TCM_EAGAIN; return nullptr; }
+        if (!(has || n == 0)) { sd.status = TCM_ENOTFOUND; return sd; }
+        sd.fresh = true;
+        return sd;
+    };
+    // Create a fragment whose device bytes have been admitted; its atoms are copied on the
+    // launch stream of this batch, ahead of the kernels that read them.
+    auto create = [&](int64_t key, const double* const atoms[4], int64_t n, int prec, int flags,
+                      int* status) -> SMol* {
         auto m = std::make_unique<SMol>();
         m->key = key;
         m->n = n;
         m->prec = prec;
         if (!take_slot(S, m.get())) { *status = TCM_EAGAIN; return nullptr; }
-        if (borrow) {
+        if (flags & TCM_BORROW_ATOMS) {
             for (int k = 0; k < 4; ++k) m->src[k] = atoms[k];
         } else {
             if (c->alloc(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1)) != TCM_OK) {
@@ -250,20 +286,55 @@ static void admit_and_launch(Server* S, Slot& sl)
         S->cache[key] = std::move(m);
         return raw;
     };
+    // Admit one request: both fragments resident or fetched, or nothing changes.
+    auto admit = [&](const tcm_request& r, SMol** pa, SMol** pb) -> int {
+        const bool same = r.key_b == r.key_a;
+        Side sa = look(r.key_a, r.atoms_a, r.n_a, r.L);
+        Side sb = same ? sa : look(r.key_b, r.atoms_b, r.n_b, r.L);
+        if (sa.status == TCM_ENOTFOUND || sb.status == TCM_ENOTFOUND) return TCM_ENOTFOUND;
+        if (sa.status != TCM_OK || sb.status != TCM_OK) return TCM_EAGAIN;
+        const bool borrow = (r.flags & TCM_BORROW_ATOMS) != 0;
+        const int nfresh = (sa.fresh ? 1 : 0) + (sb.fresh && !same ? 1 : 0);
+        size_t bytes = (sa.fresh ? mol_bytes(r.n_a, borrow) : 0) + (sb.fresh && !same ? mol_bytes(r.n_b, borrow) : 0);
+        if ((int)S->free_slots.size() < nfresh) bytes += sizeof(double) * ARENA_SLOT * ARENA_CHUNK;
+        if (bytes) {
+            // resident sides of this request must survive the eviction
+            if (sa.m) ++sa.m->pin;
+            if (sb.m) ++sb.m->pin;
+            const bool ok = make_room(S, bytes);
+            if (sa.m) --sa.m->pin;
+            if (sb.m) --sb.m->pin;
+            if (!ok) return TCM_EAGAIN;
+        }
+        int st = TCM_OK;
+        SMol* a = sa.m;
+        if (sa.fresh && !(a = create(r.key_a, r.atoms_a, r.n_a, r.precision, r.flags, &st))) return st;
+        SMol* b = same ? a : sb.m;
+        if (sb.fresh && !same) {
+            ++a->pin;
+            b = create(r.key_b, r.atoms_b, r.n_b, r.precision, r.flags, &st);
+            --a->pin;
+            if (!b) {
+                if (sa.fresh) destroy_mol(S, a);      // no copy may outlive a deferred request
+                return st;
+            }
+        }
+        *pa = a;
+        *pb = b;
+        return TCM_OK;
+    };
     const int maxp = S->cfg.max_batch_pairs > 0 ? S->cfg.max_batch_pairs : 64;
     while (!S->pending.empty() && (int)batch.size() < maxp) {
         SReq q = S->pending.front();
         S->pending.pop_front();
         const tcm_request& r = q.r;
-        int sa = TCM_OK, sb = TCM_OK;
-        SMol* a = get(r.key_a, r.atoms_a, r.n_a, r.L, r.precision, r.flags, &sa);
-        if (a) ++a->pin;                   // fetching b must not evict a
-        SMol* b = a ? get(r.key_b, r.atoms_b, r.n_b, r.L, r.precision, r.flags, &sb) : nullptr;
-        if (a) --a->pin;
-        if (!a || !b) {
-            const int st = !a ? sa : sb;
+        SMol* a = nullptr;
+        SMol* b = nullptr;
+        const int st = admit(r, &a, &b);
+        if (st != TCM_OK) {
             if (st == TCM_EAGAIN) {
-                ++S->deferred;
+                if (!q.waited) ++S->deferred;
+                q.waited = true;
                 keep.push_back(q);
                 continue;
             }

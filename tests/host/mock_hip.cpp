@@ -9,7 +9,8 @@
 #include <mutex>
 #include "tcm_runtime.h"
 static std::mutex g_mu;
-static std::mt19937 g_rng(1);
+static std::mt19937 g_rng(getenv("MOCK_SEED") ? atoi(getenv("MOCK_SEED")) : 1);
+static const int g_delay = getenv("MOCK_DELAY") ? atoi(getenv("MOCK_DELAY")) : 3;
 extern "C" {
 hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); if (*p) memset(*p, 0xAB, n); return *p ? 0 : 2; }
 hipError_t hipFree(void* p) { free(p); return 0; }
@@ -24,7 +25,7 @@ hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return 0; }
 hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t)calloc(1, 8); return 0; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)calloc(1, 8); return 0; }
 hipError_t hipEventDestroy(hipEvent_t e) { free(e); return 0; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { *(int*)e = 3; return 0; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { *(int*)e = g_delay; return 0; }
 // an event completes after a few queries: launches stay "in flight" for a while
 hipError_t hipEventQuery(hipEvent_t e) { std::lock_guard<std::mutex> g(g_mu); int* c = (int*)e; if (*c > 0 && (g_rng() % 2)) --*c; return *c > 0 ? hipErrorNotReady : 0; }
 hipError_t hipEventSynchronize(hipEvent_t e) { *(int*)e = 0; return 0; }

@@ -61,6 +61,7 @@ int main(int argc, char** argv) {
         tcm_server_stop(ctx);
         tcm_destroy(ctx);
         if (bad) return 6;
+        if (e > m) { printf("seed %d: %lld evictions > %lld misses (fragments fetched and dropped)\n", seed, (long long)e, (long long)m); return 7; }
     }
     return 0;
 }
