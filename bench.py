@@ -25,10 +25,33 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the moment pass comes from rocprofv3 counter runs, summarised in this file
+# together with the SHA-256 of every source the tile kernels are built from; it is reported
+# only while those sources are unchanged
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_uneven_batch_1024.md")
+TILE_SOURCES = ["paper_0704_1672_amd/csrc/tcm_device.h", "paper_0704_1672_amd/csrc/tcm_internal.h"] + \
+               [f"paper_0704_1672_amd/csrc/tcm_tiles_f32_{k}.hip" for k in "abcd"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_tile_traffic():
+    """Bytes per step of the tile launches from the committed counter summary, or None when
+    it is missing or the tile kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    for path in TILE_SOURCES:
+        digest = hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest()
+        if f"{digest}  {path}" not in text:
+            return None
+    m = re.search(r"tile_traffic_bytes_per_step:\s*([0-9]+)", text)
+    return int(m.group(1)) if m else None
 
 
 def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, fractions=(0.5, 0.9)):
@@ -249,23 +272,32 @@ def main():
             tuned[f"L{L}/2^{b}"] = k
     log(f"bench: autotuned {len(tuned)} (L, size) buckets in {time.time() - t_tune:.1f}s: {tuned}")
     req = tcm.make_requests(ids[0::2], ids[1::2], w["R"], w["L"], w["quats"])
-    plan = tcm.tcm_plan_create(ctx.h, req, use_graph=True)
+    plan = tcm.tcm_plan_create(ctx.h, req, use_graph=True)           # serial order, one graph
+    plan_s = tcm.tcm_plan_create(ctx.h, req, use_graph=False)        # per-L branches on streams
     info = tcm.tcm_plan_info(plan)
     log(f"bench: plan: {info}")
 
-    for _ in range(args.warmup):
-        tcm.tcm_plan_run(ctx.h, plan)
-    torch.cuda.synchronize()
-    stream.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        tcm.tcm_plan_run(ctx.h, plan)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
-    ms_step = 1e3 * elapsed / args.steps
+    def timed(p):
+        for _ in range(args.warmup):
+            tcm.tcm_plan_run(ctx.h, p)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            tcm.tcm_plan_run(ctx.h, p)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t1) / args.steps
+
+    ms_graph = timed(plan)
     U, st = tcm.tcm_plan_results(ctx.h, plan, args.npairs)
-    log(f"bench: {args.steps} graph replays, {ms_step:.3f} ms/step, statuses ok: {int(np.sum(st == 0))}")
+    ms_streams = timed(plan_s)
+    Us, sts = tcm.tcm_plan_results(ctx.h, plan_s, args.npairs)
+    assert np.array_equal(U, Us) and np.array_equal(st, sts), "graph and stream runs differ"
+    mode = "graph" if ms_graph <= ms_streams else "streams"
+    ms_step = min(ms_graph, ms_streams)
+    log(f"bench: {args.steps} steps: graph replay {ms_graph:.3f} ms/step, direct launches on forked streams "
+        f"{ms_streams:.3f} ms/step; statuses ok: {int(np.sum(st == 0))}")
 
     # per-kernel durations: HIP events on the launch stream around each phase
     phases = np.array([tcm.tcm_plan_run_timed(ctx.h, plan) for _ in range(max(3, args.steps))])
@@ -316,6 +348,7 @@ def main():
         log(f"bench: oracle sample {k} pairs in {t_cpu:.1f}s; max rel err {err['max_rel']:.2e}")
 
     tcm.tcm_plan_destroy(plan)
+    tcm.tcm_plan_destroy(plan_s)
     ctx.close()
     del soa
     torch.cuda.empty_cache()
@@ -344,8 +377,12 @@ def main():
                    "geometry": "excluded-volume random-walk chains, q~N(0,0.3) zero net charge, "
                                "R0 = 1.5(a_A+a_B), random pose of B",
                    "precision": "moments FP32 compensated; rotation, geometric factors, contraction FP64",
-                   "execution": "one HIP graph replay per step: per-L (statistics -> tiles) branches on "
-                                "forked streams, moment finalisation, pair kernel",
+                   "execution": ("one HIP graph replay per step (serial order: one statistics launch, "
+                                 "centre/scale, one persistent tile launch per L, moment finalisation, pair "
+                                 "kernel)" if mode == "graph" else
+                                 "direct launches per step: per-L (statistics -> centre/scale -> tiles) "
+                                 "branches on forked streams, then moment finalisation and pair kernel"),
+                   "ms_per_step_graph": ms_graph, "ms_per_step_streams": ms_streams,
                    "tile_autotune": tuned,
                    "parallelism": "single GPU", "seed": 4},
         "latency_ms": {"p50": ms_step, "p99": ms_step,
@@ -353,8 +390,10 @@ def main():
         "rel_err": err,
         "phase_ms": {"stats": ph[0], "moment_tiles": ph[1], "moment_finalise": ph[2], "pairs": ph[3]},
         "roofline": {"bound": "alu", "achieved": moment_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": moment_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "moment-pass tile kernels (FP32), 6(L+1)(L+2) flops per atom"},
+                     "unit": "TFLOP/s", "frac": moment_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_tile_traffic(),
+                     "kernel": "moment-pass tile kernels (FP32), 6(L+1)(L+2) flops per atom; achieved and "
+                               "traffic are per step (one launch of tcm_tiles<float, L> per order L)"},
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -149,14 +149,19 @@ typedef struct {
 int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *U_out,
                      int32_t *status_out);
 
-/* Plan a batch once and capture its launches in a HIP graph; tcm_plan_run replays it on
- * the context's stream (asynchronous: outputs stay on the device until tcm_plan_results).
- * The plan recomputes every moment the batch needs on each run (no TCM_REUSE). */
+/* Plan a batch once.  use_graph != 0: its launches are captured in a HIP graph in serial
+ * order (one statistics launch for the whole batch, centre/scale, the tile launch of each
+ * (precision, L) group, moment finalisation, pairs) and tcm_plan_run replays the graph;
+ * use_graph == 0: tcm_plan_run issues the launches directly, each (precision, L) group's
+ * statistics and tiles on its own forked stream so that groups overlap.  Either way the run
+ * is asynchronous on the context's stream (outputs stay on the device until
+ * tcm_plan_results), every moment the batch needs is recomputed (no TCM_REUSE), and the
+ * results are identical bit for bit. */
 int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
                     tcm_plan **plan_out);
 int tcm_plan_run(tcm_ctx *ctx, tcm_plan *plan);
-/* The same launches issued directly instead of through the graph; results are identical
- * bit for bit. */
+/* The serial-order launches issued directly (no graph); results are identical bit for
+ * bit. */
 int tcm_plan_run_phased(tcm_ctx *ctx, tcm_plan *plan);
 /* One synchronous run with HIP events recorded on the launch stream between its steps;
  * ms_out[4] receives the elapsed milliseconds of (statistics + centre/scale), (moment
@@ -177,10 +182,11 @@ void tcm_plan_destroy(tcm_plan *plan);
 /* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */
 int tcm_tune_get(tcm_ctx *ctx, int precision, int L, int64_t n, int *kper_out);
 int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);
-/* Autotuner: time the moment-tile kernels for every candidate kper (4..128) on a synthetic
- * batch of copies of an n-atom molecule large enough to fill the device, and keep the
- * fastest for (precision, L, n's power-of-two size bucket).  best_ms_out (may be NULL): the
- * winner's tile time per molecule, in ms. */
+/* Autotuner: time the moment-tile kernels for every candidate kper (8..256, powers of two)
+ * on a synthetic batch of copies of an n-atom molecule (at least 64M atoms, or 4096 copies)
+ * so that every candidate runs many waves of items, and keep the fastest for (precision, L,
+ * n's power-of-two size bucket).  best_ms_out (may be NULL): the winner's tile time per
+ * molecule, in ms.  Device memory for the synthetic batch comes from the context's budget. */
 int tcm_autotune(tcm_ctx *ctx, int precision, int L, int64_t n, int *best_kper_out,
                  double *best_ms_out);
 /* Persist / restore the tuning table (text file). */

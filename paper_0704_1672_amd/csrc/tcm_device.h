@@ -23,6 +23,8 @@
 // Device code of the moment pass (a1) and its fixed-order finalisation (a2), shared by the
 // per-(precision, L) tile translation units.
 #pragma once
+#include <atomic>
+
 #include "tcm.h"
 #include "tcm_internal.h"
 
@@ -158,6 +160,9 @@ __device__ __forceinline__ void atom_block(F* acc, F c, F ur, F ui, F r, F q)
     w[0] = q;
 #pragma unroll
     for (int l = 1; l <= L; ++l) w[l] = w[l - 1] * r;
+    // u^M0 by successive products, the same sequence the chains use from one m to the next:
+    // every T_mm is then the same rounded value whatever the m-block partition, so a
+    // molecule's moments up to order l do not depend on the order L it is computed at
     F sr = (F)1, si = (F)0;
 #pragma unroll
     for (int m = 1; m <= M0; ++m) {
@@ -170,8 +175,7 @@ __device__ __forceinline__ void atom_block(F* acc, F c, F ur, F ui, F r, F q)
 
 // ------------------------------------------------------------------ shared memory
 // One static buffer, reused by every item kind (a workgroup runs one item at a time).
-constexpr int SMEM_BYTES = 56 * 1024;        // statistics and pair kernels
-constexpr int TILE_SMEM_BYTES = 37 * 1024;   // tile kernels (transposed reductions)
+constexpr int TILE_SMEM_BYTES = 37 * 1024;   // tile kernels: transposed reductions
 constexpr int RED_COLS_F32 = 32;             // columns per transpose-reduction chunk
 constexpr int RED_COLS_F64 = 16;
 
@@ -263,22 +267,43 @@ __device__ __forceinline__ void reduce_write_f64(const double* acc, char* smem, 
     }
 }
 
-// Per-atom prologue shared by both precisions: FP64 centring and scaling, |r|^2 in FP64.
+// Atom loads.  Each tile reads its atoms through buffer descriptors based at the tile's first
+// atom with the tile's byte length as the range, so offsets are 32-bit and a read past the
+// tile's end returns 0 instead of touching memory (the indices are also clamped).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;       // raw 32-bit access, gfx9 family
+
+// The arguments are wavefront-uniform (one molecule per workgroup item); reading them
+// through readfirstlane keeps the descriptor in scalar registers.
+__device__ __forceinline__ rsrc_t tile_rsrc(const double* base, int64_t first, uint32_t bytes)
+{
+    const uint64_t a = (uint64_t)(base + first);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(bytes);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, (int)nb, RSRC_WORD3);
+}
+
+__device__ __forceinline__ double bload(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 struct AtomIn {
     double x, y, z, q;
 };
 
-typedef __attribute__((address_space(1))) const double gdouble;
+struct TileSrc {
+    rsrc_t x, y, z, q;
+};
 
-__device__ __forceinline__ double gload(const double* p, int64_t i) { return ((gdouble*)p)[i]; }
-
-__device__ __forceinline__ AtomIn load_atom(const MolWork& mw, int64_t a)
+__device__ __forceinline__ AtomIn load_atom(const TileSrc& t, uint32_t off)
 {
     AtomIn v;
-    v.x = gload(mw.x, a);
-    v.y = gload(mw.y, a);
-    v.z = gload(mw.z, a);
-    v.q = gload(mw.q, a);
+    v.x = bload(t.x, off);
+    v.y = bload(t.y, off);
+    v.z = bload(t.z, off);
+    v.q = bload(t.q, off);
     return v;
 }
 
@@ -291,26 +316,40 @@ __device__ __forceinline__ void tile_item(const TileCtx& tc, const DevPlan& P, c
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = (F)0;
     const int tid = threadIdx.x;
-    const int64_t base = (int64_t)tc.tile * WG * mw.kper + tid;
+    // the tile: atoms [first, first + span) of the molecule, thread tid takes first + tid,
+    // first + tid + WG, ...
+    const int64_t first = (int64_t)tc.tile * WG * mw.kper;
+    const int span = (int)min(mw.n - first, (int64_t)WG * mw.kper);
+    const uint32_t bytes = (uint32_t)span * 8u;
+    TileSrc src;
+    src.x = tile_rsrc(mw.x, first, bytes);
+    src.y = tile_rsrc(mw.y, first, bytes);
+    src.z = tile_rsrc(mw.z, first, bytes);
+    src.q = tile_rsrc(mw.q, first, bytes);
+    const double cxs = tc.cx * tc.inv_s, cys = tc.cy * tc.inv_s, czs = tc.cz * tc.inv_s;
     double r2max = 0.0;
-    // atoms of this thread: base, base + WG, ... (at most kper, all < n)
-    const int64_t left = mw.n - base;
-    const int cnt = left <= 0 ? 0 : (int)min((int64_t)mw.kper, (left + WG - 1) / WG);
+    const int cnt = tid < span ? (span - tid + WG - 1) / WG : 0;
     if (cnt > 0) {
-        // two atoms in flight ahead of the one being evaluated; indices past the thread's
-        // last atom are clamped to it (valid memory, values unused)
-        const int64_t last = base + (int64_t)(cnt - 1) * WG;
-        AtomIn n0 = load_atom(mw, base);
-        AtomIn n1 = load_atom(mw, min(base + WG, last));
-        int64_t a2 = base + 2 * WG;
+        // two atoms in flight ahead of the one being evaluated; offsets past the thread's
+        // last atom are clamped to it (values unused)
+        const uint32_t last = (uint32_t)(tid + (cnt - 1) * WG) * 8u;
+        uint32_t o = (uint32_t)tid * 8u;
+        AtomIn n0 = load_atom(src, o);
+        AtomIn n1 = load_atom(src, min(o + WG * 8u, last));
+        o += 2 * WG * 8u;
         for (int i = 0; i < cnt; ++i) {
             const AtomIn cur = n0;
             n0 = n1;
-            n1 = load_atom(mw, min(a2, last));
-            a2 += WG;
-            const double dx = cur.x - tc.cx, dy = cur.y - tc.cy, dz = cur.z - tc.cz;
-            r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
-            const F px = (F)(dx * tc.inv_s), py = (F)(dy * tc.inv_s), pz = (F)(dz * tc.inv_s);
+            n1 = load_atom(src, min(o, last));
+            o += WG * 8u;
+            if constexpr (M0 == 0) {               // max |r - c|^2 in FP64, once per atom
+                const double dx = cur.x - tc.cx, dy = cur.y - tc.cy, dz = cur.z - tc.cz;
+                r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
+            }
+            // centred and scaled in FP64 (one rounding), then cast
+            const F px = (F)fma(cur.x, tc.inv_s, -cxs);
+            const F py = (F)fma(cur.y, tc.inv_s, -cys);
+            const F pz = (F)fma(cur.z, tc.inv_s, -czs);
             const F r2 = px * px + py * py + pz * pz;
             F ir, r;
             if constexpr (sizeof(F) == 4) {
@@ -331,7 +370,7 @@ __device__ __forceinline__ void tile_item(const TileCtx& tc, const DevPlan& P, c
     } else {
         reduce_write_f64<NA>(acc, smem, L, M0, P.part_d + mw.part_off + (int64_t)tc.tile * nh(L));
     }
-    if (tc.blk == 0) {                                   // max |r|^2 of the tile (FP64)
+    if constexpr (M0 == 0) {                       // max |r|^2 of the tile (FP64)
         double* red = reinterpret_cast<double*>(smem);
         red[tid] = r2max;
         __syncthreads();
@@ -416,18 +455,11 @@ __device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j
     dispatch_block<F, L, 0>(tc, P, smem);
 }
 
-__device__ __forceinline__ int find_owner(const int32_t* prefix, int n, int item)
-{
-    int lo = 0, hi = n;                        // prefix[lo] <= item < prefix[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Persistent kernel over the tile items [begin, end) of the molecules of one (precision, L)
-// group.  Workgroups claim items from queue[slot] until the range is exhausted.
+// group.  Workgroups claim items from queue[slot] until the range is exhausted; the items
+// come in decreasing cost, so the last ones to start are the cheapest (a short tail).  The
+// order does not touch any result: each item writes its own partial slot and the partials
+// are merged in tile order afterwards.
 template <typename F, int L>
 __global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int slot, int begin, int end)
 {
@@ -437,19 +469,41 @@ __global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int slot, int begin, 
     for (;;) {
         if (tid == 0) s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: descriptors in SGPRs
         __syncthreads();
         if (item >= end) break;
         const int j = item - P.n_stats;
-        const int mol = find_owner(P.tile_prefix, P.nmol, j);
-        tile_item_entry<F, L>(P, mol, j - P.tile_prefix[mol], smem);
+        const int mol = __builtin_amdgcn_readfirstlane(P.tile_items[2 * j]);
+        tile_item_entry<F, L>(P, mol, __builtin_amdgcn_readfirstlane(P.tile_items[2 * j + 1]), smem);
         __syncthreads();
     }
 }
 
-#define TCM_TILE_CASE(F, LL)                                                                   \
-    case LL:                                                                                   \
-        hipLaunchKernelGGL((tcm_tiles<F, LL>), dim3(grid), dim3(WG), 0, s, P, slot, begin, end); \
-        break;
+// Launch the persistent tile kernel of (F, L) with as many workgroups as can be resident
+// (occupancy x compute units), capped by the number of items.
+template <typename F, int L>
+hipError_t launch_tile_kernel(const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
+{
+    static std::atomic<int> per_cu{0};
+    int k = per_cu.load(std::memory_order_relaxed);
+    if (k == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tcm_tiles<F, L>, WG, 0) == hipSuccess && nb > 0) {
+            k = nb;
+            per_cu.store(k, std::memory_order_relaxed);
+        } else {
+            (void)hipGetLastError();
+            k = 2;
+        }
+    }
+    int grid = k * num_cu;
+    if (grid > end - begin) grid = end - begin;
+    hipLaunchKernelGGL((tcm_tiles<F, L>), dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    return hipGetLastError();
+}
+
+#define TCM_TILE_CASE(F, LL) \
+    case LL:                 \
+        return launch_tile_kernel<F, LL>(P, slot, begin, end, num_cu, s);
 
 }  // namespace tcm

@@ -16,7 +16,7 @@ namespace tcm {
 
 constexpr int LMAX = 32;           // largest multipole order the library accepts
 constexpr int WG = 256;            // threads per workgroup (4 wave64s)
-constexpr int STATS_PER_THREAD = 32;
+constexpr int STATS_PER_THREAD = 8;
 constexpr int STATS_CHUNK = WG * STATS_PER_THREAD;   // atoms per STATS item
 
 __host__ __device__ constexpr int nh(int L) { return (L + 1) * (L + 1); }
@@ -63,10 +63,13 @@ struct PairWork {
 struct DevPlan {
     const MolWork* mols;
     const PairWork* pairs;
-    const int32_t* stats_prefix;   // nmol+1 cumulative STATS items
-    const int32_t* tile_prefix;    // nmol+1 cumulative TILE items (ntiles * nblk)
+    const int32_t* stats_items;    // [n_stats][2]: (molecule, chunk) of each STATS item
+    const int32_t* tile_items;     // [n_tiles][2]: (molecule, tile * nblk + m-block) of each
+                                   // TILE item, each group's items in decreasing cost
     int32_t nmol;
-    int32_t npairs;
+    int32_t npairs;                // pairs are listed in decreasing cost (largest L first)
+    int32_t pair_lmax;             // largest L of the pairs (sizes the pair kernel's LDS)
+    int32_t pad1;
     int32_t n_stats;
     int32_t n_tiles;
     // claim counters of the run's launches, cleared before each run by a fill kernel
@@ -84,7 +87,6 @@ struct DevPlan {
     const double* invk;            // 1/k_lm of the normalised recurrence, per packed index
     const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
     const double* rot;             // rotation tables: for each l, D then D^{-1}, (2l+1)^2 each
-    int64_t spin_limit;            // bound on every device-side wait
 };
 
 // Packed index helpers (layout of every moment table at the boundary):

@@ -4,35 +4,90 @@
 namespace tcm {
 
 // ------------------------------------------------------------------ STATS items
-// Partial sums of x, y, z and the bounding box of one chunk of atoms (HBM bound: 24 B/atom).
-// Loads are issued STATS_UNROLL at a time so that each thread keeps several in flight.
-constexpr int STATS_UNROLL = 8;
+// Partial sums of x, y, z and the bounding box of one chunk of STATS_CHUNK atoms (HBM bound:
+// 24 B/atom).  Every thread issues the loads of all its STATS_PER_THREAD atoms at once; the
+// chunk's nine values are reduced within each wavefront by shuffles and across the four
+// wavefronts in a fixed order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
 
 __device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk, char* smem)
 {
     const MolWork& mw = P.mols[mol];
     const int tid = threadIdx.x;
+    const int64_t first = (int64_t)chunk * STATS_CHUNK;
+    const int span = (int)min(mw.n - first, (int64_t)STATS_CHUNK);
+    const uint32_t bytes = (uint32_t)span * 8u;
+    const rsrc_t rx = tile_rsrc(mw.x, first, bytes), ry = tile_rsrc(mw.y, first, bytes),
+                 rz = tile_rsrc(mw.z, first, bytes);
+    double x[STATS_PER_THREAD], y[STATS_PER_THREAD], z[STATS_PER_THREAD];
+    const uint32_t last = span > 0 ? (uint32_t)(span - 1) * 8u : 0u;
+#pragma unroll
+    for (int j = 0; j < STATS_PER_THREAD; ++j) {     // past the chunk's end: clamped, masked below
+        const uint32_t off = min((uint32_t)(tid + j * WG) * 8u, last);
+        x[j] = span > 0 ? bload(rx, off) : 0.0;
+        y[j] = span > 0 ? bload(ry, off) : 0.0;
+        z[j] = span > 0 ? bload(rz, off) : 0.0;
+    }
     double v[9] = {0, 0, 0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    const int64_t base = (int64_t)chunk * STATS_CHUNK + tid;
-    const int64_t n = mw.n;
-    for (int i0 = 0; i0 < STATS_PER_THREAD; i0 += STATS_UNROLL) {
-        double x[STATS_UNROLL], y[STATS_UNROLL], z[STATS_UNROLL];
-        bool ok[STATS_UNROLL];
 #pragma unroll
-        for (int j = 0; j < STATS_UNROLL; ++j) {
-            const int64_t a = base + (int64_t)(i0 + j) * WG;
-            ok[j] = a < n;
-            x[j] = ok[j] ? gload(mw.x, a) : 0.0;
-            y[j] = ok[j] ? gload(mw.y, a) : 0.0;
-            z[j] = ok[j] ? gload(mw.z, a) : 0.0;
-        }
+    for (int j = 0; j < STATS_PER_THREAD; ++j) {
+        if (tid + j * WG >= span) break;
+        v[0] += x[j]; v[1] += y[j]; v[2] += z[j];
+        v[3] = fmin(v[3], x[j]); v[4] = fmin(v[4], y[j]); v[5] = fmin(v[5], z[j]);
+        v[6] = fmax(v[6], x[j]); v[7] = fmax(v[7], y[j]); v[8] = fmax(v[8], z[j]);
+    }
 #pragma unroll
-        for (int j = 0; j < STATS_UNROLL; ++j) {
-            if (!ok[j]) continue;
-            v[0] += x[j]; v[1] += y[j]; v[2] += z[j];
-            v[3] = fmin(v[3], x[j]); v[4] = fmin(v[4], y[j]); v[5] = fmin(v[5], z[j]);
-            v[6] = fmax(v[6], x[j]); v[7] = fmax(v[7], y[j]); v[8] = fmax(v[8], z[j]);
+    for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = wave_min(v[k]);
+#pragma unroll
+    for (int k = 6; k < 9; ++k) v[k] = wave_max(v[k]);
+    double* red = reinterpret_cast<double*>(smem);   // [WG / 64][9]
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0)
+        for (int k = 0; k < 9; ++k) red[wave * 9 + k] = v[k];
+    __syncthreads();
+    if (tid < 9) {
+        double a = red[tid];
+        for (int w = 1; w < WG / 64; ++w) {
+            const double b = red[w * 9 + tid];
+            a = tid < 3 ? a + b : tid < 6 ? fmin(a, b) : fmax(a, b);
         }
+        P.stats_part[(mw.stats_off + chunk) * 10 + tid] = a;
+    }
+    __syncthreads();
+}
+
+// Centre (the given one, else the centroid) and scale s >= max |r_i - c| of one molecule from
+// its chunk records: one workgroup per molecule, each thread merges a strided subset of the
+// records, then a fixed-order tree over the threads.
+__device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol, char* smem)
+{
+    const MolWork& mw = P.mols[mol];
+    const int tid = threadIdx.x;
+    double v[9] = {0, 0, 0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int c = tid; c < mw.nstats; c += WG) {
+        const double* r = P.stats_part + (mw.stats_off + c) * 10;
+        for (int k = 0; k < 3; ++k) v[k] += r[k];
+        for (int k = 3; k < 6; ++k) v[k] = fmin(v[k], r[k]);
+        for (int k = 6; k < 9; ++k) v[k] = fmax(v[k], r[k]);
     }
     double* red = reinterpret_cast<double*>(smem);   // [9][WG]
     for (int k = 0; k < 9; ++k) red[k * WG + tid] = v[k];
@@ -45,48 +100,38 @@ __device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk,
         }
         __syncthreads();
     }
-    double* rec = P.stats_part + (mw.stats_off + chunk) * 10;
-    if (tid < 9) rec[tid] = red[tid * WG];
+    if (tid == 0) {
+        double c[3];
+        if (mw.has_centre || mw.n == 0) {
+            c[0] = mw.centre[0]; c[1] = mw.centre[1]; c[2] = mw.centre[2];
+        } else {
+            c[0] = red[0] / (double)mw.n; c[1] = red[WG] / (double)mw.n; c[2] = red[2 * WG] / (double)mw.n;
+        }
+        double s2 = 0.0;
+        if (mw.n > 0)
+            for (int d = 0; d < 3; ++d) {
+                const double e = fmax(fabs(red[(6 + d) * WG] - c[d]), fabs(c[d] - red[(3 + d) * WG]));
+                s2 += e * e;
+            }
+        double s = sqrt(s2);
+        if (!(s > 0.0)) s = 1.0;
+        mw.meta[0] = c[0]; mw.meta[1] = c[1]; mw.meta[2] = c[2];
+        mw.meta[4] = s;
+    }
     __syncthreads();
 }
 
-// Centre (the given one, else the centroid) and scale s >= max |r_i - c| of one molecule from
-// its chunk records, merged in chunk order.
-__device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol)
+// ------------------------------------------------------------------ PAIR items
+// LDS layout (doubles), sized for the largest order Lm of the launch's pairs:
+// sA[nh(Lm)], sB[nh(Lm)], sI[2 * ni(Lm)] (the rotation temporary aliases sI), spow[2Lm+2],
+// scs[3][Lm+1][2], red[WG].
+__host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2) / 2; }
+__host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
 {
-    const MolWork& mw = P.mols[mol];
-    double sx = 0, sy = 0, sz = 0;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int c = 0; c < mw.nstats; ++c) {
-        const double* r = P.stats_part + (mw.stats_off + c) * 10;
-        sx += r[0]; sy += r[1]; sz += r[2];
-        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], r[3 + d]); hi[d] = fmax(hi[d], r[6 + d]); }
-    }
-    double c[3];
-    if (mw.has_centre || mw.n == 0) {
-        c[0] = mw.centre[0]; c[1] = mw.centre[1]; c[2] = mw.centre[2];
-    } else {
-        c[0] = sx / (double)mw.n; c[1] = sy / (double)mw.n; c[2] = sz / (double)mw.n;
-    }
-    double s2 = 0.0;
-    if (mw.n > 0)
-        for (int d = 0; d < 3; ++d) {
-            const double e = fmax(fabs(hi[d] - c[d]), fabs(c[d] - lo[d]));
-            s2 += e * e;
-        }
-    double s = sqrt(s2);
-    if (!(s > 0.0)) s = 1.0;
-    mw.meta[0] = c[0]; mw.meta[1] = c[1]; mw.meta[2] = c[2];
-    mw.meta[4] = s;
+    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni(Lm) + (2 * Lm + 2) + 6 * (Lm + 1) + WG);
 }
 
-// ------------------------------------------------------------------ PAIR items
-// LDS layout (doubles): sA[NH(LMAX)], sB[NH(LMAX)], sI[2*(2LMAX+1)(2LMAX+2)/2] (the rotation
-// temporary aliases sI), spow[2LMAX+2], scs[3][LMAX+1][2], red[WG].
-constexpr int NHMAX = nh(LMAX);
-constexpr int NI = (2 * LMAX + 1) * (2 * LMAX + 2) / 2;
-
-__device__ void rot_phase(double* v, int L, const double* cs /*[LMAX+1][2]*/)
+__device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
 {
     // (Re, Im) of each m > 0 rotated by m*angle: Q_lm -> e^{i m angle} Q_lm
     const int NHl = nh(L);
@@ -131,13 +176,14 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         }
         return;
     }
+    const int Lm = P.pair_lmax;
     double* sA = reinterpret_cast<double*>(smem);
-    double* sB = sA + NHMAX;
-    double* sI = sB + NHMAX;                 // complex, index (L'(L'+1)/2 + M)
+    double* sB = sA + nh(Lm);
+    double* sI = sB + nh(Lm);                // complex, index (L'(L'+1)/2 + M)
     double* sT = sI;                         // rotation temporary (before sI is built)
-    double* spow = sI + 2 * NI;
-    double* scs = spow + (2 * LMAX + 2);     // [3][LMAX+1][2]
-    double* red = scs + 3 * (LMAX + 1) * 2;
+    double* spow = sI + 2 * ni(Lm);
+    double* scs = spow + (2 * Lm + 2);       // [3][Lm+1][2]
+    double* red = scs + 3 * (Lm + 1) * 2;
     if (tid == 0) {
         const double ir = 1.0 / Rn;
         spow[0] = 1.0;
@@ -154,8 +200,8 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         for (int k = 0; k < 3; ++k) {
             double s, c;
             sincos(tid * ang[k], &s, &c);
-            scs[(k * (LMAX + 1) + tid) * 2] = c;
-            scs[(k * (LMAX + 1) + tid) * 2 + 1] = s;
+            scs[(k * (Lm + 1) + tid) * 2] = c;
+            scs[(k * (Lm + 1) + tid) * 2 + 1] = s;
         }
     }
     __syncthreads();
@@ -172,11 +218,11 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         __syncthreads();
         rot_matvec(P.rot, sB, sT, L, false);
         __syncthreads();
-        rot_phase(sT, L, scs + 2 * (LMAX + 1));
+        rot_phase(sT, L, scs + 2 * (Lm + 1));
         __syncthreads();
         rot_matvec(P.rot, sT, sB, L, true);
         __syncthreads();
-        rot_phase(sB, L, scs + 4 * (LMAX + 1));
+        rot_phase(sB, L, scs + 4 * (Lm + 1));
         __syncthreads();
     }
     for (int h = tid; h < NHl; h += WG) sB[h] *= P.invf[h];
@@ -275,27 +321,31 @@ __device__ __forceinline__ int claim(const DevPlan& P, int slot, int begin, int*
 {
     if (threadIdx.x == 0) *s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const int item = *s_item;
+    const int item = __builtin_amdgcn_readfirstlane(*s_item);      // uniform across the workgroup
     __syncthreads();
     return item;
 }
 
-__global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int slot, int begin, int end)
+// Statistics items all cost about the same (one chunk of atoms), so each workgroup takes a
+// fixed contiguous share of [begin, end): no claim counter, whose single address would
+// serialise tens of thousands of short items at one L2 channel.
+__global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int begin, int end)
 {
-    __shared__ __align__(16) char smem[9 * WG * sizeof(double)];
-    __shared__ int s_item;
-    for (;;) {
-        const int item = claim(P, slot, begin, &s_item);
-        if (item >= end) break;
-        const int mol = find_owner(P.stats_prefix, P.nmol, item);
-        stats_item(P, mol, item - P.stats_prefix[mol], smem);
+    __shared__ __align__(16) char smem[9 * (WG / 64) * sizeof(double)];
+    const int64_t n = end - begin;
+    const int lo = begin + (int)(n * blockIdx.x / gridDim.x);
+    const int hi = begin + (int)(n * (blockIdx.x + 1) / gridDim.x);
+    for (int item = lo; item < hi; ++item) {
+        const int mol = __builtin_amdgcn_readfirstlane(P.stats_items[2 * item]);
+        stats_item(P, mol, __builtin_amdgcn_readfirstlane(P.stats_items[2 * item + 1]), smem);
     }
 }
 
 __global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P, int mol_begin, int mol_end)
 {
-    for (int mol = mol_begin + blockIdx.x * blockDim.x + threadIdx.x; mol < mol_end; mol += gridDim.x * blockDim.x)
-        stats_finalize(P, mol);
+    __shared__ __align__(16) char smem[9 * WG * sizeof(double)];
+    for (int mol = mol_begin + blockIdx.x; mol < mol_end; mol += gridDim.x)
+        stats_finalize(P, mol, smem);
 }
 
 __global__ __launch_bounds__(WG) void tcm_moments_finalize(DevPlan P)
@@ -309,7 +359,7 @@ __global__ __launch_bounds__(WG) void tcm_moments_finalize(DevPlan P)
 
 __global__ __launch_bounds__(WG) void tcm_pairs(DevPlan P, int slot, int begin, int end)
 {
-    __shared__ __align__(16) char smem[SMEM_BYTES];
+    extern __shared__ __align__(16) char smem[];         // pair_smem_bytes(P.pair_lmax)
     __shared__ int s_item;
     for (;;) {
         const int item = claim(P, slot, begin, &s_item);
@@ -353,19 +403,19 @@ hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_stats(const DevPlan& P, int begin, int end, int grid, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
     if (grid > end - begin) grid = end - begin;
-    hipLaunchKernelGGL(tcm_stats, dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    hipLaunchKernelGGL(tcm_stats, dim3(grid), dim3(WG), 0, s, P, begin, end);
     return hipGetLastError();
 }
 
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s)
 {
     if (mol_end <= mol_begin) return hipSuccess;
-    hipLaunchKernelGGL(tcm_stats_finalize, dim3((mol_end - mol_begin + WG - 1) / WG), dim3(WG), 0, s, P, mol_begin,
-                       mol_end);
+    const int nb = mol_end - mol_begin;
+    hipLaunchKernelGGL(tcm_stats_finalize, dim3(nb < 4096 ? nb : 4096), dim3(WG), 0, s, P, mol_begin, mol_end);
     return hipGetLastError();
 }
 
@@ -381,33 +431,32 @@ hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid
 {
     if (end <= begin) return hipSuccess;
     if (grid > end - begin) grid = end - begin;
-    hipLaunchKernelGGL(tcm_pairs, dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    hipLaunchKernelGGL(tcm_pairs, dim3(grid), dim3(WG), pair_smem_bytes(P.pair_lmax), s, P, slot, begin, end);
     return hipGetLastError();
 }
 
-hipError_t launch_tiles_f32_a(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f32_d(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f64_a(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f64_b(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f64_c(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_tiles_f64_d(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles_f32_a(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f32_d(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f64_a(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f64_b(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f64_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f64_d(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
 
-hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
-    if (grid > end - begin) grid = end - begin;
     if (prec == TCM_F32C) {
-        if (L <= 12) return launch_tiles_f32_a(L, P, slot, begin, end, grid, s);
-        if (L <= 20) return launch_tiles_f32_b(L, P, slot, begin, end, grid, s);
-        if (L <= 26) return launch_tiles_f32_c(L, P, slot, begin, end, grid, s);
-        return launch_tiles_f32_d(L, P, slot, begin, end, grid, s);
+        if (L <= 12) return launch_tiles_f32_a(L, P, slot, begin, end, num_cu, s);
+        if (L <= 20) return launch_tiles_f32_b(L, P, slot, begin, end, num_cu, s);
+        if (L <= 26) return launch_tiles_f32_c(L, P, slot, begin, end, num_cu, s);
+        return launch_tiles_f32_d(L, P, slot, begin, end, num_cu, s);
     }
-    if (L <= 12) return launch_tiles_f64_a(L, P, slot, begin, end, grid, s);
-    if (L <= 20) return launch_tiles_f64_b(L, P, slot, begin, end, grid, s);
-    if (L <= 26) return launch_tiles_f64_c(L, P, slot, begin, end, grid, s);
-    return launch_tiles_f64_d(L, P, slot, begin, end, grid, s);
+    if (L <= 12) return launch_tiles_f64_a(L, P, slot, begin, end, num_cu, s);
+    if (L <= 20) return launch_tiles_f64_b(L, P, slot, begin, end, num_cu, s);
+    if (L <= 26) return launch_tiles_f64_c(L, P, slot, begin, end, num_cu, s);
+    return launch_tiles_f64_d(L, P, slot, begin, end, num_cu, s);
 }
 
 }  // namespace tcm

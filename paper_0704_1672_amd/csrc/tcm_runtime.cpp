@@ -243,12 +243,13 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // current capacity), so that a caller can make room under its HBM budget first.
 size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols, const std::vector<PairJob>& pairs)
 {
-    int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0;
+    int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0, nitems = 0;
     std::vector<std::pair<int, int>> groups;
     for (const MolJob& j : mols) {
         const int kper = c->kper_for(j.prec, j.L, j.n);
         const int64_t ta = (int64_t)WG * kper;
         const int64_t nt = j.n > 0 ? (j.n + ta - 1) / ta : 1;
+        nitems += nt * num_blocks_for(j.prec, j.L);
         const int64_t ns = j.n > 0 ? (j.n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
         if (j.prec == TCM_F32C) off_f += 2 * nt * nh(j.L); else off_d += nt * nh(j.L);
         off_s += ns;
@@ -258,7 +259,8 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
     std::sort(groups.begin(), groups.end());
     const int ng = (int)(std::unique(groups.begin(), groups.end()) - groups.begin());
     const size_t nmol = mols.size(), np = pairs.size();
-    const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (nmol + 1) + 1024;
+    const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (size_t)off_s +
+                        2 * sizeof(int32_t) * (size_t)nitems + 1024;
     const size_t need[8] = {blob, sizeof(int32_t) * (2 + 2 * (size_t)ng),
                             sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
                             sizeof(double) * 10 * (size_t)(off_s > 0 ? off_s : 1), sizeof(double) * (size_t)(off_r2 > 0 ? off_r2 : 1),
@@ -348,12 +350,61 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         w.has_rot = j.has_rot;
         w.out = p;
     }
+    // largest contractions first (cost ~ (L+1)^4 plus the rotation): the pair launch's tail
+    // holds the cheap ones; every pair writes U[out], so the order changes no result
+    std::stable_sort(pw.begin(), pw.end(), [](const PairWork& u, const PairWork& v) { return u.L > v.L; });
+    int pair_lmax = 0;
+    for (const PairWork& w : pw) pair_lmax = std::max(pair_lmax, (int)w.L);
+    // tile items of each (precision, L) group in decreasing estimated cost (per-thread
+    // instructions: atoms x (recurrence + set-up) + the compensated reduction)
+    const int64_t nitems = tp[nmol];
+    std::vector<int32_t> items(2 * (size_t)nitems);
+    {
+        std::vector<std::pair<int64_t, int64_t>> key;     // (-cost, item)
+        int i0 = 0;
+        while (i0 < nmol) {
+            int i1 = i0;
+            while (i1 < nmol && mols[i1].prec == mols[i0].prec && mols[i1].L == mols[i0].L) ++i1;
+            key.clear();
+            for (int i = i0; i < i1; ++i) {
+                const MolWork& w = mw[i];
+                const Partition part = make_partition(w.L, w.prec == TCM_F32C ? BUDGET_F32 : BUDGET_F64);
+                for (int t = 0; t < w.ntiles; ++t) {
+                    const int64_t span = std::min<int64_t>(w.n - (int64_t)t * WG * w.kper, (int64_t)WG * w.kper);
+                    const int64_t per_thread = (std::max<int64_t>(span, 0) + WG - 1) / WG;
+                    for (int b = 0; b < w.nblk; ++b) {
+                        int acc = 0;
+                        for (int m = part.start[b]; m < part.start[b + 1]; ++m) acc += chain_cost(w.L, m);
+                        const int64_t cost = per_thread * (5 * acc / 2 + 40) + 9 * acc + 300;
+                        key.push_back({-cost, (int64_t)tp[i] + (int64_t)t * w.nblk + b});
+                    }
+                }
+            }
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<int64_t, int64_t>& u, const std::pair<int64_t, int64_t>& v) {
+                                 return u.first < v.first;
+                             });
+            int64_t pos = tp[i0];
+            for (const auto& kv : key) {
+                // owner of item kv.second: the molecule whose prefix range holds it
+                int lo = i0, hi = i1;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) / 2;
+                    if (tp[mid] <= kv.second) lo = mid; else hi = mid;
+                }
+                items[2 * pos] = lo;
+                items[2 * pos + 1] = (int32_t)(kv.second - tp[lo]);
+                ++pos;
+            }
+            i0 = i1;
+        }
+    }
     // blob layout
     const size_t o_mw = 0;
     const size_t o_pw = align_up(o_mw + sizeof(MolWork) * nmol, 256);
     const size_t o_sp = align_up(o_pw + sizeof(PairWork) * npairs, 256);
-    const size_t o_tp = align_up(o_sp + sizeof(int32_t) * (nmol + 1), 256);
-    const size_t blob = align_up(o_tp + sizeof(int32_t) * (nmol + 1), 256);
+    const size_t o_ti = align_up(o_sp + sizeof(int32_t) * 2 * (size_t)(sp[nmol] > 0 ? sp[nmol] : 1), 256);
+    const size_t blob = align_up(o_ti + sizeof(int32_t) * 2 * (size_t)(nitems > 0 ? nitems : 1), 256);
     int rc;
     if ((rc = c->alloc(ws.blob, blob)) != TCM_OK) return rc;
     if (blob > ws.hstage_cap) {
@@ -371,8 +422,15 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
     if (npairs) std::memcpy(h + o_pw, pw.data(), sizeof(PairWork) * npairs);
-    std::memcpy(h + o_sp, sp.data(), sizeof(int32_t) * (nmol + 1));
-    std::memcpy(h + o_tp, tp.data(), sizeof(int32_t) * (nmol + 1));
+    {
+        int32_t* si = (int32_t*)(h + o_sp);                // (molecule, chunk) of each STATS item
+        for (int i = 0; i < nmol; ++i)
+            for (int32_t k = sp[i]; k < sp[i + 1]; ++k) {
+                si[2 * k] = i;
+                si[2 * k + 1] = k - sp[i];
+            }
+    }
+    if (nitems) std::memcpy(h + o_ti, items.data(), sizeof(int32_t) * 2 * (size_t)nitems);
     bp.groups.clear();
     for (int i = 0; i < nmol; ++i) {
         if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L)
@@ -397,10 +455,11 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     DevPlan& P = bp.P;
     P.mols = (const MolWork*)(d + o_mw);
     P.pairs = (const PairWork*)(d + o_pw);
-    P.stats_prefix = (const int32_t*)(d + o_sp);
-    P.tile_prefix = (const int32_t*)(d + o_tp);
+    P.stats_items = (const int32_t*)(d + o_sp);
+    P.tile_items = (const int32_t*)(d + o_ti);
     P.nmol = nmol;
     P.npairs = npairs;
+    P.pair_lmax = pair_lmax;
     P.n_stats = sp[nmol];
     P.n_tiles = tp[nmol];
     P.queue = (int32_t*)ws.sync.p;
@@ -414,7 +473,6 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.invk = (const double*)c->t_invk.p;
     P.invf = (const double*)c->t_invf.p;
     P.rot = (const double*)c->t_rot.p;
-    P.spin_limit = int64_t(1) << 22;
     bp.n_stats = P.n_stats;
     bp.n_tiles = P.n_tiles;
     bp.npairs = npairs;
@@ -437,13 +495,16 @@ static int ensure_aux(Workspace& ws)
     return TCM_OK;
 }
 
-// Issue the launches of one run.  Queue slots: 0 pairs, 1 + 2g statistics of group g,
-// 2 + 2g tiles of group g.
+// Issue the launches of one run.  Claim counters: 0 pairs, 2 + 2g tiles of group g (the
+// statistics launches split their items statically and use none).
 //   concurrent (serial = false): each (precision, L) group runs statistics -> centre/scale
 //     -> tiles on its own forked stream, so the HBM-bound statistics of one group overlap
-//     the ALU-bound tiles of another; the moment finalisation and the pairs follow the join.
-//   serial (serial = true): all statistics, then all tiles, on s; with ev (5 events) the
-//     elapsed time of each step is measured on the launch stream.
+//     the ALU-bound tiles of another and the tail of one group's tiles overlaps the next;
+//     the moment finalisation and the pairs follow the join.
+//   serial (serial = true): one statistics launch over every molecule of the batch, one
+//     centre/scale launch, then the tile launch of each group, all on s (the order a
+//     captured graph replays); with ev (5 events) the elapsed time of each step is measured
+//     on the launch stream.
 int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev)
 {
     const int grid = 2 * c->num_cu;
@@ -452,12 +513,12 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
     if (launch_clear(bp.P.queue, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
     auto group_stats = [&](int g, hipStream_t st) {
         const BuiltPlan::Group& G = bp.groups[g];
-        if (launch_stats(bp.P, 1 + 2 * g, G.stats_begin, G.stats_end, 4 * grid, st) != hipSuccess) return false;
+        if (launch_stats(bp.P, G.stats_begin, G.stats_end, 4 * grid, st) != hipSuccess) return false;
         return launch_stats_finalize(bp.P, G.mol_begin, G.mol_end, st) == hipSuccess;
     };
     auto group_tiles = [&](int g, hipStream_t st) {
         const BuiltPlan::Group& G = bp.groups[g];
-        return launch_tiles(G.prec, G.L, bp.P, 2 + 2 * g, S + G.begin, S + G.end, grid, st) == hipSuccess;
+        return launch_tiles(G.prec, G.L, bp.P, 2 + 2 * g, S + G.begin, S + G.end, c->num_cu, st) == hipSuccess;
     };
     if (!serial && ng > 1 && bp.ws && ensure_aux(*bp.ws) == TCM_OK) {
         Workspace& ws = *bp.ws;
@@ -475,8 +536,8 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
         }
     } else {
         if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
-        for (int g = 0; g < ng; ++g)
-            if (!group_stats(g, s)) return TCM_EDEVICE;
+        if (launch_stats(bp.P, 0, S, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
+        if (launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) return TCM_EDEVICE;
         if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
         for (int g = 0; g < ng; ++g)
             if (!group_tiles(g, s)) return TCM_EDEVICE;
@@ -1036,7 +1097,9 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
         bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            int r2 = run_plan(&c, pl->bp, cs, false, nullptr);
+            // the serial order: the graph runtime replays a captured fork/join one node at a
+            // time anyway, and serially the statistics are a single launch over the batch
+            int r2 = run_plan(&c, pl->bp, cs, true, nullptr);
             hipGraph_t gr = nullptr;
             ok = hipStreamEndCapture(cs, &gr) == hipSuccess && r2 == TCM_OK;
             if (ok) {
@@ -1217,7 +1280,10 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
         for (int d = 0; d < 3; ++d) coords[3 * i + d] = 10.0 * v[d];
         charges[i] = 2 * rnd() - 1;
     }
-    int64_t reps = (int64_t(4) << 20) / n;
+    // enough copies that every candidate's launch holds many waves of items (at least 64M
+    // atoms, or 4096 copies of a small molecule): the timing is then the steady-state
+    // throughput a large batch sees, not the fill of a half-empty device
+    int64_t reps = (int64_t(64) << 20) / n;
     if (reps < 1) reps = 1;
     if (reps > 4096) reps = 4096;
     DevBuf atoms, qbuf;
@@ -1232,7 +1298,7 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
     const int old = had ? c.tune[key] : 0;
     double bestt = 1e300;
     int bestk = 0;
-    for (int k = 4; rc == TCM_OK && k <= 128; k <<= 1) {
+    for (int k = 8; rc == TCM_OK && k <= 256; k <<= 1) {
         c.tune[key] = k;
         std::vector<MolJob> jobs(reps);
         for (int64_t r = 0; r < reps; ++r) {

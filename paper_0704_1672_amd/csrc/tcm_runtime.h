@@ -20,11 +20,11 @@ namespace tcm {
 
 int num_blocks_for(int prec, int L);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_stats(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_stats(const DevPlan& P, int begin, int end, int grid, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
 hipError_t launch_moments_finalize(const DevPlan& P, int grid, hipStream_t s);
-hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
 
 struct Ctx;
 

@@ -3,7 +3,7 @@
 
 namespace tcm {
 
-hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
 {
     switch (L) {
         TCM_TILE_CASE(float, 13)
@@ -17,7 +17,6 @@ hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int 
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace tcm

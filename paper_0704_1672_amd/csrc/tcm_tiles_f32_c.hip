@@ -3,7 +3,7 @@
 
 namespace tcm {
 
-hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
 {
     switch (L) {
         TCM_TILE_CASE(float, 21)
@@ -15,7 +15,6 @@ hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int 
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace tcm

@@ -237,19 +237,25 @@ def tcm_mol_moments(ctx, mid, L, flags=0):
 
 
 def make_requests(a, b, R, L, quat_b=None, flags=0):
-    """Array of tcm_pair_req from per-pair arrays (broadcasting scalars)."""
+    """Array of tcm_pair_req from per-pair arrays; scalars and single rows broadcast to the
+    longest input."""
     a = np.atleast_1d(np.asarray(a, dtype=np.int64))
-    n = len(a)
+    b = np.atleast_1d(np.asarray(b, dtype=np.int64))
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    L = np.atleast_1d(np.asarray(L, dtype=np.int32))
+    Q = None if quat_b is None else np.asarray(quat_b, dtype=np.float64).reshape(-1, 4)
+    flags = np.atleast_1d(np.asarray(flags, dtype=np.int32))
+    n = max(len(a), len(b), len(R), len(L), len(flags), 0 if Q is None else len(Q))
     req = np.zeros(n, dtype=PAIR_REQ_DTYPE)
-    req["a"] = a
-    req["b"] = np.broadcast_to(np.asarray(b, dtype=np.int64), (n,))
-    req["R"] = np.broadcast_to(np.asarray(R, dtype=np.float64).reshape(-1, 3), (n, 3))
-    if quat_b is None:
+    req["a"] = np.broadcast_to(a, (n,))
+    req["b"] = np.broadcast_to(b, (n,))
+    req["R"] = np.broadcast_to(R, (n, 3))
+    if Q is None:
         req["quat_b"][:, 0] = 1.0
     else:
-        req["quat_b"] = np.broadcast_to(np.asarray(quat_b, dtype=np.float64).reshape(-1, 4), (n, 4))
-    req["L"] = np.broadcast_to(np.asarray(L, dtype=np.int32), (n,))
-    req["flags"] = np.broadcast_to(np.asarray(flags, dtype=np.int32), (n,))
+        req["quat_b"] = np.broadcast_to(Q, (n, 4))
+    req["L"] = np.broadcast_to(L, (n,))
+    req["flags"] = np.broadcast_to(flags, (n,))
     return req
 
 

@@ -45,7 +45,7 @@ namespace tcm {
 // kernels: pairs write U = 1 + index and status OK; everything else is a no-op on data
 int num_blocks_for(int prec, int L) { return prec == TCM_F32C ? num_blocks(L, BUDGET_F32) : num_blocks(L, BUDGET_F64); }
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t) { memset(p, 0, n * 4); return 0; }
-hipError_t launch_stats(const DevPlan&, int, int, int, int, hipStream_t) { return 0; }
+hipError_t launch_stats(const DevPlan&, int, int, int, hipStream_t) { return 0; }
 hipError_t launch_stats_finalize(const DevPlan& P, int b, int e, hipStream_t) {
     for (int m = b; m < e; ++m) { P.mols[m].meta[3] = 1.0; }
     return 0; }

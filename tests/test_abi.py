@@ -39,3 +39,17 @@ def test_create_rejects_missing_device():
         assert e.value.code in (tcm.TCM_EDEVICE,)
     with pytest.raises(tcm.TCMError):
         tcm.tcm_create(10_000)
+
+
+def test_make_requests_broadcasts_scalars_and_rows():
+    import numpy as np
+    R = np.arange(48, dtype=float).reshape(16, 3)
+    req = tcm.make_requests(7, 9, R, 12)                       # one pair of molecules, many R
+    assert len(req) == 16 and np.all(req["a"] == 7) and np.all(req["b"] == 9)
+    assert np.array_equal(req["R"], R) and np.all(req["L"] == 12) and np.all(req["quat_b"][:, 0] == 1.0)
+    q = np.tile([0.5, 0.5, 0.5, 0.5], (5, 1))
+    req = tcm.make_requests([1, 2, 3, 4, 5], 0, [1.0, 2.0, 3.0], [8, 8, 16, 16, 20], q, flags=tcm.TCM_REUSE)
+    assert len(req) == 5 and np.all(req["R"] == [1.0, 2.0, 3.0]) and np.array_equal(req["quat_b"], q)
+    assert np.all(req["flags"] == tcm.TCM_REUSE) and list(req["L"]) == [8, 8, 16, 16, 20]
+    with pytest.raises(ValueError):
+        tcm.make_requests([1, 2, 3], 0, np.zeros((2, 3)), 8)  # incompatible lengths
