@@ -261,19 +261,19 @@ def main():
         n = int(w["counts"][f])
         ids.append(tcm.tcm_mol_register_device(ctx.h, base + off, base + row + off, base + 2 * row + off,
                                                base + 3 * row + off, n, precision=tcm.TCM_F32C))
-    # autotuned tile shapes: atoms per thread for every (L, size bucket) in the batch
+    # autotuned tile shapes: for each L group of this batch, the atoms per thread whose tile
+    # launch is fastest on the batch itself (one value per group, kept for its size buckets)
+    req = tcm.make_requests(ids[0::2], ids[1::2], w["R"], w["L"], w["quats"])
     t_tune = time.time()
+    tcm.tcm_autotune_batch(ctx.h, req)
     tuned = {}
     for L in sorted(set(int(x) for x in w["L"])):
         sizes = np.concatenate([w["counts"][0::2][w["L"] == L], w["counts"][1::2][w["L"] == L]])
         for b in sorted(set(int(np.log2(n)) for n in sizes)):
-            rep = int(np.median(sizes[(np.log2(sizes)).astype(int) == b]))
-            k, _ = tcm.tcm_autotune(ctx.h, tcm.TCM_F32C, L, rep)
-            tuned[f"L{L}/2^{b}"] = k
-    log(f"bench: autotuned {len(tuned)} (L, size) buckets in {time.time() - t_tune:.1f}s: {tuned}")
-    req = tcm.make_requests(ids[0::2], ids[1::2], w["R"], w["L"], w["quats"])
+            tuned[f"L{L}/2^{b}"] = tcm.tcm_tune_get(ctx.h, tcm.TCM_F32C, L, 1 << b)
+    log(f"bench: batch autotune in {time.time() - t_tune:.2f}s: {tuned}")
     plan = tcm.tcm_plan_create(ctx.h, req, use_graph=True)           # serial order, one graph
-    plan_s = tcm.tcm_plan_create(ctx.h, req, use_graph=False)        # per-L branches on streams
+    plan_s = tcm.tcm_plan_create(ctx.h, req, use_graph=False)        # tile launches on two streams
     info = tcm.tcm_plan_info(plan)
     log(f"bench: plan: {info}")
 
@@ -296,7 +296,7 @@ def main():
     assert np.array_equal(U, Us) and np.array_equal(st, sts), "graph and stream runs differ"
     mode = "graph" if ms_graph <= ms_streams else "streams"
     ms_step = min(ms_graph, ms_streams)
-    log(f"bench: {args.steps} steps: graph replay {ms_graph:.3f} ms/step, direct launches on forked streams "
+    log(f"bench: {args.steps} steps: graph replay {ms_graph:.3f} ms/step, direct launches on two streams "
         f"{ms_streams:.3f} ms/step; statuses ok: {int(np.sum(st == 0))}")
 
     # per-kernel durations: HIP events on the launch stream around each phase
@@ -378,10 +378,11 @@ def main():
                                "R0 = 1.5(a_A+a_B), random pose of B",
                    "precision": "moments FP32 compensated; rotation, geometric factors, contraction FP64",
                    "execution": ("one HIP graph replay per step (serial order: one statistics launch, "
-                                 "centre/scale, one persistent tile launch per L, moment finalisation, pair "
+                                 "centre/scale, one tile launch per L, moment finalisation, pair "
                                  "kernel)" if mode == "graph" else
-                                 "direct launches per step: per-L (statistics -> centre/scale -> tiles) "
-                                 "branches on forked streams, then moment finalisation and pair kernel"),
+                                 "direct launches per step: one statistics launch, centre/scale, the per-L "
+                                 "tile launches on two streams balanced by work, moment finalisation, pair "
+                                 "kernel"),
                    "ms_per_step_graph": ms_graph, "ms_per_step_streams": ms_streams,
                    "tile_autotune": tuned,
                    "parallelism": "single GPU", "seed": 4},

@@ -142,21 +142,23 @@ typedef struct {
     int32_t flags;
 } tcm_pair_req;
 
-/* Energies of npairs requests in one persistent launch: moments of every molecule the
- * batch names are computed on the device (or reused, per TCM_REUSE), then every pair is
- * rotated and contracted.  U_out[npairs], status_out[npairs] (host).  Returns TCM_OK if
+/* Energies of npairs requests in one batched run: moments of every molecule the batch names
+ * are computed on the device (or reused, per TCM_REUSE) with the molecules of each
+ * (precision, L) group in one launch, then every pair is rotated and contracted in one
+ * launch.  U_out[npairs], status_out[npairs] (host).  Returns TCM_OK if
  * every item succeeded, else the first failing item's code.  Synchronous. */
 int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *U_out,
                      int32_t *status_out);
 
-/* Plan a batch once.  use_graph != 0: its launches are captured in a HIP graph in serial
- * order (one statistics launch for the whole batch, centre/scale, the tile launch of each
- * (precision, L) group, moment finalisation, pairs) and tcm_plan_run replays the graph;
- * use_graph == 0: tcm_plan_run issues the launches directly, each (precision, L) group's
- * statistics and tiles on its own forked stream so that groups overlap.  Either way the run
- * is asynchronous on the context's stream (outputs stay on the device until
- * tcm_plan_results), every moment the batch needs is recomputed (no TCM_REUSE), and the
- * results are identical bit for bit. */
+/* Plan a batch once.  Its launches: one statistics launch for the whole batch, centre/scale,
+ * the tile launch of each (precision, L) group, moment finalisation, pairs.  use_graph != 0:
+ * they are captured in a HIP graph in that serial order and tcm_plan_run replays the graph;
+ * use_graph == 0: tcm_plan_run issues them directly, the groups' tile launches spread over
+ * the context's stream and one forked stream (balanced by work) so that their workgroups
+ * interleave.  Either way the run is asynchronous on the context's stream (outputs stay on
+ * the device until tcm_plan_results), every moment the batch needs is recomputed (no
+ * TCM_REUSE), and the results are identical bit for bit.  Destroy plans before their
+ * context: their device memory is returned to its budget. */
 int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
                     tcm_plan **plan_out);
 int tcm_plan_run(tcm_ctx *ctx, tcm_plan *plan);
@@ -189,6 +191,15 @@ int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);
  * molecule, in ms.  Device memory for the synthetic batch comes from the context's budget. */
 int tcm_autotune(tcm_ctx *ctx, int precision, int L, int64_t n, int *best_kper_out,
                  double *best_ms_out);
+/* Batch-aware autotuner: for each (precision, L) group of the molecules the requests name,
+ * time that group's moment-tile launch on the batch itself for kper in 16..256 (one value
+ * for all of the group's size buckets) and keep the fastest for every size bucket of the
+ * group's molecules -- the tiling that fills the device for this batch's mix of sizes.
+ * Requests are validated as by tcm_batch_energy (invalid ones are skipped); the molecules'
+ * resident moments are invalidated (the next batch recomputes them).  best_ms_out (may be
+ * NULL): the sum of the groups' best tile times, in ms.  A tiling is still a function of
+ * (precision, L, n), so results stay identical alone and in any mix. */
+int tcm_autotune_batch(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *best_ms_out);
 /* Persist / restore the tuning table (text file). */
 int tcm_tune_save(tcm_ctx *ctx, const char *path);
 int tcm_tune_load(tcm_ctx *ctx, const char *path);

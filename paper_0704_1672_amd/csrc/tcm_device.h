@@ -23,8 +23,6 @@
 // Device code of the moment pass (a1) and its fixed-order finalisation (a2), shared by the
 // per-(precision, L) tile translation units.
 #pragma once
-#include <atomic>
-
 #include "tcm.h"
 #include "tcm_internal.h"
 
@@ -455,55 +453,34 @@ __device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j
     dispatch_block<F, L, 0>(tc, P, smem);
 }
 
-// Persistent kernel over the tile items [begin, end) of the molecules of one (precision, L)
-// group.  Workgroups claim items from queue[slot] until the range is exhausted; the items
-// come in decreasing cost, so the last ones to start are the cheapest (a short tail).  The
-// order does not touch any result: each item writes its own partial slot and the partials
-// are merged in tile order afterwards.
+// Tile kernel over the items [begin, end) of the molecules of one (precision, L) group: one
+// workgroup per item (the grid is the item count), so the hardware dispatcher hands out the
+// items as slots free up -- in blockIdx order, i.e. in decreasing cost, so the last items to
+// start are the cheapest -- and the workgroups of concurrently running launches (the groups of
+// other orders on forked streams) interleave with these as the slots free up.  The order does
+// not touch any result: each item writes its own partial slot and the partials are merged in
+// tile order afterwards.
 template <typename F, int L>
-__global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int slot, int begin, int end)
+__global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int begin, int end)
 {
     __shared__ __align__(16) char smem[TILE_SMEM_BYTES];
-    __shared__ int s_item;
-    const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: descriptors in SGPRs
-        __syncthreads();
-        if (item >= end) break;
-        const int j = item - P.n_stats;
-        const int mol = __builtin_amdgcn_readfirstlane(P.tile_items[2 * j]);
-        tile_item_entry<F, L>(P, mol, __builtin_amdgcn_readfirstlane(P.tile_items[2 * j + 1]), smem);
-        __syncthreads();
-    }
+    const int item = begin + (int)blockIdx.x;
+    if (item >= end) return;
+    const int j = item - P.n_stats;
+    const int mol = __builtin_amdgcn_readfirstlane(P.tile_items[2 * j]);
+    tile_item_entry<F, L>(P, mol, __builtin_amdgcn_readfirstlane(P.tile_items[2 * j + 1]), smem);
 }
 
-// Launch the persistent tile kernel of (F, L) with as many workgroups as can be resident
-// (occupancy x compute units), capped by the number of items.
 template <typename F, int L>
-hipError_t launch_tile_kernel(const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
+hipError_t launch_tile_kernel(const DevPlan& P, int begin, int end, hipStream_t s)
 {
-    static std::atomic<int> per_cu{0};
-    int k = per_cu.load(std::memory_order_relaxed);
-    if (k == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tcm_tiles<F, L>, WG, 0) == hipSuccess && nb > 0) {
-            k = nb;
-            per_cu.store(k, std::memory_order_relaxed);
-        } else {
-            (void)hipGetLastError();
-            k = 2;
-        }
-    }
-    int grid = k * num_cu;
-    if (grid > end - begin) grid = end - begin;
-    hipLaunchKernelGGL((tcm_tiles<F, L>), dim3(grid), dim3(WG), 0, s, P, slot, begin, end);
+    if (end <= begin) return hipSuccess;
+    hipLaunchKernelGGL((tcm_tiles<F, L>), dim3(end - begin), dim3(WG), 0, s, P, begin, end);
     return hipGetLastError();
 }
 
 #define TCM_TILE_CASE(F, LL) \
     case LL:                 \
-        return launch_tile_kernel<F, LL>(P, slot, begin, end, num_cu, s);
+        return launch_tile_kernel<F, LL>(P, begin, end, s);
 
 }  // namespace tcm

@@ -1,13 +1,15 @@
 // Internal definitions shared by the HIP kernels and the host runtime of libtcm.
 //
-// Work decomposition of one batch: a sequence of launches, ordered by launch boundaries
+// Work decomposition of one batch: a sequence of launches, ordered by launch boundaries, each
+// with one workgroup per item
 //   a0 STATS      (molecule, chunk)         centroid sums + bounding box of a chunk of atoms
 //      STATS_FIN  (molecule)                centre and scale of each molecule
 //   a1 TILE       (molecule, tile, m-block) eq. (8) moments of 256*kper atoms for one m-block;
-//                                            one persistent launch per (precision, L) group
+//                                            one launch per (precision, L) group
 //   a2 MOM_FIN    (molecule)                fixed-order merge of the tile partials, unscaling
 //   a3-a5 PAIR    (pair)                    rotation, geometric factors, eq. (9) contraction
-// The launches of a batch are captured once into a HIP graph and replayed.
+// A plan's launches are captured once into a HIP graph and replayed, or issued directly with
+// each (precision, L) group on a stream of its own.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -72,9 +74,7 @@ struct DevPlan {
     int32_t pad1;
     int32_t n_stats;
     int32_t n_tiles;
-    // claim counters of the run's launches, cleared before each run by a fill kernel
-    int32_t* queue;                // one counter per launch
-    int32_t* err;                  // [1] device-side error flag (reserved)
+    int32_t* err;                  // [1] device-side error flag (reserved), cleared before each run
     // scratch
     float* part_f;                 // FP32 path tile partials (hi block, then lo block)
     double* part_d;                // FP64 path tile partials

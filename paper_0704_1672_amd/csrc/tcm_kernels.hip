@@ -125,17 +125,22 @@ __device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol, char* 
 // LDS layout (doubles), sized for the largest order Lm of the launch's pairs:
 // sA[nh(Lm)], sB[nh(Lm)], sI[2 * ni(Lm)] (the rotation temporary aliases sI), spow[2Lm+2],
 // scs[3][Lm+1][2], red[WG].
+// One pair per workgroup of PAIR_WG threads, one contraction row per thread.  The size is the
+// same for every launch, so a pair's summation order -- and its energy, bit for bit -- does not
+// depend on how many pairs share the launch (1024-thread workgroups, which split each row's
+// l2 loop four ways, shortened a lone pair but summed in another order).
+constexpr int PAIR_WG = 256;
 __host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2) / 2; }
 __host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
 {
-    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni(Lm) + (2 * Lm + 2) + 6 * (Lm + 1) + WG);
+    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni(Lm) + (2 * Lm + 2) + 6 * (Lm + 1) + PAIR_WG);
 }
 
 __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
 {
     // (Re, Im) of each m > 0 rotated by m*angle: Q_lm -> e^{i m angle} Q_lm
     const int NHl = nh(L);
-    for (int h = threadIdx.x; h < NHl; h += WG) {
+    for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
         const int l = l_of(h), off = h - l * l;
         if (off & 1) {                         // Re part of m = (off+1)/2
             const int m = (off + 1) >> 1;
@@ -150,13 +155,22 @@ __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
 __device__ void rot_matvec(const double* tab, const double* in, double* out, int L, bool inverse)
 {
     const int NHl = nh(L);
-    for (int h = threadIdx.x; h < NHl; h += WG) {
+    for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
         const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
         // tables for order l start at 2 * sum_{j<l} (2j+1)^2 = 2 l (4l^2-1)/3
         const double* D = tab + (int64_t)2 * l * (4 * l * l - 1) / 3 + (inverse ? n * n : 0) + (int64_t)i * n;
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += D[j] * in[l * l + j];
-        out[h] = s;
+        const double* v = in + l * l;
+        // four independent partial sums so that the table loads are all in flight together
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            s0 += D[j] * v[j];
+            s1 += D[j + 1] * v[j + 1];
+            s2 += D[j + 2] * v[j + 2];
+            s3 += D[j + 3] * v[j + 3];
+        }
+        for (; j < n; ++j) s0 += D[j] * v[j];
+        out[h] = (s0 + s1) + (s2 + s3);
     }
 }
 
@@ -205,7 +219,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         }
     }
     __syncthreads();
-    for (int h = tid; h < NHl; h += WG) {
+    for (int h = tid; h < NHl; h += PAIR_WG) {
         const double sc = spow[l_of(h)];
         sA[h] = pw.QA[h] * sc * P.invf[h];
         sB[h] = pw.QB[h] * sc;
@@ -225,7 +239,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         rot_phase(sB, L, scs + 4 * (Lm + 1));
         __syncthreads();
     }
-    for (int h = tid; h < NHl; h += WG) sB[h] *= P.invf[h];
+    for (int h = tid; h < NHl; h += PAIR_WG) sB[h] *= P.invf[h];
     // irregular harmonics of the unit vector n = R/|R|, factorial-scaled:
     //   I_00 = 1, I_MM = -(2M-1)(nx + i ny) I_{M-1,M-1}, I_{M+1,M} = (2M+1) nz I_MM,
     //   I_LM = (2L-1) nz I_{L-1,M} - ((L-1)^2 - M^2) I_{L-2,M}
@@ -257,7 +271,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
     // (negative m2 folded in through b_{l,-m} = (-1)^m conj(b_lm)); U = Re sum w a V.
     double Upart = 0.0;
     const int nrows = (L + 1) * (L + 2) / 2;
-    for (int r = tid; r < nrows; r += WG) {
+    for (int r = tid; r < nrows; r += PAIR_WG) {
         int l1 = 0;
         while ((l1 + 1) * (l1 + 2) / 2 <= r) ++l1;
         const int m1 = r - l1 * (l1 + 1) / 2;
@@ -303,7 +317,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
     }
     red[tid] = Upart;
     __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
+    for (int s = PAIR_WG / 2; s > 0; s >>= 1) {
         if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
@@ -315,61 +329,39 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
 }
 
 // ------------------------------------------------------------------ kernels
-// Every kernel claims items from its own queue counter until [begin, end) is exhausted;
-// the steps of a run are ordered by launch boundaries only (no device-side waits).
-__device__ __forceinline__ int claim(const DevPlan& P, int slot, int begin, int* s_item)
-{
-    if (threadIdx.x == 0) *s_item = begin + __hip_atomic_fetch_add(&P.queue[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(*s_item);      // uniform across the workgroup
-    __syncthreads();
-    return item;
-}
-
-// Statistics items all cost about the same (one chunk of atoms), so each workgroup takes a
-// fixed contiguous share of [begin, end): no claim counter, whose single address would
-// serialise tens of thousands of short items at one L2 channel.
+// One workgroup per item (the grid is the item count): no claim counters, the hardware
+// dispatcher balances the items; the steps of a run are ordered by launch boundaries only
+// (no device-side waits).
 __global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int begin, int end)
 {
     __shared__ __align__(16) char smem[9 * (WG / 64) * sizeof(double)];
-    const int64_t n = end - begin;
-    const int lo = begin + (int)(n * blockIdx.x / gridDim.x);
-    const int hi = begin + (int)(n * (blockIdx.x + 1) / gridDim.x);
-    for (int item = lo; item < hi; ++item) {
-        const int mol = __builtin_amdgcn_readfirstlane(P.stats_items[2 * item]);
-        stats_item(P, mol, __builtin_amdgcn_readfirstlane(P.stats_items[2 * item + 1]), smem);
-    }
+    const int item = begin + (int)blockIdx.x;
+    if (item >= end) return;
+    const int mol = __builtin_amdgcn_readfirstlane(P.stats_items[2 * item]);
+    stats_item(P, mol, __builtin_amdgcn_readfirstlane(P.stats_items[2 * item + 1]), smem);
 }
 
 __global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P, int mol_begin, int mol_end)
 {
     __shared__ __align__(16) char smem[9 * WG * sizeof(double)];
-    for (int mol = mol_begin + blockIdx.x; mol < mol_end; mol += gridDim.x)
-        stats_finalize(P, mol, smem);
+    const int mol = mol_begin + (int)blockIdx.x;
+    if (mol < mol_end) stats_finalize(P, mol, smem);
 }
 
 __global__ __launch_bounds__(WG) void tcm_moments_finalize(DevPlan P)
 {
     __shared__ __align__(16) double smem[(LMAX + 2) + WG];
-    for (int mol = blockIdx.x; mol < P.nmol; mol += gridDim.x) {
-        finalize_moments(P, mol, reinterpret_cast<char*>(smem));
-        __syncthreads();
-    }
+    if ((int)blockIdx.x < P.nmol) finalize_moments(P, blockIdx.x, reinterpret_cast<char*>(smem));
 }
 
-__global__ __launch_bounds__(WG) void tcm_pairs(DevPlan P, int slot, int begin, int end)
+__global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int end)
 {
     extern __shared__ __align__(16) char smem[];         // pair_smem_bytes(P.pair_lmax)
-    __shared__ int s_item;
-    for (;;) {
-        const int item = claim(P, slot, begin, &s_item);
-        if (item >= end) break;
-        pair_item(P, item, smem);
-        __syncthreads();
-    }
+    const int item = begin + (int)blockIdx.x;
+    if (item < end) pair_item(P, item, smem);
 }
 
-// Clears the queue counters of a run (a kernel, not a memset, so that it can sit in a
+// Clears the run's device-side flags (a kernel, not a memset, so that it can sit in a
 // captured graph).
 __global__ void tcm_clear(int32_t* p, int64_t n)
 {
@@ -403,60 +395,56 @@ hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const DevPlan& P, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_stats(const DevPlan& P, int begin, int end, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
-    if (grid > end - begin) grid = end - begin;
-    hipLaunchKernelGGL(tcm_stats, dim3(grid), dim3(WG), 0, s, P, begin, end);
+    hipLaunchKernelGGL(tcm_stats, dim3(end - begin), dim3(WG), 0, s, P, begin, end);
     return hipGetLastError();
 }
 
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s)
 {
     if (mol_end <= mol_begin) return hipSuccess;
-    const int nb = mol_end - mol_begin;
-    hipLaunchKernelGGL(tcm_stats_finalize, dim3(nb < 4096 ? nb : 4096), dim3(WG), 0, s, P, mol_begin, mol_end);
+    hipLaunchKernelGGL(tcm_stats_finalize, dim3(mol_end - mol_begin), dim3(WG), 0, s, P, mol_begin, mol_end);
     return hipGetLastError();
 }
 
-hipError_t launch_moments_finalize(const DevPlan& P, int grid, hipStream_t s)
+hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s)
 {
     if (P.nmol <= 0) return hipSuccess;
-    if (grid > P.nmol) grid = P.nmol;
-    hipLaunchKernelGGL(tcm_moments_finalize, dim3(grid), dim3(WG), 0, s, P);
+    hipLaunchKernelGGL(tcm_moments_finalize, dim3(P.nmol), dim3(WG), 0, s, P);
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s)
+hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
-    if (grid > end - begin) grid = end - begin;
-    hipLaunchKernelGGL(tcm_pairs, dim3(grid), dim3(WG), pair_smem_bytes(P.pair_lmax), s, P, slot, begin, end);
+    hipLaunchKernelGGL(tcm_pairs, dim3(end - begin), dim3(PAIR_WG), pair_smem_bytes(P.pair_lmax), s, P, begin, end);
     return hipGetLastError();
 }
 
-hipError_t launch_tiles_f32_a(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f32_d(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f64_a(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f64_b(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f64_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
-hipError_t launch_tiles_f64_d(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_tiles_f32_a(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f32_b(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f32_d(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f64_a(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f64_b(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f64_c(int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_tiles_f64_d(int L, const DevPlan& P, int begin, int end, hipStream_t s);
 
-hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
     if (prec == TCM_F32C) {
-        if (L <= 12) return launch_tiles_f32_a(L, P, slot, begin, end, num_cu, s);
-        if (L <= 20) return launch_tiles_f32_b(L, P, slot, begin, end, num_cu, s);
-        if (L <= 26) return launch_tiles_f32_c(L, P, slot, begin, end, num_cu, s);
-        return launch_tiles_f32_d(L, P, slot, begin, end, num_cu, s);
+        if (L <= 12) return launch_tiles_f32_a(L, P, begin, end, s);
+        if (L <= 20) return launch_tiles_f32_b(L, P, begin, end, s);
+        if (L <= 26) return launch_tiles_f32_c(L, P, begin, end, s);
+        return launch_tiles_f32_d(L, P, begin, end, s);
     }
-    if (L <= 12) return launch_tiles_f64_a(L, P, slot, begin, end, num_cu, s);
-    if (L <= 20) return launch_tiles_f64_b(L, P, slot, begin, end, num_cu, s);
-    if (L <= 26) return launch_tiles_f64_c(L, P, slot, begin, end, num_cu, s);
-    return launch_tiles_f64_d(L, P, slot, begin, end, num_cu, s);
+    if (L <= 12) return launch_tiles_f64_a(L, P, begin, end, s);
+    if (L <= 20) return launch_tiles_f64_b(L, P, begin, end, s);
+    if (L <= 26) return launch_tiles_f64_c(L, P, begin, end, s);
+    return launch_tiles_f64_d(L, P, begin, end, s);
 }
 
 }  // namespace tcm

@@ -244,7 +244,6 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols, const std::vector<PairJob>& pairs)
 {
     int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0, nitems = 0;
-    std::vector<std::pair<int, int>> groups;
     for (const MolJob& j : mols) {
         const int kper = c->kper_for(j.prec, j.L, j.n);
         const int64_t ta = (int64_t)WG * kper;
@@ -254,14 +253,11 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
         if (j.prec == TCM_F32C) off_f += 2 * nt * nh(j.L); else off_d += nt * nh(j.L);
         off_s += ns;
         off_r2 += nt;
-        groups.push_back({j.prec, j.L});
     }
-    std::sort(groups.begin(), groups.end());
-    const int ng = (int)(std::unique(groups.begin(), groups.end()) - groups.begin());
     const size_t nmol = mols.size(), np = pairs.size();
     const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (size_t)off_s +
                         2 * sizeof(int32_t) * (size_t)nitems + 1024;
-    const size_t need[8] = {blob, sizeof(int32_t) * (2 + 2 * (size_t)ng),
+    const size_t need[8] = {blob, sizeof(int32_t),
                             sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
                             sizeof(double) * 10 * (size_t)(off_s > 0 ? off_s : 1), sizeof(double) * (size_t)(off_r2 > 0 ? off_r2 : 1),
                             sizeof(double) * (np > 0 ? np : 1), sizeof(int32_t) * (np > 0 ? np : 1)};
@@ -277,8 +273,8 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
 int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const std::vector<PairJob>& pairs_in,
                BuiltPlan& bp, hipStream_t s)
 {
-    // molecules sorted by (precision, L): each group's tiles are one persistent launch of
-    // the tile kernel compiled for that order
+    // molecules sorted by (precision, L): each group's tiles are one launch of the tile
+    // kernel compiled for that order
     const int nmol = (int)mols_in.size(), npairs = (int)pairs_in.size();
     std::vector<int> order(nmol), newidx(nmol);
     for (int i = 0; i < nmol; ++i) order[i] = i;
@@ -434,15 +430,15 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     bp.groups.clear();
     for (int i = 0; i < nmol; ++i) {
         if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L)
-            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i], i, i, sp[i], sp[i]});
+            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i], i, i, sp[i], sp[i], 0.0});
         BuiltPlan::Group& G = bp.groups.back();
+        G.work += 6.0 * (mols[i].L + 1) * (mols[i].L + 2) * (double)mols[i].n;
         G.end = tp[i + 1];
         G.mol_end = i + 1;
         G.stats_end = sp[i + 1];
     }
     bp.ws = &ws;
-    const int nqueue = 1 + 2 * (int)bp.groups.size();
-    const int64_t sync_ints = nqueue + 1;
+    const int64_t sync_ints = 1;                            // the error flag
     if ((rc = c->alloc(ws.sync, sizeof(int32_t) * sync_ints)) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.part_f, sizeof(float) * (off_f > 0 ? off_f : 1))) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.part_d, sizeof(double) * (off_d > 0 ? off_d : 1))) != TCM_OK) return rc;
@@ -462,8 +458,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.pair_lmax = pair_lmax;
     P.n_stats = sp[nmol];
     P.n_tiles = tp[nmol];
-    P.queue = (int32_t*)ws.sync.p;
-    P.err = P.queue + nqueue;
+    P.err = (int32_t*)ws.sync.p;
     P.part_f = (float*)ws.part_f.p;
     P.part_d = (double*)ws.part_d.p;
     P.stats_part = (double*)ws.stats.p;
@@ -485,67 +480,91 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
 
 static int ensure_aux(Workspace& ws)
 {
-    if (ws.fork) return TCM_OK;
-    for (int k = 0; k < NAUX; ++k) {
-        if (hipStreamCreateWithFlags(&ws.aux[k], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ws.join[k], hipEventDisableTiming) != hipSuccess)
+    for (int k = 0; k < NLANES - 1; ++k) {
+        if (!ws.aux[k] && hipStreamCreateWithFlags(&ws.aux[k], hipStreamNonBlocking) != hipSuccess) {
+            ws.aux[k] = nullptr;
             return TCM_EDEVICE;
+        }
+        if (!ws.join[k] && hipEventCreateWithFlags(&ws.join[k], hipEventDisableTiming) != hipSuccess) {
+            ws.join[k] = nullptr;
+            return TCM_EDEVICE;
+        }
     }
-    if (hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming) != hipSuccess) return TCM_EDEVICE;
+    if (!ws.fork && hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming) != hipSuccess) {
+        ws.fork = nullptr;
+        return TCM_EDEVICE;
+    }
     return TCM_OK;
 }
 
-// Issue the launches of one run.  Claim counters: 0 pairs, 2 + 2g tiles of group g (the
-// statistics launches split their items statically and use none).
-//   concurrent (serial = false): each (precision, L) group runs statistics -> centre/scale
-//     -> tiles on its own forked stream, so the HBM-bound statistics of one group overlap
-//     the ALU-bound tiles of another and the tail of one group's tiles overlaps the next;
-//     the moment finalisation and the pairs follow the join.
-//   serial (serial = true): one statistics launch over every molecule of the batch, one
-//     centre/scale launch, then the tile launch of each group, all on s (the order a
-//     captured graph replays); with ev (5 events) the elapsed time of each step is measured
-//     on the launch stream.
+static void destroy_streams(Workspace& ws)
+{
+    for (int k = 0; k < NLANES - 1; ++k) {
+        if (ws.aux[k]) (void)hipStreamDestroy(ws.aux[k]);
+        ws.aux[k] = nullptr;
+        if (ws.join[k]) (void)hipEventDestroy(ws.join[k]);
+        ws.join[k] = nullptr;
+    }
+    if (ws.fork) (void)hipEventDestroy(ws.fork);
+    ws.fork = nullptr;
+}
+
+// Issue the launches of one run (every kernel has one workgroup per item).  Both orders start
+// with one statistics launch over every molecule of the batch and one centre/scale launch,
+// and end with the moment finalisation and the pair launch on s.
+//   serial (serial = true): the tile launch of each (precision, L) group in turn on s (the
+//     order a captured graph replays); with ev (5 events) the elapsed time of each step is
+//     measured on the launch stream.
+//   lanes (serial = false): the groups' tile launches are spread over s and NLANES - 1 more
+//     streams, balanced by work (largest first, each to the lightest lane).  The workgroups of
+//     the two lanes' launches interleave as slots free up, so a small group's items fill the
+//     tail of a large one instead of running alone on a half-empty device.  Two streams, not
+//     one per group: the process's streams share four hardware queues, and with one stream
+//     per group some groups queued behind others.
 int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev)
 {
-    const int grid = 2 * c->num_cu;
+    (void)c;
     const int S = bp.n_stats;
     const int ng = (int)bp.groups.size();
-    if (launch_clear(bp.P.queue, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
-    auto group_stats = [&](int g, hipStream_t st) {
-        const BuiltPlan::Group& G = bp.groups[g];
-        if (launch_stats(bp.P, G.stats_begin, G.stats_end, 4 * grid, st) != hipSuccess) return false;
-        return launch_stats_finalize(bp.P, G.mol_begin, G.mol_end, st) == hipSuccess;
-    };
+    if (launch_clear(bp.P.err, bp.sync_ints, s) != hipSuccess) return TCM_EDEVICE;
     auto group_tiles = [&](int g, hipStream_t st) {
         const BuiltPlan::Group& G = bp.groups[g];
-        return launch_tiles(G.prec, G.L, bp.P, 2 + 2 * g, S + G.begin, S + G.end, c->num_cu, st) == hipSuccess;
+        return launch_tiles(G.prec, G.L, bp.P, S + G.begin, S + G.end, st) == hipSuccess;
     };
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_stats(bp.P, 0, S, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) return TCM_EDEVICE;
+    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
     if (!serial && ng > 1 && bp.ws && ensure_aux(*bp.ws) == TCM_OK) {
         Workspace& ws = *bp.ws;
+        std::vector<int> order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int u, int v) { return bp.groups[u].work > bp.groups[v].work; });
+        const int nl = ng < NLANES ? ng : NLANES;
         if (hipEventRecord(ws.fork, s) != hipSuccess) return TCM_EDEVICE;
-        const int nuse = ng < NAUX ? ng : NAUX;
-        for (int k = 0; k < nuse; ++k)
+        for (int k = 0; k < nl - 1; ++k)
             if (hipStreamWaitEvent(ws.aux[k], ws.fork, 0) != hipSuccess) return TCM_EDEVICE;
-        for (int g = 0; g < ng; ++g) {
-            hipStream_t st = ws.aux[g % NAUX];
-            if (!group_stats(g, st) || !group_tiles(g, st)) return TCM_EDEVICE;
+        double load[NLANES] = {};
+        for (int g : order) {
+            int lane = 0;
+            for (int k = 1; k < nl; ++k)
+                if (load[k] < load[lane]) lane = k;
+            load[lane] += bp.groups[g].work;
+            if (!group_tiles(g, lane ? ws.aux[lane - 1] : s)) return TCM_EDEVICE;
         }
-        for (int k = 0; k < nuse; ++k) {
+        for (int k = 0; k < nl - 1; ++k) {
             if (hipEventRecord(ws.join[k], ws.aux[k]) != hipSuccess) return TCM_EDEVICE;
             if (hipStreamWaitEvent(s, ws.join[k], 0) != hipSuccess) return TCM_EDEVICE;
         }
     } else {
-        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
-        if (launch_stats(bp.P, 0, S, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
-        if (launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) return TCM_EDEVICE;
-        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
         for (int g = 0; g < ng; ++g)
             if (!group_tiles(g, s)) return TCM_EDEVICE;
-        if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
     }
-    if (launch_moments_finalize(bp.P, 4 * grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_moments_finalize(bp.P, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_pairs(bp.P, 0, 0, bp.npairs, grid, s) != hipSuccess) return TCM_EDEVICE;
+    if (launch_pairs(bp.P, 0, bp.npairs, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[4], s) != hipSuccess) return TCM_EDEVICE;
     return TCM_OK;
 }
@@ -561,14 +580,7 @@ int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s)
 
 void free_workspace(Ctx* c, Workspace& ws)
 {
-    for (int k = 0; k < NAUX; ++k) {
-        if (ws.aux[k]) (void)hipStreamDestroy(ws.aux[k]);
-        if (ws.join[k]) (void)hipEventDestroy(ws.join[k]);
-        ws.aux[k] = nullptr;
-        ws.join[k] = nullptr;
-    }
-    if (ws.fork) (void)hipEventDestroy(ws.fork);
-    ws.fork = nullptr;
+    destroy_streams(ws);
     c->release(ws.blob); c->release(ws.sync); c->release(ws.part_f); c->release(ws.part_d);
     c->release(ws.stats); c->release(ws.r2); c->release(ws.outU); c->release(ws.outS);
     if (ws.hstage) (void)hipHostFree(ws.hstage);
@@ -1079,6 +1091,7 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
     if (first_error(rp.pre_status.data(), np) != TCM_OK) return first_error(rp.pre_status.data(), np);
     tcm_plan* pl = new (std::nothrow) tcm_plan();
     if (!pl) return TCM_ENOMEM;
+    pl->ctx = &c;
     if ((rc = build_plan(&c, pl->ws, rp.mj, rp.pj, pl->bp, s)) != TCM_OK) {
         free_workspace(&c, pl->ws);
         delete pl;
@@ -1194,18 +1207,9 @@ extern "C" void tcm_plan_destroy(tcm_plan* pl)
     if (!pl) return;
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    // the plan's buffers were charged to the context that created it; freeing them here
-    // without the context only returns device memory (budget accounting is per context and
-    // plans are expected to be destroyed before their context)
-    for (DevBuf* b : {&pl->ws.blob, &pl->ws.sync, &pl->ws.part_f, &pl->ws.part_d, &pl->ws.stats, &pl->ws.r2,
-                      &pl->ws.outU, &pl->ws.outS})
-        if (b->p) (void)hipFree(b->p);
-    if (pl->ws.hstage) (void)hipHostFree(pl->ws.hstage);
-    for (int k = 0; k < NAUX; ++k) {
-        if (pl->ws.aux[k]) (void)hipStreamDestroy(pl->ws.aux[k]);
-        if (pl->ws.join[k]) (void)hipEventDestroy(pl->ws.join[k]);
-    }
-    if (pl->ws.fork) (void)hipEventDestroy(pl->ws.fork);
+    // the plan's buffers were charged to the context that created it (plans are destroyed
+    // before their context): return them to its budget
+    free_workspace(pl->ctx, pl->ws);
     delete pl;
 }
 
@@ -1258,6 +1262,86 @@ extern "C" int tcm_tune_load(tcm_ctx* t, const char* path)
 // tile launches of a synthetic batch: copies of one molecule of n atoms (points in a ball,
 // charges in [-1, 1]), enough copies to fill the device, so the measurement reflects batched
 // throughput rather than launch latency.
+// Batch-aware tuning: the tile launch of each (precision, L) group of the batch is timed for
+// every candidate kper (applied to all the group's size buckets), and the fastest is kept
+// for every size bucket of the group's molecules.
+extern "C" int tcm_autotune_batch(tcm_ctx* t, const tcm_pair_req* reqs, int64_t npairs, double* best_ms)
+{
+    if (!t || npairs < 0 || (npairs > 0 && !reqs)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, npairs, false, rp);   // molecules are recomputed afterwards
+    if (rc != TCM_OK) return rc;
+    if (best_ms) *best_ms = 0.0;
+    if (rp.mj.empty()) return TCM_OK;
+    std::map<std::pair<int, int>, std::vector<int64_t>> sizes;   // (prec, L) -> molecule sizes
+    for (const MolJob& j : rp.mj) sizes[{j.prec, j.L}].push_back(j.n);
+    std::map<int64_t, int> saved;                                 // tune entries to restore on failure
+    for (auto& kv : sizes)
+        for (int64_t n : kv.second) {
+            const int64_t key = tune_key(kv.first.first, kv.first.second, n);
+            auto it = c.tune.find(key);
+            saved[key] = it == c.tune.end() ? 0 : it->second;
+        }
+    std::map<std::pair<int, int>, std::pair<double, int>> best;    // (prec, L) -> (ms, kper)
+    std::vector<hipEvent_t> ev(2 * sizes.size(), nullptr);
+    for (auto& e : ev)
+        if (rc == TCM_OK && hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
+    for (int k = 16; rc == TCM_OK && k <= 256; k <<= 1) {
+        for (auto& kv : sizes)
+            for (int64_t n : kv.second) c.tune[tune_key(kv.first.first, kv.first.second, n)] = k;
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, rp.mj, {}, bp, s)) != TCM_OK) break;
+        const int ng = (int)bp.groups.size();
+        if (launch_clear(bp.P.err, bp.sync_ints, s) != hipSuccess ||
+            launch_stats(bp.P, 0, bp.n_stats, s) != hipSuccess ||
+            launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) {
+            rc = TCM_EDEVICE;
+            break;
+        }
+        std::vector<double> ms(ng, 1e300);
+        for (int rep = 0; rc == TCM_OK && rep < 3; ++rep) {
+            for (int gi = 0; gi < ng && rc == TCM_OK; ++gi) {
+                const BuiltPlan::Group& G = bp.groups[gi];
+                if (hipEventRecord(ev[2 * gi], s) != hipSuccess ||
+                    launch_tiles(G.prec, G.L, bp.P, bp.n_stats + G.begin, bp.n_stats + G.end, s) != hipSuccess ||
+                    hipEventRecord(ev[2 * gi + 1], s) != hipSuccess)
+                    rc = TCM_EDEVICE;
+            }
+            if (rc == TCM_OK && hipStreamSynchronize(s) != hipSuccess) rc = TCM_EDEVICE;
+            for (int gi = 0; gi < ng && rc == TCM_OK; ++gi) {
+                float e = 0.f;
+                (void)hipEventElapsedTime(&e, ev[2 * gi], ev[2 * gi + 1]);
+                if (rep > 0 || gi > 0) ms[gi] = std::min(ms[gi], (double)e);   // the very first launch warms up
+            }
+        }
+        for (int gi = 0; gi < ng && rc == TCM_OK; ++gi) {
+            const std::pair<int, int> key{bp.groups[gi].prec, bp.groups[gi].L};
+            auto it = best.find(key);
+            if (it == best.end() || ms[gi] < it->second.first) best[key] = {ms[gi], k};
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != TCM_OK) {
+        for (auto& kv : saved) {
+            if (kv.second) c.tune[kv.first] = kv.second; else c.tune.erase(kv.first);
+        }
+        return rc;
+    }
+    double total = 0.0;
+    for (auto& kv : sizes) {
+        const auto& b = best[kv.first];
+        total += b.first;
+        for (int64_t n : kv.second) c.tune[tune_key(kv.first.first, kv.first.second, n)] = b.second;
+    }
+    if (best_ms) *best_ms = total;
+    return TCM_OK;
+}
+
 extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k, double* best_ms)
 {
     if (!t || L < 0 || L > LMAX || n <= 0 || n > (int64_t(1) << 30) || (prec != TCM_F64 && prec != TCM_F32C))

@@ -20,11 +20,11 @@ namespace tcm {
 
 int num_blocks_for(int prec, int L);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_stats(const DevPlan& P, int begin, int end, int grid, hipStream_t s);
-hipError_t launch_pairs(const DevPlan& P, int slot, int begin, int end, int grid, hipStream_t s);
+hipError_t launch_stats(const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
-hipError_t launch_moments_finalize(const DevPlan& P, int grid, hipStream_t s);
-hipError_t launch_tiles(int prec, int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s);
+hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s);
+hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s);
 
 struct Ctx;
 
@@ -73,17 +73,18 @@ struct PairJob {
     int has_rot;
 };
 
-constexpr int NAUX = 4;            // forked streams for concurrent (precision, L) groups
 
 // Device-side state of a planned batch: the uploaded plan blob, scratch and outputs, and
 // the streams and events its launches fork onto.
+constexpr int NLANES = 2;          // streams the tile launches of a run are spread over
+
 struct Workspace {
     DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS;
     void* hstage = nullptr;        // pinned host staging for the blob
     size_t hstage_cap = 0;
-    hipStream_t aux[NAUX] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t aux[NLANES - 1] = {}; // the further lanes of tile launches
     hipEvent_t fork = nullptr;
-    hipEvent_t join[NAUX] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t join[NLANES - 1] = {};
 };
 
 struct BuiltPlan {
@@ -95,6 +96,7 @@ struct BuiltPlan {
         int prec, L, begin, end;   // tile item range (tile numbering, before n_stats offset)
         int mol_begin, mol_end;    // molecule range
         int stats_begin, stats_end;
+        double work;               // moment flops of the group (its tile launch's size)
     };
     Workspace* ws = nullptr;
     std::vector<Group> groups;
@@ -150,6 +152,7 @@ struct tcm_ctx {
 };
 
 struct tcm_plan {
+    tcm::Ctx* ctx = nullptr;       // the context that created it (destroy plans first)
     tcm::Workspace ws;
     tcm::BuiltPlan bp;
     hipGraph_t graph = nullptr;

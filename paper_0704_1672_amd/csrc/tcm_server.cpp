@@ -286,7 +286,38 @@ static void admit_and_launch(Server* S, Slot& sl)
         S->cache[key] = std::move(m);
         return raw;
     };
-    // Admit one request: both fragments resident or fetched, or nothing changes.
+    // Workspace growth of the launch if the batch so far took one more request whose sides
+    // are (a or a fresh fragment of n_a atoms) and (b or n_b), at order L.
+    int npairs_batch = 0;
+    auto growth_with = [&](const Side& sa, const Side& sb, const tcm_request& r) -> size_t {
+        std::vector<MolJob> mj;
+        std::map<SMol*, int> lv(need.begin(), need.end());
+        for (const Side* sd : {&sa, &sb}) {
+            if (sd->m && sd->m->Lcached < r.L) {
+                auto it = lv.find(sd->m);
+                if (it == lv.end()) lv[sd->m] = r.L; else if (it->second < r.L) it->second = r.L;
+            }
+        }
+        for (auto& kv : lv) {
+            MolJob j{};
+            j.n = kv.first->n;
+            j.L = std::max(kv.second, kv.first->Lcached);
+            j.prec = kv.first->prec;
+            mj.push_back(j);
+        }
+        const bool same = r.key_b == r.key_a;
+        for (int side = 0; side < (same ? 1 : 2); ++side) {
+            if (!(side == 0 ? sa.fresh : sb.fresh)) continue;
+            MolJob j{};
+            j.n = side == 0 ? r.n_a : r.n_b;
+            j.L = r.L;
+            j.prec = r.precision;
+            mj.push_back(j);
+        }
+        return workspace_growth(c, sl.ws, mj, std::vector<PairJob>(npairs_batch + 1));
+    };
+    // Admit one request: both fragments resident or fetched, with room in the budget for
+    // them and for the launch's workspace, or nothing changes.
     auto admit = [&](const tcm_request& r, SMol** pa, SMol** pb) -> int {
         const bool same = r.key_b == r.key_a;
         Side sa = look(r.key_a, r.atoms_a, r.n_a, r.L);
@@ -297,6 +328,7 @@ static void admit_and_launch(Server* S, Slot& sl)
         const int nfresh = (sa.fresh ? 1 : 0) + (sb.fresh && !same ? 1 : 0);
         size_t bytes = (sa.fresh ? mol_bytes(r.n_a, borrow) : 0) + (sb.fresh && !same ? mol_bytes(r.n_b, borrow) : 0);
         if ((int)S->free_slots.size() < nfresh) bytes += sizeof(double) * ARENA_SLOT * ARENA_CHUNK;
+        if (c->budget) bytes += growth_with(sa, sb, r);
         if (bytes) {
             // resident sides of this request must survive the eviction
             if (sa.m) ++sa.m->pin;
@@ -356,6 +388,7 @@ static void admit_and_launch(Server* S, Slot& sl)
         }
         batch.push_back(q);
         pre.push_back(TCM_OK);
+        ++npairs_batch;
     }
     if (batch.empty() && S->inflight == 0 && !keep.empty()) {
         // nothing in flight can free memory or finish a fragment: the oldest deferred

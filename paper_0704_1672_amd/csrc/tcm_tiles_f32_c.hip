@@ -3,7 +3,7 @@
 
 namespace tcm {
 
-hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int slot, int begin, int end, int num_cu, hipStream_t s)
+hipError_t launch_tiles_f32_c(int L, const DevPlan& P, int begin, int end, hipStream_t s)
 {
     switch (L) {
         TCM_TILE_CASE(float, 21)

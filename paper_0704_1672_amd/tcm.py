@@ -73,6 +73,7 @@ _SIGS = {
     "tcm_tune_get": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32]),
     "tcm_tune_set": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, C.c_int]),
     "tcm_autotune": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32, _dp]),
+    "tcm_autotune_batch": (C.c_int, [_vp, _vp, C.c_int64, _dp]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -334,6 +335,15 @@ def tcm_autotune(ctx, precision, L, n):
     ms = C.c_double()
     _check(lib().tcm_autotune(ctx, precision, L, n, C.byref(k), C.byref(ms)), "tcm_autotune")
     return k.value, ms.value
+
+
+def tcm_autotune_batch(ctx, reqs):
+    """Returns the sum of the groups' best tile times (ms)."""
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    ms = C.c_double()
+    _check(lib().tcm_autotune_batch(ctx, reqs.ctypes.data if len(reqs) else None, len(reqs), C.byref(ms)),
+           "tcm_autotune_batch")
+    return ms.value
 
 
 def tcm_tune_save(ctx, path):

@@ -45,16 +45,16 @@ namespace tcm {
 // kernels: pairs write U = 1 + index and status OK; everything else is a no-op on data
 int num_blocks_for(int prec, int L) { return prec == TCM_F32C ? num_blocks(L, BUDGET_F32) : num_blocks(L, BUDGET_F64); }
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t) { memset(p, 0, n * 4); return 0; }
-hipError_t launch_stats(const DevPlan&, int, int, int, hipStream_t) { return 0; }
+hipError_t launch_stats(const DevPlan&, int, int, hipStream_t) { return 0; }
 hipError_t launch_stats_finalize(const DevPlan& P, int b, int e, hipStream_t) {
     for (int m = b; m < e; ++m) { P.mols[m].meta[3] = 1.0; }
     return 0; }
-hipError_t launch_moments_finalize(const DevPlan& P, int, hipStream_t) {
+hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t) {
     for (int m = 0; m < P.nmol; ++m) { const MolWork& w = P.mols[m];
         for (int h = 0; h < nh(w.L); ++h) w.Q[h] = w.n; w.meta[3] = 0.5; }
     return 0; }
-hipError_t launch_tiles(int, int, const DevPlan&, int, int, int, int, hipStream_t) { return 0; }
-hipError_t launch_pairs(const DevPlan& P, int, int b, int e, int, hipStream_t) {
+hipError_t launch_tiles(int, int, const DevPlan&, int, int, hipStream_t) { return 0; }
+hipError_t launch_pairs(const DevPlan& P, int b, int e, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; double s = w.QA[0] + 1e-3 * w.QB[0];
         double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
         if (!(w.flags & TCM_UNCHECKED) && !(R > w.metaA[3] + w.metaB[3])) { P.status[w.out] = TCM_EDOMAIN; P.U[w.out] = 0; }

@@ -9,7 +9,37 @@
 #include <chrono>
 #include <cmath>
 #include <map>
+// Plans return their device memory to the context's budget when destroyed.
+static int plan_lifecycle() {
+    tcm_ctx* ctx; if (tcm_create(&ctx, 0, 0, 0)) return 1;
+    std::vector<double> xyz(3 * 5000, 1.0), q(5000, 0.5);
+    for (int i = 0; i < 5000; ++i) xyz[3 * i] = i * 1e-3;
+    tcm_mol_id a, b;
+    if (tcm_mol_upload(ctx, xyz.data(), q.data(), 5000, nullptr, TCM_F32C, &a) ||
+        tcm_mol_upload(ctx, xyz.data(), q.data(), 5000, nullptr, TCM_F64, &b)) return 2;
+    // the molecules' own moment tables grow to the largest order a plan asks for (they stay
+    // with the molecules): warm up with every order first, then every plan must give back
+    // exactly what it took
+    size_t base = 0;
+    for (int rep = 0; rep < 60; ++rep) {
+        if (rep == 10) tcm_mem_info(ctx, &base, nullptr);
+        tcm_pair_req r[2] = {};
+        r[0].a = a; r[0].b = b; r[0].R[0] = 100.0; r[0].quat_b[0] = 1; r[0].L = 8 + rep % 9;
+        r[1] = r[0]; r[1].L = 3;
+        tcm_plan* p;
+        if (tcm_plan_create(ctx, r, 2, rep & 1, &p)) { printf("plan_create failed\n"); return 3; }
+        if (tcm_plan_run(ctx, p)) return 4;
+        tcm_plan_destroy(p);
+        size_t u; tcm_mem_info(ctx, &u, nullptr);
+        if (rep >= 10 && u != base) { printf("plan %d: used %zu != %zu after destroy\n", rep, u, base); return 5; }
+    }
+    tcm_destroy(ctx);
+    printf("plan lifecycle ok\n");
+    return 0;
+}
+
 int main(int argc, char** argv) {
+    if (int rc = plan_lifecycle()) return 10 + rc;
     int seeds = argc > 1 ? atoi(argv[1]) : 20;
     for (int seed = 0; seed < seeds; ++seed) {
         std::mt19937 rng(seed);

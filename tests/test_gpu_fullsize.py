@@ -102,12 +102,8 @@ def test_uneven_batch_full_size(ctx, orc, synth):
         ids.append(tcm.tcm_mol_register_device(ctx, base + off, base + row + off, base + 2 * row + off,
                                                base + 3 * row + off, int(w["counts"][f])))
     try:
-        for L in (8, 12, 16, 20):           # the benchmark's autotuned launch configuration
-            sizes = np.concatenate([w["counts"][0::2][w["L"] == L], w["counts"][1::2][w["L"] == L]])
-            for b in sorted(set(int(np.log2(n)) for n in sizes)):
-                rep = int(np.median(sizes[(np.log2(sizes)).astype(int) == b]))
-                tcm.tcm_autotune(ctx, tcm.TCM_F32C, L, rep)
         req = tcm.make_requests(ids[0::2], ids[1::2], w["R"], w["L"], w["quats"])
+        assert tcm.tcm_autotune_batch(ctx, req) > 0      # the benchmark's launch configuration
         plan = tcm.tcm_plan_create(ctx, req, use_graph=True)
         try:
             tcm.tcm_plan_run(ctx, plan)
