@@ -208,6 +208,74 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
     return out
 
 
+def scan_section(tcm, synth, torch, npos=1 << 20, L=16, oracle_samples=8):
+    """Translation scan (the paper's section IV scan shape, in all directions): B at npos
+    positions around A, B keeping one pose, L = 16, two 20k-bead chains; positions, energies and
+    statuses in device memory.  Throughput of tcm_scan_translations against the pair path
+    (tcm_batch_energy with resident moments) on the first 16384 positions, and the error
+    against the FP64 oracle on a sample."""
+    import ctypes as C
+    import oracle
+    xa, qa, _ = synth.chain(21, 1, 20_000)
+    xb, qb, _ = synth.chain(21, 2, 20_000)
+    ctx = tcm.Context(0)
+    mA = tcm.tcm_mol_upload(ctx.h, xa, qa, precision=tcm.TCM_F32C)
+    mB = tcm.tcm_mol_upload(ctx.h, xb, qb, precision=tcm.TCM_F32C)
+    cA, cB = oracle.centroid(xa), oracle.centroid(xb)
+    rho = oracle.radius(xa, cA) + oracle.radius(xb, cB)
+    rng = np.random.default_rng(77)
+    d = rng.normal(size=(npos, 3))
+    R = d / np.linalg.norm(d, axis=1)[:, None] * rng.uniform(1.1, 3.0, npos)[:, None] * rho
+    quat = np.array([0.7, 0.1, -0.5, 0.5])
+    quat /= np.linalg.norm(quat)
+    dR = torch.tensor(R, dtype=torch.float64, device="cuda")
+    dU = torch.empty(npos, dtype=torch.float64, device="cuda")
+    dS = torch.empty(npos, dtype=torch.int32, device="cuda")
+    q = np.ascontiguousarray(quat)
+    torch.cuda.synchronize()                  # R is on the device before the context's stream reads it
+
+    def scan(flags):
+        rc = tcm.lib().tcm_scan_translations(ctx.h, mA, mB, L, q.ctypes.data_as(tcm._dp), flags | tcm.TCM_DEVICE_IO,
+                                             C.cast(dR.data_ptr(), tcm._dp), npos, C.cast(dU.data_ptr(), tcm._dp),
+                                             C.cast(dS.data_ptr(), tcm._ip32))
+        assert rc == tcm.TCM_OK, rc
+
+    scan(0)                                   # moments at L, then the scan
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        scan(tcm.TCM_REUSE)
+    torch.cuda.synchronize()
+    t_scan = (time.perf_counter() - t0) / reps
+    U = dU.cpu().numpy()
+    st = dS.cpu().numpy()
+    npair = 16384
+    req = tcm.make_requests(mA, mB, R[:npair], L, quat, flags=tcm.TCM_REUSE)
+    tcm.tcm_batch_energy(ctx.h, req)
+    t0 = time.perf_counter()
+    Ub, stb, _ = tcm.tcm_batch_energy(ctx.h, req)
+    t_pair = time.perf_counter() - t0
+    QA = oracle.moments(xa, qa, cA, L)
+    QB = oracle.moments(oracle.pose(xb, cB, quat, cB), qb, cB, L)
+    errs = []
+    for k in np.linspace(0, npos - 1, oracle_samples).astype(int):
+        e = oracle.energy(QA, QB, R[k], L, full=True)
+        errs.append(abs(U[k] - e["U"]) / e["abs_sum"])
+    out = {"workload": f"two 20k-bead chains, L = {L}, {npos} positions at 1.1-3.0 (a_A + a_B) in random "
+                       "directions, one pose of B; FP32-compensated moments once, FP64 pair tensor and "
+                       "evaluation; positions and results in device memory",
+           "positions_per_s": npos / t_scan, "ms_per_scan": 1e3 * t_scan, "statuses_ok": int(np.sum(st == 0)),
+           "pair_path_positions_per_s": npair / t_pair,
+           "speedup_vs_pair_path": (npos / t_scan) / (npair / t_pair),
+           "scan_vs_pair_path_max_abs_diff": float(np.max(np.abs(U[:npair] - Ub))),
+           "max_err_over_abs_terms_vs_oracle": float(max(errs)), "oracle_samples": oracle_samples}
+    tcm.tcm_mol_release(ctx.h, mA)
+    tcm.tcm_mol_release(ctx.h, mB)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +286,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference "
                          "point for the HBM byte counters) and exit")
@@ -359,6 +428,13 @@ def main():
         log(f"bench: serving section in {time.time() - t_s:.1f}s: "
             f"saturation {serving['saturation_pairs_per_s']:.0f} pairs/s, open loop {serving['open_loop']}")
 
+    scan = None
+    if not args.no_scan:
+        t_s = time.time()
+        scan = scan_section(tcm, synth, torch)
+        log(f"bench: scan section in {time.time() - t_s:.1f}s: {scan['positions_per_s']:.3e} positions/s, "
+            f"{scan['speedup_vs_pair_path']:.0f}x the pair path, err {scan['max_err_over_abs_terms_vs_oracle']:.1e}")
+
     out = {
         "metric": "pair energies/s & p50/p99 latency at stated rel. err vs FP64 oracle",
         "value": args.npairs / (ms_step * 1e-3),
@@ -397,6 +473,7 @@ def main():
                                "traffic are per step (one launch of tcm_tiles<float, L> per order L)"},
         "cpu_baseline": cpu,
         "serving": serving,
+        "scan": scan,
     }
     print(json.dumps(out), flush=True)
 

@@ -49,7 +49,7 @@ extern "C" {
 #define TCM_EINVAL     -1   /* null pointer, n < 0, L outside [0, TCM_LMAX], non-finite input */
 #define TCM_EDOMAIN    -2   /* |R0| <= a_A + a_B: eq. 2 violated                             */
 #define TCM_ENOMEM     -3   /* device allocation failed or the HBM budget is exceeded        */
-#define TCM_EDEVICE    -4   /* HIP runtime error or an expired device-side wait               */
+#define TCM_EDEVICE    -4   /* HIP runtime error                                             */
 #define TCM_EAGAIN     -5   /* serving queue full; retry later                               */
 #define TCM_ENOTFOUND  -6   /* unknown molecule id or ticket                                 */
 
@@ -62,6 +62,8 @@ extern "C" {
 /* per-request flags */
 #define TCM_UNCHECKED  1    /* skip the eq. 2 separation test (parity tests only)            */
 #define TCM_REUSE      2    /* use the molecule's resident moments if their order is >= L    */
+#define TCM_DEVICE_IO  16   /* tcm_scan_translations: R, U_out, status_out are device         */
+                            /* pointers and the call is asynchronous on the context's stream  */
 
 typedef struct tcm_ctx tcm_ctx;
 typedef struct tcm_plan tcm_plan;
@@ -178,6 +180,25 @@ int tcm_plan_device_outputs(tcm_plan *plan, double **d_U, int32_t **d_status);
 int tcm_plan_info(tcm_plan *plan, int64_t *atoms, double *moment_flops, int64_t *tiles,
                   int64_t *pairs);
 void tcm_plan_destroy(tcm_plan *plan);
+
+/* ---- translation scan ------------------------------------------------------------ */
+
+/* Energies of molecule B at nR positions relative to A (the scan of the paper's section IV,
+ * in any directions), B keeping one orientation: quat_b (w, x, y, z), NULL = identity, as in
+ * tcm_pair_req.  R: FP64 [nR][3], each c_B - c_A.  Eq. (9) with l1, l2 <= L regrouped by
+ * L' = l1 + l2: the pair tensor G_{L'M} = sum over l1 + l2 = L', m1 + m2 = M of
+ * (-1)^{l2} Q^A_{l1 m1} Q^B_{l2 m2} (with the factorial normalisation) is built once from the
+ * moments (computed, or reused with TCM_REUSE in flags), and each position then costs
+ * O(L^2) instead of the O(L^4) of a full contraction.  U_out[nR], status_out[nR]:
+ * TCM_EDOMAIN (and NaN) where |R| <= a_A + a_B unless TCM_UNCHECKED, TCM_EINVAL where R is
+ * zero or not finite.  With TCM_DEVICE_IO, R / U_out / status_out are device pointers and the
+ * call returns once the launches are queued on the context's stream (R must be complete on
+ * the device before that stream reaches the launches); otherwise they are host arrays and the
+ * call is synchronous.  Returns TCM_ENOTFOUND for an unknown id, TCM_EINVAL
+ * for bad arguments. */
+int tcm_scan_translations(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, int L, const double *quat_b,
+                          int flags, const double *R, int64_t nR, double *U_out,
+                          int32_t *status_out);
 
 /* ---- tuning ------------------------------------------------------------------------ */
 

@@ -174,6 +174,40 @@ __device__ void rot_matvec(const double* tab, const double* in, double* out, int
     }
 }
 
+// cos / sin of m * (gamma, beta, alpha), the ZYZ Euler angles of the unit quaternion
+// q = (w, x, y, z) (R = Rz(alpha) Ry(beta) Rz(gamma)), for m = this thread's index <= L.
+__device__ inline void euler_phases(const double* quat, int m, int Lm, double* scs /*[3][Lm+1][2]*/)
+{
+    const double qn = sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+    const double w = quat[0] / qn, x = quat[1] / qn, y = quat[2] / qn, z = quat[3] / qn;
+    const double beta = 2.0 * atan2(sqrt(x * x + y * y), sqrt(w * w + z * z));
+    const double ap = atan2(z, w), am = atan2(-x, y);
+    const double ang[3] = {ap - am /*gamma*/, beta, ap + am /*alpha*/};
+    for (int k = 0; k < 3; ++k) {
+        double s, c;
+        sincos(m * ang[k], &s, &c);
+        scs[(k * (Lm + 1) + m) * 2] = c;
+        scs[(k * (Lm + 1) + m) * 2 + 1] = s;
+    }
+}
+
+// Q' = Z(alpha) D^{-1} Z(beta) D Z(gamma) Q in place on v (t: temporary of nh(L)), D = the
+// representation of a +90 degree rotation about x, Z(phi) = diag(e^{i m phi}); every thread
+// of the workgroup takes part.
+__device__ inline void rotate_moments(const double* rot, double* v, double* t, int L, int Lm, const double* scs)
+{
+    rot_phase(v, L, scs);
+    __syncthreads();
+    rot_matvec(rot, v, t, L, false);
+    __syncthreads();
+    rot_phase(t, L, scs + 2 * (Lm + 1));
+    __syncthreads();
+    rot_matvec(rot, t, v, L, true);
+    __syncthreads();
+    rot_phase(v, L, scs + 4 * (Lm + 1));
+    __syncthreads();
+}
+
 __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
 {
     // the moment launches that precede this one have finalised every table it reads
@@ -203,21 +237,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         spow[0] = 1.0;
         for (int l = 1; l <= 2 * L + 1; ++l) spow[l] = spow[l - 1] * ir;
     }
-    if (pw.has_rot && tid <= L) {
-        // ZYZ Euler angles of the unit quaternion: R = Rz(alpha) Ry(beta) Rz(gamma)
-        const double qn = sqrt(pw.quat[0] * pw.quat[0] + pw.quat[1] * pw.quat[1] +
-                               pw.quat[2] * pw.quat[2] + pw.quat[3] * pw.quat[3]);
-        const double w = pw.quat[0] / qn, x = pw.quat[1] / qn, y = pw.quat[2] / qn, z = pw.quat[3] / qn;
-        const double beta = 2.0 * atan2(sqrt(x * x + y * y), sqrt(w * w + z * z));
-        const double ap = atan2(z, w), am = atan2(-x, y);
-        const double ang[3] = {ap - am /*gamma*/, beta, ap + am /*alpha*/};
-        for (int k = 0; k < 3; ++k) {
-            double s, c;
-            sincos(tid * ang[k], &s, &c);
-            scs[(k * (Lm + 1) + tid) * 2] = c;
-            scs[(k * (Lm + 1) + tid) * 2 + 1] = s;
-        }
-    }
+    if (pw.has_rot && tid <= L) euler_phases(pw.quat, tid, Lm, scs);
     __syncthreads();
     for (int h = tid; h < NHl; h += PAIR_WG) {
         const double sc = spow[l_of(h)];
@@ -225,20 +245,7 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         sB[h] = pw.QB[h] * sc;
     }
     __syncthreads();
-    if (pw.has_rot) {
-        // Q' = Z(alpha) D^{-1} Z(beta) D Z(gamma) Q, D = representation of a +90 degree
-        // rotation about x, Z(phi) = diag(e^{i m phi})
-        rot_phase(sB, L, scs);
-        __syncthreads();
-        rot_matvec(P.rot, sB, sT, L, false);
-        __syncthreads();
-        rot_phase(sT, L, scs + 2 * (Lm + 1));
-        __syncthreads();
-        rot_matvec(P.rot, sT, sB, L, true);
-        __syncthreads();
-        rot_phase(sB, L, scs + 4 * (Lm + 1));
-        __syncthreads();
-    }
+    if (pw.has_rot) rotate_moments(P.rot, sB, sT, L, Lm, scs);
     for (int h = tid; h < NHl; h += PAIR_WG) sB[h] *= P.invf[h];
     // irregular harmonics of the unit vector n = R/|R|, factorial-scaled:
     //   I_00 = 1, I_MM = -(2M-1)(nx + i ny) I_{M-1,M-1}, I_{M+1,M} = (2M+1) nz I_MM,
@@ -326,6 +333,169 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
         P.status[pw.out] = TCM_OK;
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------------------ translation scan
+// Regrouping eq. (9) by L' = l1 + l2 and M = m1 + m2 (the geometric factor depends on them
+// only) gives, for B translated without rotation,
+//     U(R) = (1/R) sum_{L'} (rho/R)^{L'} [Re(conj(I_{L'0}) G_{L'0}) + 2 sum_{M>0} Re(conj(I_{L'M}) G_{L'M})]
+// with the pair tensor G_{L'M} = sum_{l1+l2=L', m1+m2=M} (-1)^{l2} a_{l1 m1} b_{l2 m2},
+// a = Q^A / (f rho^l), b = Q^B / (f rho^l) (f = sqrt((l+m)!(l-m)!), rho = a_A + a_B, so that
+// rho/R < 1 inside the domain of eq. (2)), I the factorial-scaled irregular harmonics of R/|R|
+// (the pair kernel's recurrences), and G_{L',-M} = (-1)^M conj(G_{L'M}) folding M < 0 in.
+//
+// With t = rho/R and u = -t (n_x + i n_y), the recurrences of I give
+//     t^{L'} I_{L'M} = (2L'-1)!! u^M p_{L'M},   p_{MM} = 1, p_{M-1,M} = 0,
+//     p_{L'M} = (n_z t) p_{L'-1,M} - gamma_{L'M} t^2 p_{L'-2,M},
+//     gamma_{L'M} = ((L'-1)^2 - M^2) / ((2L'-1)(2L'-3)),
+// so that U R = sum_M Re(conj(u^M) sum_{L'} p_{L'M} Gt_{L'M}) with Gt = w_M (2L'-1)!! G
+// (w_0 = 1, w_M = 2).  The table holds one row {Re Gt, Im Gt, gamma, 0} per (L', M),
+// column by column (M = 0 .. 2L, L' = M .. 2L): each position then costs five FP64
+// operations per row, the rows read with wave-uniform loads.  G costs O(L^4) once.
+
+__host__ __device__ constexpr int scan_col_start(int L, int M) { return M * (2 * L + 1) - M * (M - 1) / 2; }
+
+// One wave per table row: lanes take the (l1, m1) terms of G_{L'M}, a butterfly sums them.
+// Every workgroup rotates and scales its own copy of the moment tables in LDS.
+__global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, const double* QB, int L, double rho,
+                                                           const double* invf, const double* rot, int has_rot,
+                                                           double q0, double q1, double q2, double q3, double* T)
+{
+    extern __shared__ __align__(16) double sm[];        // sA, sB, sT [nh(L)], scs [3][L+1][2]
+    const int tid = threadIdx.x, NHl = nh(L);
+    double* sA = sm;
+    double* sB = sA + NHl;
+    double* sT = sB + NHl;
+    double* scs = sT + NHl;
+    const double quat[4] = {q0, q1, q2, q3};
+    if (has_rot && tid <= L) euler_phases(quat, tid, L, scs);
+    for (int h = tid; h < NHl; h += PAIR_WG) {
+        sA[h] = QA[h];
+        sB[h] = QB[h];
+    }
+    __syncthreads();
+    if (has_rot) rotate_moments(rot, sB, sT, L, L, scs);
+    for (int h = tid; h < NHl; h += PAIR_WG) {
+        const double sc = invf[h] * pow(rho, -(double)l_of(h));
+        sA[h] *= sc;
+        sB[h] *= sc;
+    }
+    __syncthreads();
+    const int e = __builtin_amdgcn_readfirstlane(blockIdx.x * (PAIR_WG / 64) + tid / 64);
+    if (e >= ni(L)) return;
+    int M = 0;
+    while (scan_col_start(L, M + 1) <= e) ++M;
+    const int Lp = M + (e - scan_col_start(L, M));
+    // a_{l m} for any m: m < 0 through a_{l,-m} = (-1)^m conj(a_lm)
+    auto get = [&](const double* v, int l, int m, double& re, double& im) {
+        const int am = m < 0 ? -m : m;
+        if (am == 0) { re = v[l * l]; im = 0.0; return; }
+        re = v[l * l + 2 * am - 1];
+        im = v[l * l + 2 * am];
+        if (m < 0) {
+            im = -im;
+            if (am & 1) { re = -re; im = -im; }
+        }
+    };
+    const int l1lo = Lp - L > 0 ? Lp - L : 0, l1hi = Lp < L ? Lp : L;
+    const int W = 2 * L + 1, nterm = (l1hi - l1lo + 1) * W;
+    double gr = 0.0, gi = 0.0;
+    for (int k = tid & 63; k < nterm; k += 64) {
+        const int l1 = l1lo + k / W, m1 = k % W - L, l2 = Lp - l1, m2 = M - m1;
+        if (m1 < -l1 || m1 > l1 || m2 < -l2 || m2 > l2) continue;
+        double ar, ai, br, bi;
+        get(sA, l1, m1, ar, ai);
+        get(sB, l2, m2, br, bi);
+        const double sg = (l2 & 1) ? -1.0 : 1.0;
+        gr += sg * (ar * br - ai * bi);
+        gi += sg * (ar * bi + ai * br);
+    }
+    gr = wave_sum(gr);
+    gi = wave_sum(gi);
+    if ((tid & 63) == 0) {
+        double kap = 1.0;                                // (2L'-1)!!
+        for (int j = 3; j <= 2 * Lp - 1; j += 2) kap *= j;
+        const double w = (M == 0 ? 1.0 : 2.0) * kap;
+        const double gam = Lp >= M + 2 ? ((Lp - 1.0) * (Lp - 1.0) - (double)M * M) / ((2.0 * Lp - 1.0) * (2.0 * Lp - 3.0))
+                                       : 0.0;
+        double* row = T + 4 * (size_t)e;
+        row[0] = w * gr;
+        row[1] = w * gi;
+        row[2] = gam;
+        row[3] = 0.0;
+    }
+}
+
+// One thread per position; the table rows are the same for every lane (scalar loads).
+__global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T, int L, double rho, double aA,
+                                                    double aB, int unchecked, const double* __restrict__ R,
+                                                    int64_t nR, double* __restrict__ U, int32_t* __restrict__ status)
+{
+    const int64_t k = blockIdx.x * (int64_t)WG + threadIdx.x;
+    if (k >= nR) return;
+    const double Rx = R[3 * k], Ry = R[3 * k + 1], Rz = R[3 * k + 2];
+    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    if (!(Rn > 0.0) || (!unchecked && !(Rn > aA + aB))) {
+        status[k] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
+        U[k] = __builtin_nan("");
+        return;
+    }
+    const double ir = 1.0 / Rn, t = rho * ir;
+    const double x = Rz * ir * t, y = t * t, ur = -t * Rx * ir, ui = -t * Ry * ir;
+    const int L2 = 2 * L;
+    double acc = 0.0, wr = 1.0, wi = 0.0;               // u^M
+    // the table is read-only here and the same for every lane: constant address space, so
+    // that its loads are scalar loads into SGPRs
+    using crow = const __attribute__((address_space(4))) double*;
+    crow row = (crow)T;
+    for (int M = 0; M <= L2; ++M) {
+        if (M > 0) {
+            const double tr = wr * ur - wi * ui;
+            wi = wr * ui + wi * ur;
+            wr = tr;
+        }
+        double Sr = row[0], Si = row[1], p1 = 1.0, p2 = 0.0;
+        row += 4;
+        int Lp = M + 1;
+        for (; Lp < L2; Lp += 2, row += 8) {            // two rows per trip
+            const double g0 = row[0], g1 = row[1], c0 = row[2], h0 = row[4], h1 = row[5], c1 = row[6];
+            const double pa = x * p1 - (c0 * y) * p2;
+            Sr += pa * g0;
+            Si += pa * g1;
+            const double pb = x * pa - (c1 * y) * p1;
+            Sr += pb * h0;
+            Si += pb * h1;
+            p2 = pa;
+            p1 = pb;
+        }
+        if (Lp == L2) {
+            const double p = x * p1 - (row[2] * y) * p2;
+            Sr += p * row[0];
+            Si += p * row[1];
+            row += 4;
+        }
+        acc += wr * Sr + wi * Si;
+    }
+    U[k] = acc * ir;
+    status[k] = TCM_OK;
+}
+
+hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
+                       const double* invf, const double* rot, const double* quat, double* T, const double* R,
+                       int64_t nR, double* U, int32_t* status, hipStream_t s)
+{
+    const int has_rot = quat && !(quat[0] > 0 && quat[1] == 0 && quat[2] == 0 && quat[3] == 0);
+    const double q[4] = {quat ? quat[0] : 1.0, quat ? quat[1] : 0.0, quat ? quat[2] : 0.0, quat ? quat[3] : 0.0};
+    const size_t tb = sizeof(double) * (3 * (size_t)nh(L) + 6 * (L + 1));
+    const int waves = PAIR_WG / 64;
+    hipLaunchKernelGGL(tcm_scan_tensor, dim3((unsigned)((ni(L) + waves - 1) / waves)), dim3(PAIR_WG), tb, s, QA, QB,
+                       L, rho, invf, rot, has_rot, q[0], q[1], q[2], q[3], T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nR <= 0) return e;
+    const int64_t blocks = (nR + WG - 1) / WG;
+    hipLaunchKernelGGL(tcm_scan_eval, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, rho, aA, aB, unchecked, R, nR, U,
+                       status);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ kernels

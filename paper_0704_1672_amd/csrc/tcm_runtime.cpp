@@ -516,7 +516,8 @@ static void destroy_streams(Workspace& ws)
 //     order a captured graph replays); with ev (5 events) the elapsed time of each step is
 //     measured on the launch stream.
 //   lanes (serial = false): the groups' tile launches are spread over s and NLANES - 1 more
-//     streams, balanced by work (largest first, each to the lightest lane).  The workgroups of
+//     streams, balanced by work (largest first, each to the lightest lane), each lane issuing
+//     its smallest launch first.  The workgroups of
 //     the two lanes' launches interleave as slots free up, so a small group's items fill the
 //     tail of a large one instead of running alone on a half-empty device.  Two streams, not
 //     one per group: the process's streams share four hardware queues, and with one stream
@@ -546,13 +547,20 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
         for (int k = 0; k < nl - 1; ++k)
             if (hipStreamWaitEvent(ws.aux[k], ws.fork, 0) != hipSuccess) return TCM_EDEVICE;
         double load[NLANES] = {};
+        std::vector<int> lanes[NLANES];
         for (int g : order) {
             int lane = 0;
             for (int k = 1; k < nl; ++k)
                 if (load[k] < load[lane]) lane = k;
             load[lane] += bp.groups[g].work;
-            if (!group_tiles(g, lane ? ws.aux[lane - 1] : s)) return TCM_EDEVICE;
+            lanes[lane].push_back(g);
         }
+        // within a lane the smallest launch first: the small groups run beside the start of
+        // the large ones, and every lane ends in a large launch whose own cheapest items fill
+        // the tail
+        for (int k = 0; k < nl; ++k)
+            for (auto it = lanes[k].rbegin(); it != lanes[k].rend(); ++it)
+                if (!group_tiles(*it, k ? ws.aux[k - 1] : s)) return TCM_EDEVICE;
         for (int k = 0; k < nl - 1; ++k) {
             if (hipEventRecord(ws.join[k], ws.aux[k]) != hipSuccess) return TCM_EDEVICE;
             if (hipStreamWaitEvent(s, ws.join[k], 0) != hipSuccess) return TCM_EDEVICE;
@@ -671,6 +679,7 @@ extern "C" void tcm_destroy(tcm_ctx* t)
     free_workspace(&c, c.ws);
     c.release(c.tmp_atoms);
     c.release(c.tmp_q);
+    c.release(c.scan_g); c.release(c.scan_r); c.release(c.scan_u); c.release(c.scan_s);
     c.release(c.t_invk);
     c.release(c.t_invf);
     c.release(c.t_rot);
@@ -1262,6 +1271,77 @@ extern "C" int tcm_tune_load(tcm_ctx* t, const char* path)
 // tile launches of a synthetic batch: copies of one molecule of n atoms (points in a ball,
 // charges in [-1, 1]), enough copies to fill the device, so the measurement reflects batched
 // throughput rather than launch latency.
+// ---------------------------------------------------------------- translation scan
+extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int L, const double* quat_b, int flags,
+                                     const double* R, int64_t nR, double* U_out, int32_t* status_out)
+{
+    if (!t || L < 0 || L > LMAX || nR < 0 || (nR > 0 && (!R || !U_out || !status_out))) return TCM_EINVAL;
+    if (nR > (int64_t(1) << 31)) return TCM_EINVAL;
+    if (quat_b) {
+        const double qq = quat_b[0] * quat_b[0] + quat_b[1] * quat_b[1] + quat_b[2] * quat_b[2] + quat_b[3] * quat_b[3];
+        if (!std::isfinite(qq) || !(qq > 0)) return TCM_EINVAL;
+    }
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    const bool dev = (flags & TCM_DEVICE_IO) != 0;
+    // moments of A and B at order L (a one-pair request, R and pose unused here)
+    tcm_pair_req req{};
+    req.a = a;
+    req.b = b;
+    req.R[0] = 1.0;
+    req.quat_b[0] = 1.0;
+    req.L = L;
+    req.flags = flags & TCM_REUSE;
+    ReqPlan rp;
+    int rc = plan_requests(c, &req, 1, (flags & TCM_REUSE) != 0, rp);
+    if (rc != TCM_OK) return rc;
+    if (rp.pre_status[0] != TCM_OK) return rp.pre_status[0];
+    if (!rp.mj.empty()) {
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, rp.mj, {}, bp, s)) != TCM_OK) return rc;
+        if ((rc = run_plan(&c, bp, s, true, nullptr)) != TCM_OK) return rc;
+        if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+        mark_computed(rp);
+    }
+    Mol* ma = c.mols[a].get();
+    Mol* mb = c.mols[b].get();
+    double meta[2][8];
+    if (hipMemcpyAsync(meta[0], ma->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(meta[1], mb->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TCM_EDEVICE;
+    const double aA = meta[0][3], aB = meta[1][3];
+    const double rho = aA + aB > 0.0 ? aA + aB : 1.0;
+    const int64_t NG = (2 * (int64_t)L + 1) * (2 * L + 2) / 2;
+    if ((rc = c.alloc(c.scan_g, sizeof(double) * 4 * NG)) != TCM_OK) return rc;   // table rows of 4 doubles
+    const double* dR = R;
+    double* dU = U_out;
+    int32_t* dS = status_out;
+    if (!dev && nR > 0) {
+        if ((rc = c.alloc(c.scan_r, sizeof(double) * 3 * nR)) != TCM_OK ||
+            (rc = c.alloc(c.scan_u, sizeof(double) * nR)) != TCM_OK ||
+            (rc = c.alloc(c.scan_s, sizeof(int32_t) * nR)) != TCM_OK)
+            return rc;
+        if (hipMemcpyAsync(c.scan_r.p, R, sizeof(double) * 3 * nR, hipMemcpyHostToDevice, s) != hipSuccess)
+            return TCM_EDEVICE;
+        dR = (const double*)c.scan_r.p;
+        dU = (double*)c.scan_u.p;
+        dS = (int32_t*)c.scan_s.p;
+    }
+    if (launch_scan((const double*)ma->moments.p, (const double*)mb->moments.p, L, rho, aA, aB,
+                    (flags & TCM_UNCHECKED) ? 1 : 0, (const double*)c.t_invf.p, (const double*)c.t_rot.p, quat_b,
+                    (double*)c.scan_g.p, dR, nR, dU, dS, s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (dev || nR == 0) return TCM_OK;
+    if (hipMemcpyAsync(U_out, dU, sizeof(double) * nR, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(status_out, dS, sizeof(int32_t) * nR, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TCM_EDEVICE;
+    return TCM_OK;
+}
+
 // Batch-aware tuning: the tile launch of each (precision, L) group of the batch is timed for
 // every candidate kper (applied to all the group's size buckets), and the fastest is kept
 // for every size bucket of the group's molecules.

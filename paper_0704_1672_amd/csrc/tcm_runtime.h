@@ -25,6 +25,9 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
 hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s);
+hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
+                       const double* invf, const double* rot, const double* quat, double* T, const double* R,
+                       int64_t nR, double* U, int32_t* status, hipStream_t s);
 
 struct Ctx;
 
@@ -120,6 +123,7 @@ struct Ctx {
     uint64_t use_clock = 0;
     Workspace ws;                  // shared by the synchronous entry points
     DevBuf tmp_atoms, tmp_q;       // one-shot uploads
+    DevBuf scan_g, scan_r, scan_u, scan_s;   // translation scan: pair-tensor table, host-side I/O
     void* hpin = nullptr;          // pinned staging for one-shot uploads
     size_t hpin_cap = 0;
     std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tcm.h")
 TCM_OK, TCM_EINVAL, TCM_EDOMAIN, TCM_ENOMEM, TCM_EDEVICE, TCM_EAGAIN, TCM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 TCM_LMAX = 32
 TCM_F64, TCM_F32C = 0, 1
-TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS, TCM_BORROW_ATOMS = 1, 2, 4, 8
+TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS, TCM_BORROW_ATOMS, TCM_DEVICE_IO = 1, 2, 4, 8, 16
 
 _dp = C.POINTER(C.c_double)
 _ip32 = C.POINTER(C.c_int32)
@@ -74,6 +74,8 @@ _SIGS = {
     "tcm_tune_set": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, C.c_int]),
     "tcm_autotune": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32, _dp]),
     "tcm_autotune_batch": (C.c_int, [_vp, _vp, C.c_int64, _dp]),
+    "tcm_scan_translations": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int, _dp, C.c_int, _dp, C.c_int64, _dp,
+                                        _ip32]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -344,6 +346,20 @@ def tcm_autotune_batch(ctx, reqs):
     _check(lib().tcm_autotune_batch(ctx, reqs.ctypes.data if len(reqs) else None, len(reqs), C.byref(ms)),
            "tcm_autotune_batch")
     return ms.value
+
+
+def tcm_scan_translations(ctx, a, b, L, R, quat_b=None, flags=0):
+    """Energies of B at the positions R ([n][3], c_B - c_A) with one pose of B; returns
+    (U[n], status[n]).  Host arrays (TCM_DEVICE_IO is for callers passing device addresses
+    through the C ABI)."""
+    R = _f64(R, (-1, 3))
+    n = len(R)
+    U = np.empty(max(n, 1))
+    st = np.empty(max(n, 1), dtype=np.int32)
+    q = _f64(quat_b, (4,)) if quat_b is not None else None
+    _check(lib().tcm_scan_translations(ctx, int(a), int(b), int(L), _p(q), int(flags), _p(R), n, _p(U),
+                                       st.ctypes.data_as(_ip32)), "tcm_scan_translations")
+    return U[:n], st[:n]
 
 
 def tcm_tune_save(ctx, path):

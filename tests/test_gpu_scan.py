@@ -1,0 +1,148 @@
+"""Translation scan (tcm_scan_translations): eq. (9) regrouped by L' = l1 + l2 through the pair
+tensor G_{L'M}, then O(L^2) per position.  Checked against the oracle's literal eq. (9) at
+every position (with and without a pose of B), against the pair path on the same positions,
+device-pointer I/O against host I/O bit for bit, and the error cases."""
+import numpy as np
+import pytest
+
+from paper_0704_1672_amd import tcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tcm.Context(0)
+    yield c.h
+    c.close()
+
+
+def directions(rng, n):
+    d = rng.normal(size=(n, 3))
+    return d / np.linalg.norm(d, axis=1)[:, None]
+
+
+@pytest.mark.parametrize("L", [0, 1, 4, 10, 16])
+@pytest.mark.parametrize("posed", [False, True])
+def test_scan_matches_oracle(ctx, orc, synth, L, posed):
+    w = synth.ball_pair(seed=1)
+    cA, cB = w["cA"], w["cB"]
+    mA = tcm.tcm_mol_upload(ctx, w["xyzA"], w["qA"], centre=cA, precision=tcm.TCM_F64)
+    mB = tcm.tcm_mol_upload(ctx, w["xyzB"], w["qB"], centre=cB, precision=tcm.TCM_F64)
+    try:
+        rho = orc.radius(w["xyzA"], cA) + orc.radius(w["xyzB"], cB)
+        rng = np.random.default_rng(100 + L)
+        R = directions(rng, 48) * rng.uniform(0.8, 3.0, 48)[:, None] * rho   # some inside a_A + a_B
+        quat = synth.quaternions(7, L, 1)[0] if posed else None
+        U, st = tcm.tcm_scan_translations(ctx, mA, mB, L, R, quat_b=quat)
+        QA = orc.moments(w["xyzA"], w["qA"], cA, L)
+        xB = orc.pose(w["xyzB"], cB, quat, cB) if posed else w["xyzB"]
+        QB = orc.moments(xB, w["qB"], cB, L)
+        for k in range(len(R)):
+            if not np.linalg.norm(R[k]) > rho:
+                assert st[k] == tcm.TCM_EDOMAIN and np.isnan(U[k])
+                continue
+            d = orc.energy(QA, QB, R[k], L, full=True)
+            assert st[k] == tcm.TCM_OK
+            assert abs(U[k] - d["U"]) <= (1e-11 if posed else 1e-12) * d["abs_sum"], (k, U[k], d["U"])
+        assert np.sum(st == tcm.TCM_EDOMAIN) > 0 and np.sum(st == tcm.TCM_OK) > 0
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+        tcm.tcm_mol_release(ctx, mB)
+
+
+def test_scan_matches_pair_path(ctx, orc, synth):
+    xa, qa, _ = synth.chain(3, 1, 4000)
+    xb, qb, _ = synth.chain(3, 2, 6000)
+    L = 12
+    for prec in (tcm.TCM_F64, tcm.TCM_F32C):
+        mA = tcm.tcm_mol_upload(ctx, xa, qa, precision=prec)
+        mB = tcm.tcm_mol_upload(ctx, xb, qb, precision=prec)
+        try:
+            cA, cB = orc.centroid(xa), orc.centroid(xb)
+            rho = orc.radius(xa, cA) + orc.radius(xb, cB)
+            rng = np.random.default_rng(5)
+            R = directions(rng, 200) * rng.uniform(1.05, 4.0, 200)[:, None] * rho
+            quat = [0.3, -0.4, 0.5, 0.7]
+            U, st = tcm.tcm_scan_translations(ctx, mA, mB, L, R, quat_b=quat)
+            Ub, stb, _ = tcm.tcm_batch_energy(ctx, tcm.make_requests(mA, mB, R, L, quat, flags=tcm.TCM_REUSE))
+            assert np.all(st == 0) and np.all(stb == 0)
+            # the same moments, two summation orders of eq. (9)
+            d = orc.energy(orc.moments(xa, qa, cA, L), orc.moments(orc.pose(xb, cB, quat, cB), qb, cB, L), R[0], L,
+                           full=True)
+            assert np.max(np.abs(U - Ub)) <= 1e-11 * d["abs_sum"]
+        finally:
+            tcm.tcm_mol_release(ctx, mA)
+            tcm.tcm_mol_release(ctx, mB)
+
+
+def test_scan_device_io_equals_host(ctx, synth):
+    import ctypes as C
+    import torch
+    xa, qa, _ = synth.chain(4, 1, 3000)
+    xb, qb, _ = synth.chain(4, 2, 3000)
+    mA = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F32C)
+    mB = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F32C)
+    try:
+        R = np.tile([400.0, 0.0, 0.0], (1000, 1)) + np.linspace(0, 300, 1000)[:, None] * [0.3, 0.9, -0.2]
+        U, st = tcm.tcm_scan_translations(ctx, mA, mB, 14, R)
+        dR = torch.tensor(R, dtype=torch.float64, device="cuda")
+        dU = torch.empty(len(R), dtype=torch.float64, device="cuda")
+        dS = torch.empty(len(R), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        rc = tcm.lib().tcm_scan_translations(ctx, mA, mB, 14, None, tcm.TCM_DEVICE_IO | tcm.TCM_REUSE,
+                                             C.cast(dR.data_ptr(), tcm._dp), len(R), C.cast(dU.data_ptr(), tcm._dp),
+                                             C.cast(dS.data_ptr(), tcm._ip32))
+        assert rc == tcm.TCM_OK
+        torch.cuda.synchronize()                # the context's stream is torch's current one
+        assert np.array_equal(dU.cpu().numpy(), U) and np.array_equal(dS.cpu().numpy(), st)
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+        tcm.tcm_mol_release(ctx, mB)
+
+
+def test_scan_edge_cases(ctx, synth):
+    xa, qa, _ = synth.chain(5, 1, 500)
+    mA = tcm.tcm_mol_upload(ctx, xa, qa)
+    try:
+        U, st = tcm.tcm_scan_translations(ctx, mA, mA, 6, np.zeros((0, 3)))
+        assert len(U) == 0
+        U, st = tcm.tcm_scan_translations(ctx, mA, mA, 6, [[0.0, 0.0, 0.0], [1e5, 0, 0]])
+        assert st[0] == tcm.TCM_EINVAL and np.isnan(U[0]) and st[1] == tcm.TCM_OK
+        with pytest.raises(tcm.TCMError) as e:
+            tcm.tcm_scan_translations(ctx, mA, 987654, 6, [[1e5, 0, 0]])
+        assert e.value.code == tcm.TCM_ENOTFOUND
+        with pytest.raises(tcm.TCMError) as e:
+            tcm.tcm_scan_translations(ctx, mA, mA, 33, [[1e5, 0, 0]])
+        assert e.value.code == tcm.TCM_EINVAL
+        with pytest.raises(tcm.TCMError):
+            tcm.tcm_scan_translations(ctx, mA, mA, 6, [[1e5, 0, 0]], quat_b=[0, 0, 0, 0])
+        # unchecked: positions inside a_A + a_B are evaluated (parity use only)
+        U, st = tcm.tcm_scan_translations(ctx, mA, mA, 4, [[1.0, 0, 0]], flags=tcm.TCM_UNCHECKED)
+        assert st[0] == tcm.TCM_OK and np.isfinite(U[0])
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+
+
+def test_plane_scan_section_iv_shape(ctx, orc, synth):
+    # the paper's scan shape: B translated in the xy-plane over a grid of (R0, Theta) around A;
+    # two chains of 2900 beads stand in for the protein pair
+    xa, qa, _ = synth.chain(6, 1, 2900)
+    xb, qb, _ = synth.chain(6, 2, 2900)
+    cA, cB = orc.centroid(xa), orc.centroid(xb)
+    rho = orc.radius(xa, cA) + orc.radius(xb, cB)
+    r0 = np.linspace(1.05, 1.8, 10) * rho
+    th = np.radians(np.arange(0, 360, 5))
+    R = np.array([[r * np.cos(t), r * np.sin(t), 0.0] for r in r0 for t in th])
+    mA = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F32C)
+    mB = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F32C)
+    try:
+        U, st = tcm.tcm_scan_translations(ctx, mA, mB, 10, R)
+        assert np.all(st == 0)
+        QA, QB = orc.moments(xa, qa, cA, 10), orc.moments(xb, qb, cB, 10)
+        for k in range(0, len(R), 37):
+            d = orc.energy(QA, QB, R[k], 10, full=True)
+            assert abs(U[k] - d["U"]) <= 1e-5 * d["abs_sum"], (k, U[k], d["U"])
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+        tcm.tcm_mol_release(ctx, mB)
