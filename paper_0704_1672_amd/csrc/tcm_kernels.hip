@@ -426,58 +426,97 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, con
     }
 }
 
-// One thread per position; the table rows are the same for every lane (scalar loads).
+// SCAN_NP positions per thread (k, k + WG, ...: each a coalesced run of the workgroup), so
+// that every table row loaded into SGPRs feeds SCAN_NP positions' arithmetic.
+constexpr int SCAN_NP = 2;
+
 __global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T, int L, double rho, double aA,
                                                     double aB, int unchecked, const double* __restrict__ R,
                                                     int64_t nR, double* __restrict__ U, int32_t* __restrict__ status)
 {
-    const int64_t k = blockIdx.x * (int64_t)WG + threadIdx.x;
-    if (k >= nR) return;
-    const double Rx = R[3 * k], Ry = R[3 * k + 1], Rz = R[3 * k + 2];
-    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-    if (!(Rn > 0.0) || (!unchecked && !(Rn > aA + aB))) {
-        status[k] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
-        U[k] = __builtin_nan("");
-        return;
+    const int64_t k0 = blockIdx.x * (int64_t)(WG * SCAN_NP) + threadIdx.x;
+    double x[SCAN_NP], y[SCAN_NP], ur[SCAN_NP], ui[SCAN_NP], ir[SCAN_NP], acc[SCAN_NP], wr[SCAN_NP], wi[SCAN_NP];
+    int st[SCAN_NP];
+#pragma unroll
+    for (int j = 0; j < SCAN_NP; ++j) {
+        const int64_t k = k0 + j * WG;
+        st[j] = TCM_EINVAL;
+        x[j] = y[j] = ur[j] = ui[j] = ir[j] = 0.0;
+        if (k < nR) {
+            const double Rx = R[3 * k], Ry = R[3 * k + 1], Rz = R[3 * k + 2];
+            const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+            if (Rn > 0.0 && (unchecked || Rn > aA + aB)) {
+                st[j] = TCM_OK;
+                ir[j] = 1.0 / Rn;
+                const double t = rho * ir[j];
+                x[j] = Rz * ir[j] * t;
+                y[j] = t * t;
+                ur[j] = -t * Rx * ir[j];
+                ui[j] = -t * Ry * ir[j];
+            } else if (Rn > 0.0) {
+                st[j] = TCM_EDOMAIN;
+            }
+        }
+        acc[j] = 0.0;
+        wr[j] = 1.0;                                     // u^M
+        wi[j] = 0.0;
     }
-    const double ir = 1.0 / Rn, t = rho * ir;
-    const double x = Rz * ir * t, y = t * t, ur = -t * Rx * ir, ui = -t * Ry * ir;
     const int L2 = 2 * L;
-    double acc = 0.0, wr = 1.0, wi = 0.0;               // u^M
     // the table is read-only here and the same for every lane: constant address space, so
     // that its loads are scalar loads into SGPRs
     using crow = const __attribute__((address_space(4))) double*;
     crow row = (crow)T;
     for (int M = 0; M <= L2; ++M) {
-        if (M > 0) {
-            const double tr = wr * ur - wi * ui;
-            wi = wr * ui + wi * ur;
-            wr = tr;
+        double Sr[SCAN_NP], Si[SCAN_NP], p1[SCAN_NP], p2[SCAN_NP];
+#pragma unroll
+        for (int j = 0; j < SCAN_NP; ++j) {
+            if (M > 0) {
+                const double tr = wr[j] * ur[j] - wi[j] * ui[j];
+                wi[j] = wr[j] * ui[j] + wi[j] * ur[j];
+                wr[j] = tr;
+            }
+            Sr[j] = row[0];
+            Si[j] = row[1];
+            p1[j] = 1.0;
+            p2[j] = 0.0;
         }
-        double Sr = row[0], Si = row[1], p1 = 1.0, p2 = 0.0;
         row += 4;
         int Lp = M + 1;
         for (; Lp < L2; Lp += 2, row += 8) {            // two rows per trip
             const double g0 = row[0], g1 = row[1], c0 = row[2], h0 = row[4], h1 = row[5], c1 = row[6];
-            const double pa = x * p1 - (c0 * y) * p2;
-            Sr += pa * g0;
-            Si += pa * g1;
-            const double pb = x * pa - (c1 * y) * p1;
-            Sr += pb * h0;
-            Si += pb * h1;
-            p2 = pa;
-            p1 = pb;
+#pragma unroll
+            for (int j = 0; j < SCAN_NP; ++j) {
+                const double pa = x[j] * p1[j] - (c0 * y[j]) * p2[j];
+                Sr[j] += pa * g0;
+                Si[j] += pa * g1;
+                const double pb = x[j] * pa - (c1 * y[j]) * p1[j];
+                Sr[j] += pb * h0;
+                Si[j] += pb * h1;
+                p2[j] = pa;
+                p1[j] = pb;
+            }
         }
         if (Lp == L2) {
-            const double p = x * p1 - (row[2] * y) * p2;
-            Sr += p * row[0];
-            Si += p * row[1];
+            const double g0 = row[0], g1 = row[1], c0 = row[2];
+#pragma unroll
+            for (int j = 0; j < SCAN_NP; ++j) {
+                const double p = x[j] * p1[j] - (c0 * y[j]) * p2[j];
+                Sr[j] += p * g0;
+                Si[j] += p * g1;
+            }
             row += 4;
         }
-        acc += wr * Sr + wi * Si;
+#pragma unroll
+        for (int j = 0; j < SCAN_NP; ++j) acc[j] += wr[j] * Sr[j] + wi[j] * Si[j];
     }
-    U[k] = acc * ir;
-    status[k] = TCM_OK;
+#pragma unroll
+    for (int j = 0; j < SCAN_NP; ++j) {
+        const int64_t k = k0 + j * WG;
+        if (k < nR) {
+            U[k] = st[j] == TCM_OK ? acc[j] * ir[j] : __builtin_nan("");
+            status[k] = st[j];
+        }
+    }
 }
 
 hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
@@ -492,7 +531,7 @@ hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, do
                        L, rho, invf, rot, has_rot, q[0], q[1], q[2], q[3], T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nR <= 0) return e;
-    const int64_t blocks = (nR + WG - 1) / WG;
+    const int64_t blocks = (nR + WG * SCAN_NP - 1) / (WG * SCAN_NP);
     hipLaunchKernelGGL(tcm_scan_eval, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, rho, aA, aB, unchecked, R, nR, U,
                        status);
     return hipGetLastError();

@@ -970,6 +970,7 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
         rp.mj.push_back(j);
         rp.computed.push_back({m, L});
         m->Lcached = -1;                      // invalid until this run completes
+        m->radius_host = -1.0;
     }
     for (int64_t i = 0; i < np; ++i) {
         if (rp.pre_status[i] != TCM_OK) continue;
@@ -998,7 +999,10 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
 
 void mark_computed(ReqPlan& rp)
 {
-    for (auto& pr : rp.computed) pr.first->Lcached = pr.second;
+    for (auto& pr : rp.computed) {
+        pr.first->Lcached = pr.second;
+        pr.first->radius_host = -1.0;
+    }
 }
 }  // namespace tcm
 
@@ -1028,6 +1032,7 @@ extern "C" int tcm_mol_moments(tcm_ctx* t, tcm_mol_id id, int L, int flags, doub
         j.Q = (double*)m->moments.p;
         j.meta = (double*)m->meta.p;
         m->Lcached = -1;
+        m->radius_host = -1.0;
         BuiltPlan bp;
         if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) return rc;
         if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
@@ -1307,12 +1312,16 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
     }
     Mol* ma = c.mols[a].get();
     Mol* mb = c.mols[b].get();
-    double meta[2][8];
-    if (hipMemcpyAsync(meta[0], ma->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(meta[1], mb->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return TCM_EDEVICE;
-    const double aA = meta[0][3], aB = meta[1][3];
+    if (ma->radius_host < 0.0 || mb->radius_host < 0.0) {   // radii of eq. 2, read once per computation
+        double meta[2][8];
+        if (hipMemcpyAsync(meta[0], ma->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(meta[1], mb->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return TCM_EDEVICE;
+        ma->radius_host = meta[0][3];
+        mb->radius_host = meta[1][3];
+    }
+    const double aA = ma->radius_host, aB = mb->radius_host;
     const double rho = aA + aB > 0.0 ? aA + aB : 1.0;
     const int64_t NG = (2 * (int64_t)L + 1) * (2 * L + 2) / 2;
     if ((rc = c.alloc(c.scan_g, sizeof(double) * 4 * NG)) != TCM_OK) return rc;   // table rows of 4 doubles

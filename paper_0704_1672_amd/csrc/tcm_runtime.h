@@ -51,6 +51,8 @@ struct Mol {
     DevBuf moments;                // (Lcap+1)^2 FP64 resident moments
     DevBuf meta;                   // 5 FP64: centre, radius, scale
     int Lcached = -1;              // order of valid resident moments (-1: none)
+    double radius_host = -1.0;     // meta[3] read back to the host, -1 until then; reset
+                                   // whenever the moments are recomputed
     uint64_t last_use = 0;
 };
 

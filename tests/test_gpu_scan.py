@@ -146,3 +146,48 @@ def test_plane_scan_section_iv_shape(ctx, orc, synth):
     finally:
         tcm.tcm_mol_release(ctx, mA)
         tcm.tcm_mol_release(ctx, mB)
+
+
+def test_scan_ragged_counts_are_prefixes(ctx, synth):
+    # every position is evaluated alone: any count (one or two per thread, ragged tails)
+    # gives the same value at the same position, bit for bit
+    xa, qa, _ = synth.chain(8, 1, 3000)
+    xb, qb, _ = synth.chain(8, 2, 2000)
+    mA = tcm.tcm_mol_upload(ctx, xa, qa)
+    mB = tcm.tcm_mol_upload(ctx, xb, qb)
+    try:
+        rng = np.random.default_rng(9)
+        R = directions(rng, 1100) * rng.uniform(200.0, 400.0, 1100)[:, None]
+        Uall, sall = tcm.tcm_scan_translations(ctx, mA, mB, 12, R)
+        for n in (1, 2, 255, 256, 257, 511, 512, 513, 1023):
+            U, st = tcm.tcm_scan_translations(ctx, mA, mB, 12, R[:n], flags=tcm.TCM_REUSE)
+            assert np.array_equal(st, sall[:n]) and np.array_equal(U, Uall[:n], equal_nan=True), n
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+        tcm.tcm_mol_release(ctx, mB)
+
+
+def test_scan_radius_follows_recomputed_moments(ctx, synth):
+    # caller-owned atoms change in place: without TCM_REUSE the moments and the radius of
+    # eq. 2 are recomputed, so a position that was outside a_A + a_B falls inside
+    import torch
+    xa, qa, _ = synth.chain(9, 1, 1000)
+    soa = torch.tensor(np.vstack([xa.T, qa[None]]), dtype=torch.float64, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    base, row = soa.data_ptr(), soa.shape[1] * 8
+    mA = tcm.tcm_mol_register_device(ctx, base, base + row, base + 2 * row, base + 3 * row, len(qa))
+    try:
+        c = xa.mean(axis=0)
+        a = np.max(np.linalg.norm(xa - c, axis=1))
+        R = np.array([[2.5 * a, 0.0, 0.0]])
+        U, st = tcm.tcm_scan_translations(ctx, mA, mA, 6, R)
+        assert st[0] == tcm.TCM_OK
+        soa[0:3] *= 2.0                                  # radius doubles: 2.5 a < 2 (2 a)
+        torch.cuda.synchronize()
+        U2, st2 = tcm.tcm_scan_translations(ctx, mA, mA, 6, R, flags=tcm.TCM_REUSE)
+        assert st2[0] == tcm.TCM_OK and U2[0] == U[0]    # resident moments and radius reused
+        U3, st3 = tcm.tcm_scan_translations(ctx, mA, mA, 6, R)
+        assert st3[0] == tcm.TCM_EDOMAIN and np.isnan(U3[0])
+    finally:
+        tcm.tcm_mol_release(ctx, mA)
+        del soa
