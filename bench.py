@@ -276,6 +276,41 @@ def scan_section(tcm, synth, torch, npos=1 << 20, L=16, oracle_samples=8):
     return out
 
 
+def all_pairs_section(tcm, synth, K=256, L=8, reps=5):
+    """Every pair of K chain fragments in place (log-uniform 2k..20k beads on a cubic grid
+    wide enough that no two overlap): moments once per fragment, then K(K-1)/2 contractions.
+    Timed as a first call (moments + centres + contractions) and as calls reusing the
+    resident moments."""
+    counts = np.floor(np.exp(np.random.default_rng(41).uniform(np.log(2e3), np.log(2e4), K))).astype(np.int64)
+    xyz, q, off, _ = synth.chains(41, 1, counts, nthreads=min(16, os.cpu_count() or 1))
+    side = int(np.ceil(K ** (1 / 3)))
+    ctx = tcm.Context(0)
+    ids = []
+    for k in range(K):
+        x = xyz[off[k]:off[k + 1]]
+        g = np.array([k % side, (k // side) % side, k // (side * side)], dtype=float) * 600.0
+        ids.append(tcm.tcm_mol_upload(ctx.h, x - x.mean(axis=0) + g, q[off[k]:off[k + 1]], precision=tcm.TCM_F32C))
+    t0 = time.perf_counter()
+    U, st = tcm.tcm_all_pairs(ctx.h, ids, L)
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U2, _ = tcm.tcm_all_pairs(ctx.h, ids, L, flags=tcm.TCM_REUSE)
+    t_reuse = (time.perf_counter() - t0) / reps
+    npairs = len(U)
+    out = {"workload": f"{K} chain fragments in place ({int(counts.sum())} atoms, log-uniform 2e3..2e4 beads, "
+                       f"600 A grid), L = {L}, FP32-compensated moments, FP64 contractions, host I/O",
+           "pairs": npairs, "statuses_ok": int(np.sum(st == 0)),
+           "first_call_ms": 1e3 * t_first, "pairs_per_s_first_call": npairs / t_first,
+           "reuse_call_ms": 1e3 * t_reuse, "pairs_per_s_reuse": npairs / t_reuse,
+           "reuse_equal_bitwise": bool(np.array_equal(U, U2)),
+           "system_energy": float(np.sum(U[st == 0]))}
+    for i in ids:
+        tcm.tcm_mol_release(ctx.h, i)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +322,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-scan", action="store_true")
+    ap.add_argument("--no-all-pairs", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference "
                          "point for the HBM byte counters) and exit")
@@ -435,6 +471,14 @@ def main():
         log(f"bench: scan section in {time.time() - t_s:.1f}s: {scan['positions_per_s']:.3e} positions/s, "
             f"{scan['speedup_vs_pair_path']:.0f}x the pair path, err {scan['max_err_over_abs_terms_vs_oracle']:.1e}")
 
+    all_pairs = None
+    if not args.no_all_pairs:
+        t_s = time.time()
+        all_pairs = all_pairs_section(tcm, synth)
+        log(f"bench: all-pairs section in {time.time() - t_s:.1f}s: {all_pairs['pairs']} pairs, first call "
+            f"{all_pairs['first_call_ms']:.1f} ms, reuse {all_pairs['reuse_call_ms']:.1f} ms "
+            f"({all_pairs['pairs_per_s_reuse']:.3e} pairs/s)")
+
     out = {
         "metric": "pair energies/s & p50/p99 latency at stated rel. err vs FP64 oracle",
         "value": args.npairs / (ms_step * 1e-3),
@@ -474,6 +518,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "scan": scan,
+        "all_pairs": all_pairs,
     }
     print(json.dumps(out), flush=True)
 

@@ -200,6 +200,19 @@ int tcm_scan_translations(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, int L, const
                           int flags, const double *R, int64_t nR, double *U_out,
                           int32_t *status_out);
 
+/* Interaction energies of every pair of K resident fragments in place (the many-fragment
+ * use of eq. (9) that the paper's outlook names): each fragment's moments once at order L
+ * (reused with TCM_REUSE in flags), then the K(K-1)/2 contractions with R = c_j - c_i (no
+ * pose; the centres are those of the moment pass, given or centroid).  U_out and
+ * status_out: host arrays of K(K-1)/2 in row-major upper-triangle order, pair (i, j), i < j,
+ * at index i*K - i*(i+1)/2 + (j - i - 1).  Pairs closer than a_i + a_j return TCM_EDOMAIN
+ * (NaN) unless TCM_UNCHECKED; their interaction is outside the expansion's domain (eq. 2)
+ * and left to the caller.  The system's inter-fragment energy is the sum of the valid
+ * entries.  K <= 11585 (K(K-1)/2 <= 2^26).  Returns the first per-pair error, TCM_ENOTFOUND
+ * for an unknown id, TCM_EINVAL for bad arguments. */
+int tcm_all_pairs(tcm_ctx *ctx, const tcm_mol_id *ids, int64_t K, int L, int flags,
+                  double *U_out, int32_t *status_out);
+
 /* ---- tuning ------------------------------------------------------------------------ */
 
 /* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */

@@ -1057,13 +1057,9 @@ static int first_error(const int32_t* st, int64_t n)
     return TCM_OK;
 }
 
-extern "C" int tcm_batch_energy(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
+// The batch path with the context locked and current.
+static int batch_energy_locked(Ctx& c, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
 {
-    if (!t || np < 0 || (np > 0 && (!reqs || !U_out || !status_out))) return TCM_EINVAL;
-    if (np > (1 << 26)) return TCM_EINVAL;
-    Ctx& c = t->c;
-    std::lock_guard<std::mutex> g(c.mu);
-    (void)hipSetDevice(c.device);
     hipStream_t s = c.stream;
     ReqPlan rp;
     int rc = plan_requests(c, reqs, np, true, rp);
@@ -1088,6 +1084,75 @@ extern "C" int tcm_batch_energy(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np
         U_out[rp.pj_req[k]] = st[k] == TCM_OK ? U[k] : std::nan("");
     }
     return first_error(status_out, np);
+}
+
+extern "C" int tcm_batch_energy(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
+{
+    if (!t || np < 0 || (np > 0 && (!reqs || !U_out || !status_out))) return TCM_EINVAL;
+    if (np > (1 << 26)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    return batch_energy_locked(c, reqs, np, U_out, status_out);
+}
+
+// Every pair of K resident fragments at their own positions: the moments of each fragment
+// once (order L), the centres read back, then one batch of K(K-1)/2 contractions with
+// R = c_j - c_i.
+extern "C" int tcm_all_pairs(tcm_ctx* t, const tcm_mol_id* ids, int64_t K, int L, int flags, double* U_out,
+                             int32_t* status_out)
+{
+    if (!t || K < 0 || (K > 0 && !ids) || L < 0 || L > LMAX) return TCM_EINVAL;
+    const int64_t np = K * (K - 1) / 2;
+    if (K > 11585 || (np > 0 && (!U_out || !status_out))) return TCM_EINVAL;   // np <= 2^26
+    if (np == 0) return TCM_OK;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    for (int64_t i = 0; i < K; ++i)
+        if (c.mols.find(ids[i]) == c.mols.end()) return TCM_ENOTFOUND;
+    // moments (and centres) of every fragment: one request per fragment, paired with itself
+    std::vector<tcm_pair_req> one((size_t)K);
+    for (int64_t i = 0; i < K; ++i) {
+        one[i] = tcm_pair_req{};
+        one[i].a = one[i].b = ids[i];
+        one[i].R[0] = 1.0;
+        one[i].quat_b[0] = 1.0;
+        one[i].L = L;
+        one[i].flags = flags & TCM_REUSE;
+    }
+    ReqPlan rp;
+    int rc = plan_requests(c, one.data(), K, (flags & TCM_REUSE) != 0, rp);
+    if (rc != TCM_OK) return rc;
+    if ((rc = first_error(rp.pre_status.data(), K)) != TCM_OK) return rc;
+    if (!rp.mj.empty()) {
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, rp.mj, {}, bp, s)) != TCM_OK) return rc;
+        if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+        if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+        mark_computed(rp);
+    }
+    std::vector<double> meta((size_t)K * 8);
+    for (int64_t i = 0; i < K; ++i)
+        if (hipMemcpyAsync(&meta[(size_t)i * 8], c.mols[ids[i]]->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost,
+                           s) != hipSuccess)
+            return TCM_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    std::vector<tcm_pair_req> reqs((size_t)np);
+    int64_t k = 0;
+    for (int64_t i = 0; i < K; ++i)
+        for (int64_t j = i + 1; j < K; ++j, ++k) {
+            tcm_pair_req& r = reqs[(size_t)k];
+            r = tcm_pair_req{};
+            r.a = ids[i];
+            r.b = ids[j];
+            for (int d = 0; d < 3; ++d) r.R[d] = meta[(size_t)j * 8 + d] - meta[(size_t)i * 8 + d];
+            r.quat_b[0] = 1.0;
+            r.L = L;
+            r.flags = (flags & TCM_UNCHECKED) | TCM_REUSE;
+        }
+    return batch_energy_locked(c, reqs.data(), np, U_out, status_out);
 }
 
 // ---------------------------------------------------------------- plans (graph replay)

@@ -76,6 +76,7 @@ _SIGS = {
     "tcm_autotune_batch": (C.c_int, [_vp, _vp, C.c_int64, _dp]),
     "tcm_scan_translations": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int, _dp, C.c_int, _dp, C.c_int64, _dp,
                                         _ip32]),
+    "tcm_all_pairs": (C.c_int, [_vp, _ip64, C.c_int64, C.c_int, C.c_int, _dp, _ip32]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -360,6 +361,25 @@ def tcm_scan_translations(ctx, a, b, L, R, quat_b=None, flags=0):
     _check(lib().tcm_scan_translations(ctx, int(a), int(b), int(L), _p(q), int(flags), _p(R), n, _p(U),
                                        st.ctypes.data_as(_ip32)), "tcm_scan_translations")
     return U[:n], st[:n]
+
+
+def tcm_all_pairs(ctx, ids, L, flags=0):
+    """Energies of every pair (i < j) of the resident fragments ids at their own positions;
+    returns (U, status), each K(K-1)/2 long in row-major upper-triangle order."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    K = len(ids)
+    n = K * (K - 1) // 2
+    U = np.empty(max(n, 1))
+    st = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib().tcm_all_pairs(ctx, ids.ctypes.data_as(_ip64), K, int(L), int(flags), _p(U), st.ctypes.data_as(_ip32))
+    if rc in (TCM_EINVAL, TCM_ENOMEM, TCM_EDEVICE, TCM_ENOTFOUND) and np.all(st[:n] == 0):
+        raise TCMError(rc, "tcm_all_pairs")
+    return U[:n], st[:n]
+
+
+def pair_index(i, j, K):
+    """Index of pair (i, j), i < j, in tcm_all_pairs' output."""
+    return i * K - i * (i + 1) // 2 + (j - i - 1)
 
 
 def tcm_tune_save(ctx, path):

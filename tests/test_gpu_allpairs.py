@@ -1,0 +1,97 @@
+"""Every pair of K fragments in place (tcm_all_pairs): the moments of each fragment once, then
+K(K-1)/2 contractions with R = c_j - c_i.  Checked pair by pair against the oracle, against
+the batch path with the same requests (bit for bit), the output order, overlapping pairs
+(eq. 2) and the error cases."""
+import numpy as np
+import pytest
+
+from paper_0704_1672_amd import tcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tcm.Context(0)
+    yield c.h
+    c.close()
+
+
+def fragments(synth, K, seed, spacing, close=None):
+    """K chain fragments of 300..900 beads on a cubic grid `spacing` apart (fragment `close`
+    moved next to fragment 0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(K):
+        x, q, _ = synth.chain(seed, 10 + k, int(rng.integers(300, 900)))
+        g = np.array([k % 3, (k // 3) % 3, k // 9], dtype=float) * spacing
+        x = x - x.mean(axis=0) + g
+        out.append((x, q))
+    if close is not None:
+        x0 = out[0][0]
+        x, q = out[close]
+        out[close] = (x - x.mean(axis=0) + x0.mean(axis=0) + np.array([5.0, 0.0, 0.0]), q)
+    return out
+
+
+def test_all_pairs_match_oracle_and_batch(ctx, orc, synth):
+    K, L = 7, 8
+    fr = fragments(synth, K, 31, 400.0)
+    ids = [tcm.tcm_mol_upload(ctx, x, q, precision=tcm.TCM_F64) for x, q in fr]
+    try:
+        U, st = tcm.tcm_all_pairs(ctx, ids, L)
+        assert len(U) == K * (K - 1) // 2 and np.all(st == 0)
+        cs = [orc.centroid(x) for x, _ in fr]
+        Q = [orc.moments(x, q, c, L) for (x, q), c in zip(fr, cs)]
+        req = []
+        for i in range(K):
+            for j in range(i + 1, K):
+                k = tcm.pair_index(i, j, K)
+                d = orc.energy(Q[i], Q[j], cs[j] - cs[i], L, full=True)
+                assert abs(U[k] - d["U"]) <= 1e-12 * d["abs_sum"], (i, j, U[k], d["U"])
+                req.append((ids[i], ids[j], cs[j] - cs[i]))
+        # the same contractions through the batch path (host-computed centres): equal up to
+        # the last bits of R; bit for bit once R is taken from the device centres
+        Ub, stb, _ = tcm.tcm_batch_energy(ctx, tcm.make_requests([r[0] for r in req], [r[1] for r in req],
+                                                                 np.array([r[2] for r in req]), L,
+                                                                 flags=tcm.TCM_REUSE))
+        assert np.all(stb == 0) and np.allclose(U, Ub, rtol=1e-12, atol=0)
+        cen = []
+        for i in ids:
+            _, _, c = tcm.tcm_mol_moments(ctx, i, L, flags=tcm.TCM_REUSE)
+            cen.append(c)
+        Rd = np.array([cen[j] - cen[i] for i in range(K) for j in range(i + 1, K)])
+        Ub2, _, _ = tcm.tcm_batch_energy(ctx, tcm.make_requests([r[0] for r in req], [r[1] for r in req], Rd, L,
+                                                                flags=tcm.TCM_REUSE))
+        assert np.array_equal(U, Ub2)
+        # reusing the resident moments gives the same values
+        U2, _ = tcm.tcm_all_pairs(ctx, ids, L, flags=tcm.TCM_REUSE)
+        assert np.array_equal(U, U2)
+    finally:
+        for i in ids:
+            tcm.tcm_mol_release(ctx, i)
+
+
+def test_all_pairs_overlap_and_errors(ctx, synth):
+    K = 5
+    fr = fragments(synth, K, 32, 400.0, close=3)
+    ids = [tcm.tcm_mol_upload(ctx, x, q) for x, q in fr]
+    try:
+        U, st = tcm.tcm_all_pairs(ctx, ids, 6)
+        k03 = tcm.pair_index(0, 3, K)
+        assert st[k03] == tcm.TCM_EDOMAIN and np.isnan(U[k03])
+        others = np.delete(np.arange(len(st)), k03)
+        assert np.all(st[others] == 0) and np.all(np.isfinite(U[others]))
+        U, st = tcm.tcm_all_pairs(ctx, ids, 6, flags=tcm.TCM_UNCHECKED)
+        assert st[k03] == tcm.TCM_OK and np.isfinite(U[k03])
+        assert len(tcm.tcm_all_pairs(ctx, ids[:1], 6)[0]) == 0
+        assert len(tcm.tcm_all_pairs(ctx, [], 6)[0]) == 0
+        with pytest.raises(tcm.TCMError) as e:
+            tcm.tcm_all_pairs(ctx, ids + [987654], 6)
+        assert e.value.code == tcm.TCM_ENOTFOUND
+        with pytest.raises(tcm.TCMError) as e:
+            tcm.tcm_all_pairs(ctx, ids, 33)
+        assert e.value.code == tcm.TCM_EINVAL
+    finally:
+        for i in ids:
+            tcm.tcm_mol_release(ctx, i)
