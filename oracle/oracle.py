@@ -43,6 +43,12 @@ def load():
     lib.oracle_pose.restype = C.c_int
     lib.oracle_trunc_bound.argtypes = [C.c_double] * 5 + [C.c_int]
     lib.oracle_trunc_bound.restype = C.c_double
+    lib.oracle_energy_grad.argtypes = [_dp, C.c_int, _dp, C.c_int, _dp, C.c_int, _dp]
+    lib.oracle_energy_grad.restype = C.c_int
+    lib.oracle_energy_coeffs.argtypes = [_dp, C.c_int, _dp, C.c_int, _dp, C.c_int, C.c_int, _dp]
+    lib.oracle_energy_coeffs.restype = C.c_int
+    lib.oracle_atom_forces.argtypes = [_dp, C.c_int, _dp, _dp, C.c_int64, _dp, _dp]
+    lib.oracle_atom_forces.restype = C.c_int
     _LIB = lib
     return lib
 
@@ -180,3 +186,63 @@ def pair_energy_from_atoms(xyzA, qA, cA, xyzB, qB, cB, L, full=False):
     QB = moments(xyzB, qB, cB, L)
     R = _f64(cB, (3,)) - _f64(cA, (3,))
     return energy(QA, QB, R, L, full=full)
+
+
+def _interleave(Q):
+    Q = np.asarray(Q, dtype=np.complex128)
+    out = np.empty(2 * len(Q))
+    out[0::2] = Q.real
+    out[1::2] = Q.imag
+    return out
+
+
+def energy_grad(QA, QB, R, L):
+    """grad_R0 of eq. (9) with the moments fixed; the force on B is its negative."""
+    qa, qb = _interleave(QA), _interleave(QB)
+    g = np.zeros(3)
+    rc = load().oracle_energy_grad(_p(qa), order_of(QA), _p(qb), order_of(QB), _p(_f64(R, (3,))), int(L), _p(g))
+    if rc != 0:
+        raise ValueError(f"oracle_energy_grad failed ({rc})")
+    return g
+
+
+def energy_coeffs(QA, QB, R, L, side):
+    """Complex (L+1)^2 table W with U = Re sum W * Q^B (side 1) or Re sum W * Q^A (side 0)."""
+    qa, qb = _interleave(QA), _interleave(QB)
+    W = np.zeros(2 * (L + 1) ** 2)
+    rc = load().oracle_energy_coeffs(_p(qa), order_of(QA), _p(qb), order_of(QB), _p(_f64(R, (3,))), int(L),
+                                     int(side), _p(W))
+    if rc != 0:
+        raise ValueError(f"oracle_energy_coeffs failed ({rc})")
+    return W[0::2] + 1j * W[1::2]
+
+
+def atom_forces(W, xyz, q, c):
+    """Per-atom forces F[n][3] = -dU/dR_i at fixed centre c for U = Re sum W * Q(eq. 8)."""
+    xyz = _f64(xyz, (-1, 3))
+    q = _f64(q, (-1,))
+    w = _interleave(W)
+    F = np.zeros((len(q), 3))
+    rc = load().oracle_atom_forces(_p(w), order_of(W), _p(xyz), _p(q), len(q), _p(_f64(c, (3,))), _p(F))
+    if rc != 0:
+        raise ValueError(f"oracle_atom_forces failed ({rc})")
+    return F
+
+
+def pair_forces(xyzA, qA, cA, xyzB, qB, cB, R, L, quat=None):
+    """Forces and torques of the truncated energy of A (atoms xyzA about centre cA) and B
+    (atoms xyzB about cB, posed by quat about cB, then placed at cA + R):
+    U, F_B = -grad_R U (F_A = -F_B), the per-atom forces FA[nA][3] and FB[nB][3] at fixed
+    centres (FB on the posed atoms), and the torques about each centre,
+    tau = sum_i (x_i - c) x F_i."""
+    xB = pose(xyzB, cB, quat, cB) if quat is not None else _f64(xyzB, (-1, 3))
+    QA = moments(xyzA, qA, cA, L)
+    QB = moments(xB, qB, cB, L)
+    U = energy(QA, QB, R, L)
+    FB_c = -energy_grad(QA, QB, R, L)
+    FA = atom_forces(energy_coeffs(QA, QB, R, L, 0), xyzA, qA, cA)
+    FB = atom_forces(energy_coeffs(QA, QB, R, L, 1), xB, qB, cB)
+    tA = np.sum(np.cross(_f64(xyzA, (-1, 3)) - cA, FA), axis=0)
+    tB = np.sum(np.cross(xB - cB, FB), axis=0)
+    return dict(U=U, F_B=FB_c, FA=FA, FB=FB, tau_A=tA, tau_B=tB, QA=QA, QB=QB)
+

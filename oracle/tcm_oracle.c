@@ -15,7 +15,12 @@
  *   - eq. (9)  truncated two-centre energy, square truncation l1,l2 <= Lmax
  *                                                          -> oracle_energy
  * plus two test helpers that are not in the paper: the rigid pose of a molecule
- * (oracle_pose) and a rigorous truncation-error bound (oracle_trunc_bound).
+ * (oracle_pose) and a rigorous truncation-error bound (oracle_trunc_bound), and the
+ * forces the paper names as the other use of its final expression (section I):
+ *   - -grad_R0 of eq. (9), term by term                   -> oracle_energy_grad
+ *   - the coefficients of eq. (9) as a linear function of one molecule's moments
+ *                                                          -> oracle_energy_coeffs
+ *   - per-atom forces at fixed centres, through eq. (8)   -> oracle_atom_forces
  *
  * Conventions (the paper is silent; readings listed in the design notes):
  *   - Y_lm carries the Condon-Shortley phase; Y_{l,-m} = (-1)^m conj(Y_lm).
@@ -316,6 +321,232 @@ int oracle_energy(const double *QA, int LA, const double *QB, int LB, const doub
     *U_re = nsum_value(&sre);
     if (U_im) *U_im = nsum_value(&sim);
     if (abs_sum) *abs_sum = nsum_value(&sab);
+    free(P);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Derivatives of the solid harmonics for the forces (not printed in the paper; textbook
+ * calculus on its eq. (8) and eq. (9) ingredients).
+ *
+ * For a direction theta, three tables over l <= L, 0 <= m <= l (index l*(l+1)/2 + m):
+ *   P = Pbar_l^m(cos theta)                      (legendre_normalised)
+ *   S = Pbar_l^m(cos theta) / sin(theta), m >= 1 (the same three-term recurrence in l,
+ *       started from Pbar_m^m / sin = -sqrt((2m+1)/(2m)) Pbar_{m-1}^{m-1}: no division, so
+ *       it holds on the axis too)
+ *   D = d Pbar_l^m / d theta:  m = 0: sqrt(l(l+1)) Pbar_l^1;
+ *       m >= 1: (sqrt((l-m)(l+m+1)) Pbar_l^{m+1} - sqrt((l+m)(l-m+1)) Pbar_l^{m-1}) / 2
+ *       (Condon-Shortley phase).
+ * ------------------------------------------------------------------------------- */
+static void legendre_derivs(int L, double ct, double st, double *P, double *S, double *D)
+{
+    legendre_normalised(L, ct, st, P);
+    for (int k = 0; k < (L + 1) * (L + 2) / 2; ++k) S[k] = 0.0;
+    for (int m = 1; m <= L; ++m) {
+        int i = m * (m + 1) / 2 + m, j = (m - 1) * m / 2 + (m - 1);
+        S[i] = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * P[j];
+        if (m + 1 <= L) S[(m + 1) * (m + 2) / 2 + m] = sqrt(2.0 * m + 3.0) * ct * S[i];
+        for (int l = m + 2; l <= L; ++l) {
+            double a = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+            double b = sqrt((((double)l - 1.0) * (l - 1.0) - (double)m * m) /
+                            (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+            S[l * (l + 1) / 2 + m] = a * (ct * S[(l - 1) * l / 2 + m] - b * S[(l - 2) * (l - 1) / 2 + m]);
+        }
+    }
+    for (int l = 0; l <= L; ++l) {
+        for (int m = 0; m <= l; ++m) {
+            double up = m + 1 <= l ? P[l * (l + 1) / 2 + m + 1] : 0.0;
+            if (m == 0)
+                D[l * (l + 1) / 2] = sqrt((double)l * (l + 1)) * up;
+            else
+                D[l * (l + 1) / 2 + m] = 0.5 * (sqrt((double)(l - m) * (l + m + 1)) * up -
+                                                sqrt((double)(l + m) * (l - m + 1)) * P[l * (l + 1) / 2 + m - 1]);
+        }
+    }
+}
+
+/* Gradient of g = r^p Y_lm(theta, phi) (any m in [-l, l]) at the point (r, theta, phi), as
+ * 3 complex components (re, im interleaved) in out[6]:
+ *   grad g = r^{p-1} e^{i m phi} [ p Pbar r_hat + dPbar/dtheta theta_hat + i m (Pbar/sin) phi_hat ],
+ * with negative m through Y_{l,-m} = (-1)^m conj(Y_lm).  The tables P, S, D are those of the
+ * point's theta (order >= l).  p = l gives the regular solid harmonic (up to the factor
+ * sqrt(4 pi/(2l+1))), p = -(l+1) the irregular one. */
+static void grad_solid(int l, int m, int p, double r, double theta, double phi, const double *P,
+                       const double *S, const double *D, double *out)
+{
+    int am = m < 0 ? -m : m;
+    int k = l * (l + 1) / 2 + am;
+    double ct = cos(theta), st = sin(theta), cp = cos(phi), sp = sin(phi);
+    double rh[3] = {st * cp, st * sp, ct}, th[3] = {ct * cp, ct * sp, -st}, ph[3] = {-sp, cp, 0.0};
+    double rp = (p - 1 == 0) ? 1.0 : pow(r, (double)(p - 1));
+    double er = cos(am * phi), ei = sin(am * phi);
+    for (int d = 0; d < 3; ++d) {
+        /* v = p P rh + D th + i m S ph  (m >= 0 part) */
+        double vr = p * P[k] * rh[d] + D[k] * th[d];
+        double vi = am > 0 ? am * S[k] * ph[d] : 0.0;
+        double gr = rp * (vr * er - vi * ei), gi = rp * (vr * ei + vi * er);
+        if (m < 0) {
+            double sg = (am & 1) ? -1.0 : 1.0;
+            gr = sg * gr;
+            gi = -sg * gi;
+        }
+        out[2 * d] = gr;
+        out[2 * d + 1] = gi;
+    }
+}
+
+/* ---------------------------------------------------------------------------------
+ * grad_R0 of eq. (9): the same literal sum as oracle_energy with R0^{-(L'+1)} conj(Y_{L'M})
+ * replaced by its gradient in R0 (the moments held fixed: B translated rigidly).  The force
+ * on B is -grad, the force on A +grad.  Output grad[3].
+ * ------------------------------------------------------------------------------- */
+int oracle_energy_grad(const double *QA, int LA, const double *QB, int LB, const double *R, int L,
+                       double *grad)
+{
+    fact_init();
+    if (!QA || !QB || !R || !grad || L < 0 || L > LA || L > LB || 2 * L > 4 * ORACLE_LMAX) return -1;
+    double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (!(Rn > 0.0)) return -1;
+    double ctr = R[2] / Rn;
+    if (ctr > 1.0) ctr = 1.0;
+    if (ctr < -1.0) ctr = -1.0;
+    double Theta = acos(ctr), Phi = atan2(R[1], R[0]);
+    int L2 = 2 * L, nt = (L2 + 1) * (L2 + 2) / 2;
+    double *P = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
+    if (!P) return -3;
+    double *S = P + nt, *D = S + nt;
+    legendre_derivs(L2, cos(Theta), sin(Theta), P, S, D);
+    nsum_t g[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int l1 = 0; l1 <= L; ++l1) {
+        for (int l2 = 0; l2 <= L; ++l2) {
+            int Lp = l1 + l2;
+            double coef = (double)sqrtl(4.0L * (long double)M_PI * fact(2 * Lp) /
+                                        (fact(2 * l1) * fact(2 * l2)));
+            for (int m1 = -l1; m1 <= l1; ++m1) {
+                const double *a = QA + 2 * (l1 * l1 + l1 + m1);
+                for (int m2 = -l2; m2 <= l2; ++m2) {
+                    const double *b = QB + 2 * (l2 * l2 + l2 + m2);
+                    int M = m1 + m2;
+                    double tj = oracle_threej(l1, l2, Lp, m1, m2, -M);
+                    if (tj == 0.0) continue;
+                    double gy[6];
+                    grad_solid(Lp, M, -(Lp + 1), Rn, Theta, Phi, P, S, D, gy);
+                    double sgn = (((l1 + M) % 2) + 2) % 2 ? -1.0 : 1.0;
+                    double f = sgn * coef * tj;
+                    double abr = a[0] * b[0] - a[1] * b[1];
+                    double abi = a[0] * b[1] + a[1] * b[0];
+                    for (int d = 0; d < 3; ++d) {
+                        /* Re(f a b conj(gy_d)) */
+                        nsum_add(&g[d], f * (abr * gy[2 * d] + abi * gy[2 * d + 1]));
+                    }
+                }
+            }
+        }
+    }
+    for (int d = 0; d < 3; ++d) grad[d] = nsum_value(&g[d]);
+    free(P);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * eq. (9) is bilinear in the two moment tables.  side = 1: W with U = Re sum_{l2 m2}
+ * W_{l2 m2} Q^B_{l2 m2}, i.e. W_{l2 m2} = sum_{l1 m1} (the eq. (9) factor) Q^A_{l1 m1}
+ * R0^{-(L'+1)} conj(Y_{L'M}); side = 0: the same with the roles of the tables exchanged
+ * (U = Re sum V_{l1 m1} Q^A_{l1 m1}).  Output: 2 (L+1)^2 doubles, layout of oracle_moments.
+ * ------------------------------------------------------------------------------- */
+int oracle_energy_coeffs(const double *QA, int LA, const double *QB, int LB, const double *R, int L,
+                         int side, double *W)
+{
+    fact_init();
+    if (!QA || !QB || !R || !W || L < 0 || L > LA || L > LB || 2 * L > 4 * ORACLE_LMAX) return -1;
+    double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (!(Rn > 0.0)) return -1;
+    double ctr = R[2] / Rn;
+    if (ctr > 1.0) ctr = 1.0;
+    if (ctr < -1.0) ctr = -1.0;
+    double Theta = acos(ctr), Phi = atan2(R[1], R[0]);
+    int L2 = 2 * L, nc = (L + 1) * (L + 1);
+    double *P = (double *)malloc(sizeof(double) * (size_t)(L2 + 1) * (L2 + 2) / 2);
+    nsum_t *acc = (nsum_t *)calloc((size_t)2 * nc, sizeof(nsum_t));
+    if (!P || !acc) { free(P); free(acc); return -3; }
+    legendre_normalised(L2, cos(Theta), sin(Theta), P);
+    for (int l1 = 0; l1 <= L; ++l1) {
+        for (int l2 = 0; l2 <= L; ++l2) {
+            int Lp = l1 + l2;
+            double coef = (double)sqrtl(4.0L * (long double)M_PI * fact(2 * Lp) /
+                                        (fact(2 * l1) * fact(2 * l2)));
+            double rpow = pow(Rn, -(double)(Lp + 1));
+            for (int m1 = -l1; m1 <= l1; ++m1) {
+                for (int m2 = -l2; m2 <= l2; ++m2) {
+                    int M = m1 + m2;
+                    double tj = oracle_threej(l1, l2, Lp, m1, m2, -M);
+                    if (tj == 0.0) continue;
+                    int aM = M < 0 ? -M : M;
+                    double p = P[Lp * (Lp + 1) / 2 + aM];
+                    double yr = p * cos(aM * Phi), yi = p * sin(aM * Phi);
+                    if (M < 0) {
+                        double s = (aM & 1) ? -1.0 : 1.0;
+                        yr = s * yr;
+                        yi = -s * yi;
+                    }
+                    yi = -yi; /* conjugate */
+                    double sgn = (((l1 + M) % 2) + 2) % 2 ? -1.0 : 1.0;
+                    double f = sgn * rpow * coef * tj;
+                    /* coefficient of the other table's entry: f * Q_this * conj(Y) */
+                    const double *o = side ? QA + 2 * (l1 * l1 + l1 + m1) : QB + 2 * (l2 * l2 + l2 + m2);
+                    int k = side ? l2 * l2 + l2 + m2 : l1 * l1 + l1 + m1;
+                    nsum_add(&acc[2 * k], f * (o[0] * yr - o[1] * yi));
+                    nsum_add(&acc[2 * k + 1], f * (o[0] * yi + o[1] * yr));
+                }
+            }
+        }
+    }
+    for (int k = 0; k < 2 * nc; ++k) W[k] = nsum_value(&acc[k]);
+    free(P);
+    free(acc);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Per-atom forces at fixed centres: with U = Re sum_{lm} W_lm Q_lm (oracle_energy_coeffs)
+ * and Q_lm = sum_i q_i r_i^l sqrt(4 pi/(2l+1)) Y_lm(r_i) (eq. (8)), the force on atom i is
+ *   F_i = -dU/dR_i = -q_i Re sum_{lm} W_lm sqrt(4 pi/(2l+1)) grad(r^l Y_lm)(r_i),
+ * r_i = xyz_i - c (the rigid pose, if any, already applied to xyz).  W: order L, layout of
+ * oracle_moments.  Output F[n][3].
+ * ------------------------------------------------------------------------------- */
+int oracle_atom_forces(const double *W, int L, const double *xyz, const double *q, int64_t n, const double *c,
+                       double *F)
+{
+    if (!W || !xyz || !q || !c || !F || n < 0 || L < 0 || L > ORACLE_LMAX) return -1;
+    int nt = (L + 1) * (L + 2) / 2;
+    double *P = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
+    if (!P) return -3;
+    double *S = P + nt, *D = S + nt;
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = xyz[3 * i] - c[0], dy = xyz[3 * i + 1] - c[1], dz = xyz[3 * i + 2] - c[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double theta = 0.0, phi = 0.0;
+        if (r > 0.0) {
+            double ctr = dz / r;
+            if (ctr > 1.0) ctr = 1.0;
+            if (ctr < -1.0) ctr = -1.0;
+            theta = acos(ctr);
+            phi = atan2(dy, dx);
+        }
+        legendre_derivs(L, cos(theta), sin(theta), P, S, D);
+        nsum_t f[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int l = 1; l <= L; ++l) {                 /* l = 0 is constant */
+            if (r == 0.0 && l > 1) break;              /* grad r^l Y_lm vanishes at 0 for l > 1 */
+            double racah = sqrt(4.0 * M_PI / (2.0 * l + 1.0));
+            for (int m = -l; m <= l; ++m) {
+                double g[6];
+                grad_solid(l, m, l, r, theta, phi, P, S, D, g);
+                const double *w = W + 2 * (l * l + l + m);
+                for (int d = 0; d < 3; ++d) nsum_add(&f[d], racah * (w[0] * g[2 * d] - w[1] * g[2 * d + 1]));
+            }
+        }
+        for (int d = 0; d < 3; ++d) F[3 * i + d] = -q[i] * nsum_value(&f[d]);
+    }
     free(P);
     return 0;
 }
