@@ -200,6 +200,24 @@ int tcm_scan_translations(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, int L, const
                           int flags, const double *R, int64_t nR, double *U_out,
                           int32_t *status_out);
 
+/* Forces and torques of the truncated energy of one pair (the paper names forces between the
+ * fragments as the other use of its final expression; the derivatives are those of eq. (9)
+ * as truncated, l1, l2 <= L).  Request fields as in tcm_pair_req; flags: TCM_REUSE,
+ * TCM_UNCHECKED, TCM_DEVICE_IO.  out[10] (host): U, F_B[3] = -grad_R U (the force on B's
+ * centre for a rigid translation of B; F_A = -F_B), tau_A[3] and tau_B[3] (torques about
+ * each centre for a rigid rotation, tau = -dU/dtheta; tau_A + tau_B + R x F_B = 0).
+ * forces_A / forces_B (may be NULL): FP64 [n][3] forces on each atom at fixed centres,
+ * F_i = -dU/dx_i through eq. (8), B's in the posed frame (atoms at c_B + Rot(quat_b)(x - c_B));
+ * host arrays, or device pointers with TCM_DEVICE_IO.  Per-atom forces are zero at L = 0.
+ * Returns the pair's status: TCM_EDOMAIN when |R| <= a_A + a_B (out and host force arrays
+ * NaN, device force arrays undefined), TCM_ENOTFOUND, TCM_EINVAL. */
+int tcm_pair_forces(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, const double R[3], const double quat_b[4],
+                    int L, int flags, double out[10], double *forces_A, double *forces_B);
+/* tcm_pair_forces' out[10] for a batch of requests (no per-atom forces): out[npairs][10],
+ * status_out[npairs]; failed items NaN.  Returns the first per-item error. */
+int tcm_batch_forces(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *out,
+                     int32_t *status_out);
+
 /* Interaction energies of every pair of K resident fragments in place (the many-fragment
  * use of eq. (9) that the paper's outlook names): each fragment's moments once at order L
  * (reused with TCM_REUSE in flags), then the K(K-1)/2 contractions with R = c_j - c_i (no

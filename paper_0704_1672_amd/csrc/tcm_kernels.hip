@@ -537,6 +537,333 @@ hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, do
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ forces and torques
+// With a = Q^A / (f R^l), b = Q^B / (f R^l) (f = sqrt((l+m)!(l-m)!), B posed) and the
+// factorial-scaled irregular harmonics I of n = R/|R| (the pair kernel's recurrences), eq. (9)
+// reads U = (1/R) Re sum (-1)^{l2} a_{l1 m1} b_{l2 m2} conj(I_{l1+l2, m1+m2}).  The solid
+// harmonics I_{L'M}(R)/R^{L'+1} obey unit ladders: d/dz -> -I_{L'+1,M}, (d/dx + i d/dy) ->
+// I_{L'+1,M+1}, (d/dx - i d/dy) -> -I_{L'+1,M-1}, so with
+//     S = sum (-1)^{l2} a b conj(I_{L'+1, M+1}),   Z = sum (-1)^{l2} a b conj(I_{L'+1, M})
+// the gradient of U in R is (Re S, -Im S, -Re Z) / R^2 and the force on B is its negative.
+// Rotating B about its centre by a small angle about axis k moves each moment by the
+// generator J_k = (k x r).grad acting on its harmonic: J_z b_lm = i m b_lm,
+// J_+ b_lm = i (l+m+1) b_{l,m+1}, J_- b_lm = i (l-m+1) b_{l,m-1} (J_x = (J_+ + J_-)/2,
+// J_y = (J_+ - J_-)/(2i)); the torque on B is tau_B = -(1/R) Re sum W (J b) with
+// W_{l2 m2} = sum (-1)^{l2} a conj(I_{L'M}) (U = (1/R) Re sum b W), and likewise for A with
+// V_{l1 m1} = sum (-1)^{l2} b conj(I_{L'M}).
+//
+// Per-atom forces at fixed centres: with What = W / R^{l+1} (the coefficients of U in the
+// moments of eq. (8) divided by f) and the factorial-scaled regular harmonics Rh of the
+// atom's position about its centre (d/dz Rh_lm = Rh_{l-1,m}, (d/dx + i d/dy) Rh_lm =
+// Rh_{l-1,m+1}, (d/dx - i d/dy) Rh_lm = -Rh_{l-1,m-1}), the force on atom i is
+//     F_i = -q_i sum_{l' < L, m' >= 0} (Re(X Rh), Im(Y Rh), Re(Z Rh))_{l' m'},
+// X = P - N, Y = P + N, Z = w_m' What_{l'+1, m'}, P = What_{l'+1, m'-1} (m' = 0:
+// -conj(What_{l'+1, 1})), N = What_{l'+1, m'+1} (m' >= 1, else 0), w = 1 (m' = 0) or 2.
+constexpr int FT_NSUM = 10;        // U, Z, Re S, Im S, dU/dtheta_B (3), dU/dtheta_A (3)
+constexpr int ATAB_ROW = 8;        // Xr Xi Yr Yi Zr Zi c1 c2
+
+__host__ __device__ constexpr int ni1(int Lm) { return (2 * Lm + 2) * (2 * Lm + 3) / 2; }
+__host__ __device__ constexpr int nrows(int L) { return (L + 1) * (L + 2) / 2; }
+__host__ __device__ constexpr int atab_rows(int L) { return L * (L + 1) / 2; }
+__host__ __device__ constexpr size_t ft_smem_bytes(int Lm)
+{
+    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni1(Lm) + (2 * Lm + 3) + 6 * (Lm + 1) +
+                             (PAIR_WG / 64) * FT_NSUM);
+}
+
+// Entry (l, m) of a real-packed table for any m in [-l, l] (v_{l,-m} = (-1)^m conj(v_lm)).
+__device__ __forceinline__ void cget(const double* v, int l, int m, double& re, double& im)
+{
+    const int am = m < 0 ? -m : m;
+    if (am > l) { re = 0.0; im = 0.0; return; }
+    if (am == 0) { re = v[l * l]; im = 0.0; return; }
+    re = v[l * l + 2 * am - 1];
+    im = v[l * l + 2 * am];
+    if (m < 0) {
+        im = -im;
+        if (am & 1) { re = -re; im = -im; }
+    }
+}
+
+// conj(I_{Lp, M}) for any M (I_{L,-M} = (-1)^M conj(I_LM)); sI indexed Lp(Lp+1)/2 + M, M >= 0.
+__device__ __forceinline__ void iconj(const double* sI, int Lp, int M, double& re, double& im)
+{
+    const int aM = M < 0 ? -M : M;
+    if (aM > Lp) { re = 0.0; im = 0.0; return; }
+    const double* e = sI + 2 * (Lp * (Lp + 1) / 2 + aM);
+    re = e[0];
+    im = -e[1];
+    if (M < 0) {                           // conj((-1)^M conj(I)) = (-1)^M I
+        im = -im;
+        if (aM & 1) { re = -re; im = -im; }
+    }
+}
+
+// (J_x v, J_y v, J_z v) at (l, m) for a real-packed table v (complex, interleaved in j[6]).
+__device__ __forceinline__ void jvec(const double* v, int l, int m, double* j)
+{
+    double br, bi, dr, di, ur, ui;
+    cget(v, l, m, br, bi);
+    cget(v, l, m - 1, dr, di);
+    cget(v, l, m + 1, ur, ui);
+    const double cp = l + m + 1, cm = l - m + 1;
+    // J_x = (i/2)(cp v_{m+1} + cm v_{m-1}),  J_y = (1/2)(cp v_{m+1} - cm v_{m-1}),  J_z = i m v
+    const double sr = cp * ur + cm * dr, si = cp * ui + cm * di;
+    j[0] = -0.5 * si;
+    j[1] = 0.5 * sr;
+    j[2] = 0.5 * (cp * ur - cm * dr);
+    j[3] = 0.5 * (cp * ui - cm * di);
+    j[4] = -m * bi;
+    j[5] = m * br;
+}
+
+// One workgroup per pair: FT[out][10] = (U, F_B, tau_A, tau_B); wscr (when not null) gets
+// What (side B) then Vhat (side A), nrows(L) complex each, for the per-atom tables atab
+// (when not null: side A then side B, atab_rows(L) rows of ATAB_ROW doubles each).
+__device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem, double* FT, double* wscr,
+                                             double* atab)
+{
+    const PairWork& pw = P.pairs[p];
+    const int tid = threadIdx.x;
+    const int L = pw.L, NHl = nh(L);
+    const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
+    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    const double aA = pw.metaA[3], aB = pw.metaB[3];
+    double* out = FT + (size_t)FT_NSUM * pw.out;
+    if (!(Rn > 0.0) || (!(pw.flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
+        if (tid < FT_NSUM) out[tid] = __builtin_nan("");
+        return;
+    }
+    const int Lm = P.pair_lmax;
+    double* sA = reinterpret_cast<double*>(smem);
+    double* sB = sA + nh(Lm);
+    double* sI = sB + nh(Lm);                // complex, index L'(L'+1)/2 + M, L' <= 2L + 1
+    double* sT = sI;                         // rotation temporary (before sI is built)
+    double* spow = sI + 2 * ni1(Lm);         // R^-k, k <= 2L + 2
+    double* scs = spow + (2 * Lm + 3);
+    double* red = scs + 6 * (Lm + 1);        // [waves][FT_NSUM]
+    if (tid == 0) {
+        const double ir = 1.0 / Rn;
+        spow[0] = 1.0;
+        for (int l = 1; l <= 2 * L + 2; ++l) spow[l] = spow[l - 1] * ir;
+    }
+    if (pw.has_rot && tid <= L) euler_phases(pw.quat, tid, Lm, scs);
+    __syncthreads();
+    for (int h = tid; h < NHl; h += PAIR_WG) {
+        const double sc = spow[l_of(h)];
+        sA[h] = pw.QA[h] * sc * P.invf[h];
+        sB[h] = pw.QB[h] * sc;
+    }
+    __syncthreads();
+    if (pw.has_rot) rotate_moments(P.rot, sB, sT, L, Lm, scs);
+    for (int h = tid; h < NHl; h += PAIR_WG) sB[h] *= P.invf[h];
+    const int L2 = 2 * L + 1;
+    if (tid <= L2) {                         // column M of the irregular harmonics, L' = M .. 2L+1
+        const int M = tid;
+        const double nx = Rx / Rn, ny = Ry / Rn, nz = Rz / Rn;
+        double cr = 1.0, ci = 0.0;
+        for (int k = 1; k <= M; ++k) {
+            const double f = -(2.0 * k - 1.0);
+            const double tr = f * (cr * nx - ci * ny);
+            ci = f * (cr * ny + ci * nx);
+            cr = tr;
+        }
+        double pr = 0.0, pi = 0.0, qr = cr, qi = ci;
+        sI[2 * (M * (M + 1) / 2 + M)] = cr;
+        sI[2 * (M * (M + 1) / 2 + M) + 1] = ci;
+        for (int Lp = M + 1; Lp <= L2; ++Lp) {
+            const double a = 2.0 * Lp - 1.0, b = (Lp - 1.0) * (Lp - 1.0) - (double)M * M;
+            const double nr = a * nz * qr - b * pr, nim = a * nz * qi - b * pi;
+            pr = qr; pi = qi; qr = nr; qi = nim;
+            sI[2 * (Lp * (Lp + 1) / 2 + M)] = nr;
+            sI[2 * (Lp * (Lp + 1) / 2 + M) + 1] = nim;
+        }
+    }
+    __syncthreads();
+    double acc[FT_NSUM];
+    for (int k = 0; k < FT_NSUM; ++k) acc[k] = 0.0;
+    const int nr = nrows(L);
+    for (int r = tid; r < 2 * nr; r += PAIR_WG) {
+        const bool sideB = r < nr;
+        const int rr = sideB ? r : r - nr;
+        int l = 0;
+        while ((l + 1) * (l + 2) / 2 <= rr) ++l;
+        const int m = rr - l * (l + 1) / 2;
+        const double w = m == 0 ? 1.0 : 2.0;
+        double j[6];
+        if (sideB) {                         // row (l2, m2) = (l, m): W, Wz, Wp, Wm
+            double Wr = 0, Wi = 0, Zr = 0, Zi = 0, Pr = 0, Pi = 0, Nr = 0, Ni = 0;
+            for (int l1 = 0; l1 <= L; ++l1) {
+                const int Lp = l1 + l;
+                for (int m1 = -l1; m1 <= l1; ++m1) {
+                    double ar, ai, cr, ci;
+                    cget(sA, l1, m1, ar, ai);
+                    const int M = m1 + m;
+                    iconj(sI, Lp, M, cr, ci);
+                    Wr += ar * cr - ai * ci;
+                    Wi += ar * ci + ai * cr;
+                    iconj(sI, Lp + 1, M, cr, ci);
+                    Zr += ar * cr - ai * ci;
+                    Zi += ar * ci + ai * cr;
+                    iconj(sI, Lp + 1, M + 1, cr, ci);
+                    Pr += ar * cr - ai * ci;
+                    Pi += ar * ci + ai * cr;
+                    iconj(sI, Lp + 1, M - 1, cr, ci);
+                    Nr += ar * cr - ai * ci;
+                    Ni += ar * ci + ai * cr;
+                }
+            }
+            if (l & 1) { Wr = -Wr; Wi = -Wi; Zr = -Zr; Zi = -Zi; Pr = -Pr; Pi = -Pi; Nr = -Nr; Ni = -Ni; }
+            double br, bi;
+            cget(sB, l, m, br, bi);
+            acc[0] += w * (br * Wr - bi * Wi);
+            acc[1] += w * (br * Zr - bi * Zi);
+            double sr = br * Pr - bi * Pi, si = br * Pi + bi * Pr;
+            if (m > 0) {                     // - conj(b Wm)
+                sr -= br * Nr - bi * Ni;
+                si += br * Ni + bi * Nr;
+            }
+            acc[2] += sr;
+            acc[3] += si;
+            jvec(sB, l, m, j);
+            for (int d = 0; d < 3; ++d) acc[4 + d] += w * (Wr * j[2 * d] - Wi * j[2 * d + 1]);
+            if (wscr) {
+                wscr[2 * rr] = Wr * spow[l + 1];
+                wscr[2 * rr + 1] = Wi * spow[l + 1];
+            }
+        } else {                             // row (l1, m1) = (l, m): V
+            double Vr = 0, Vi = 0;
+            for (int l2 = 0; l2 <= L; ++l2) {
+                const int Lp = l + l2;
+                double vr = 0, vi = 0;
+                for (int m2 = -l2; m2 <= l2; ++m2) {
+                    double br, bi, cr, ci;
+                    cget(sB, l2, m2, br, bi);
+                    iconj(sI, Lp, m + m2, cr, ci);
+                    vr += br * cr - bi * ci;
+                    vi += br * ci + bi * cr;
+                }
+                if (l2 & 1) { Vr -= vr; Vi -= vi; } else { Vr += vr; Vi += vi; }
+            }
+            jvec(sA, l, m, j);
+            for (int d = 0; d < 3; ++d) acc[7 + d] += w * (Vr * j[2 * d] - Vi * j[2 * d + 1]);
+            if (wscr) {
+                wscr[2 * (nr + rr)] = Vr * spow[l + 1];
+                wscr[2 * (nr + rr) + 1] = Vi * spow[l + 1];
+            }
+        }
+    }
+    for (int k = 0; k < FT_NSUM; ++k) acc[k] = wave_sum(acc[k]);
+    if ((tid & 63) == 0)
+        for (int k = 0; k < FT_NSUM; ++k) red[(tid >> 6) * FT_NSUM + k] = acc[k];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        double t[FT_NSUM];
+        for (int k = 0; k < FT_NSUM; ++k) {
+            t[k] = 0.0;
+            for (int wv = 0; wv < PAIR_WG / 64; ++wv) t[k] += red[wv * FT_NSUM + k];
+        }
+        const double ir = spow[1], ir2 = spow[2];
+        out[0] = t[0] * ir;
+        out[1] = -t[2] * ir2;                // F_B = -grad U = -(Re S, -Im S, -Z) / R^2
+        out[2] = t[3] * ir2;
+        out[3] = t[1] * ir2;
+        for (int d = 0; d < 3; ++d) {
+            out[4 + d] = -t[7 + d] * ir;     // tau_A
+            out[7 + d] = -t[4 + d] * ir;     // tau_B
+        }
+    }
+    if (!atab || !wscr || L == 0) return;
+    // per-atom tables, column by column (m' = 0 .. L-1, l' = m' .. L-1)
+    const int na = atab_rows(L);
+    for (int e = tid; e < 2 * na; e += PAIR_WG) {
+        const int side = e < na ? 0 : 1;     // 0: A (Vhat), 1: B (What)
+        const int k = side ? e - na : e;
+        int mp = 0;
+        while ((mp + 1) * L - (mp + 1) * mp / 2 <= k) ++mp;
+        const int lp = mp + (k - (mp * L - mp * (mp - 1) / 2));
+        const double* Wt = wscr + (side ? 0 : 2 * nr);
+        auto W = [&](int l, int mm, double& re, double& im) {   // packed rows (l, m >= 0), any m
+            const int am = mm < 0 ? -mm : mm;
+            if (am > l) { re = 0.0; im = 0.0; return; }
+            re = Wt[2 * (l * (l + 1) / 2 + am)];
+            im = Wt[2 * (l * (l + 1) / 2 + am) + 1];
+            if (mm < 0) {
+                im = -im;
+                if (am & 1) { re = -re; im = -im; }
+            }
+        };
+        double Pr, Pi, Nr = 0.0, Ni = 0.0, Zr, Zi;
+        W(lp + 1, mp - 1, Pr, Pi);
+        if (mp >= 1) W(lp + 1, mp + 1, Nr, Ni);
+        W(lp + 1, mp, Zr, Zi);
+        const double wz = mp == 0 ? 1.0 : 2.0;
+        double* row = atab + (size_t)ATAB_ROW * (side * na + k);
+        row[0] = Pr - Nr;
+        row[1] = Pi - Ni;
+        row[2] = Pr + Nr;
+        row[3] = Pi + Ni;
+        row[4] = wz * Zr;
+        row[5] = wz * Zi;
+        if (lp == mp) {                      // diagonal: Rh_mm = -(x + i y)/(2m) Rh_{m-1,m-1}
+            row[6] = 0.0;
+            row[7] = mp > 0 ? -1.0 / (2.0 * mp) : 0.0;
+        } else {                             // Rh_lm = ((2l-1) z Rh_{l-1} - r^2 Rh_{l-2}) / ((l+m)(l-m))
+            const double den = (double)(lp + mp) * (lp - mp);
+            row[6] = (2.0 * lp - 1.0) / den;
+            row[7] = 1.0 / den;
+        }
+    }
+}
+
+// One thread per atom: F[i][3] = -q_i sum over the table rows of (Re(X Rh), Im(Y Rh), Re(Z Rh))
+// with Rh the factorial-scaled regular harmonics of Rot (x_i - c); the rows are the same for
+// every lane (scalar loads).
+__global__ __launch_bounds__(WG) void tcm_atom_forces(const double* __restrict__ T, int L,
+                                                      const double* __restrict__ X, const double* __restrict__ Y,
+                                                      const double* __restrict__ Zc, const double* __restrict__ Q,
+                                                      int64_t n, const double* __restrict__ centre, double r00,
+                                                      double r01, double r02, double r10, double r11, double r12,
+                                                      double r20, double r21, double r22, double* __restrict__ F)
+{
+    const int64_t k = blockIdx.x * (int64_t)WG + threadIdx.x;
+    if (k >= n) return;
+    const double dx = X[k] - centre[0], dy = Y[k] - centre[1], dz = Zc[k] - centre[2];
+    const double x = r00 * dx + r01 * dy + r02 * dz;
+    const double y = r10 * dx + r11 * dy + r12 * dz;
+    const double z = r20 * dx + r21 * dy + r22 * dz;
+    const double r2 = x * x + y * y + z * z;
+    using crow = const __attribute__((address_space(4))) double*;
+    crow row = (crow)T;
+    double fx = 0.0, fy = 0.0, fz = 0.0, dr = 1.0, di = 0.0;       // Rh_mm
+    for (int m = 0; m < L; ++m) {
+        if (m > 0) {
+            const double c2 = row[7];
+            const double tr = (x * dr - y * di) * c2;
+            di = (x * di + y * dr) * c2;
+            dr = tr;
+        }
+        double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
+        fx += row[0] * p1r - row[1] * p1i;
+        fy += row[2] * p1i + row[3] * p1r;
+        fz += row[4] * p1r - row[5] * p1i;
+        row += ATAB_ROW;
+        for (int l = m + 1; l < L; ++l, row += ATAB_ROW) {
+            const double a = row[6] * z, b = row[7] * r2;
+            const double pr = a * p1r - b * p2r, pi = a * p1i - b * p2i;
+            p2r = p1r; p2i = p1i; p1r = pr; p1i = pi;
+            fx += row[0] * pr - row[1] * pi;
+            fy += row[2] * pi + row[3] * pr;
+            fz += row[4] * pr - row[5] * pi;
+        }
+    }
+    const double q = Q[k];
+    F[3 * k] = -q * fx;
+    F[3 * k + 1] = -q * fy;
+    F[3 * k + 2] = -q * fz;
+}
+
 // ------------------------------------------------------------------ kernels
 // One workgroup per item (the grid is the item count): no claim counters, the hardware
 // dispatcher balances the items; the steps of a run are ordered by launch boundaries only
@@ -568,6 +895,14 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int e
     extern __shared__ __align__(16) char smem[];         // pair_smem_bytes(P.pair_lmax)
     const int item = begin + (int)blockIdx.x;
     if (item < end) pair_item(P, item, smem);
+}
+
+__global__ __launch_bounds__(PAIR_WG) void tcm_pairs_ft(DevPlan P, int begin, int end, double* FT, double* wscr,
+                                                        double* atab)
+{
+    extern __shared__ __align__(16) char smem[];         // ft_smem_bytes(P.pair_lmax)
+    const int item = begin + (int)blockIdx.x;
+    if (item < end) pair_ft_item(P, item, smem, FT, wscr, atab);
 }
 
 // Clears the run's device-side flags (a kernel, not a memset, so that it can sit in a
@@ -622,6 +957,26 @@ hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s)
 {
     if (P.nmol <= 0) return hipSuccess;
     hipLaunchKernelGGL(tcm_moments_finalize, dim3(P.nmol), dim3(WG), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, double* wscr, double* atab,
+                           hipStream_t s)
+{
+    if (end <= begin) return hipSuccess;
+    hipLaunchKernelGGL(tcm_pairs_ft, dim3(end - begin), dim3(PAIR_WG), ft_smem_bytes(P.pair_lmax), s, P, begin, end,
+                       FT, wscr, atab);
+    return hipGetLastError();
+}
+
+hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
+                              const double* q, int64_t n, const double* centre, const double* rot9, double* F,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + WG - 1) / WG;
+    hipLaunchKernelGGL(tcm_atom_forces, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, x, y, z, q, n, centre,
+                       rot9[0], rot9[1], rot9[2], rot9[3], rot9[4], rot9[5], rot9[6], rot9[7], rot9[8], F);
     return hipGetLastError();
 }
 

@@ -680,6 +680,7 @@ extern "C" void tcm_destroy(tcm_ctx* t)
     c.release(c.tmp_atoms);
     c.release(c.tmp_q);
     c.release(c.scan_g); c.release(c.scan_r); c.release(c.scan_u); c.release(c.scan_s);
+    c.release(c.force_ft); c.release(c.force_w); c.release(c.force_t); c.release(c.force_a); c.release(c.force_b);
     c.release(c.t_invk);
     c.release(c.t_invf);
     c.release(c.t_rot);
@@ -1414,6 +1415,145 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
         hipStreamSynchronize(s) != hipSuccess)
         return TCM_EDEVICE;
     return TCM_OK;
+}
+
+// ---------------------------------------------------------------- forces and torques
+static void quat_matrix(const double* quat, double* M)
+{
+    double w = 1, x = 0, y = 0, z = 0;
+    if (quat) {
+        const double qn = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+        w = quat[0] / qn; x = quat[1] / qn; y = quat[2] / qn; z = quat[3] / qn;
+    }
+    const double m[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    for (int k = 0; k < 9; ++k) M[k] = m[k];
+}
+
+constexpr int FT_N = 10;
+
+extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const double* R, const double* quat_b, int L,
+                               int flags, double* out, double* forces_A, double* forces_B)
+{
+    if (!t || !R || !out || L < 0 || L > LMAX) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    for (int k = 0; k < FT_N; ++k) out[k] = std::nan("");
+    tcm_pair_req req{};
+    req.a = a;
+    req.b = b;
+    for (int d = 0; d < 3; ++d) req.R[d] = R[d];
+    if (quat_b)
+        for (int d = 0; d < 4; ++d) req.quat_b[d] = quat_b[d];
+    else
+        req.quat_b[0] = 1.0;
+    req.L = L;
+    req.flags = flags & (TCM_REUSE | TCM_UNCHECKED);
+    ReqPlan rp;
+    int rc = plan_requests(c, &req, 1, (flags & TCM_REUSE) != 0, rp);
+    if (rc != TCM_OK) return rc;
+    if (rp.pre_status[0] != TCM_OK) return rp.pre_status[0];
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    const bool atoms = forces_A || forces_B;
+    const int nr = (L + 1) * (L + 2) / 2, na = L * (L + 1) / 2;
+    if ((rc = c.alloc(c.force_ft, sizeof(double) * FT_N)) != TCM_OK) return rc;
+    if (atoms && ((rc = c.alloc(c.force_w, sizeof(double) * 4 * nr)) != TCM_OK ||
+                  (rc = c.alloc(c.force_t, sizeof(double) * 16 * (na > 0 ? na : 1))) != TCM_OK))
+        return rc;
+    if (launch_pairs_ft(bp.P, 0, 1, (double*)c.force_ft.p, atoms ? (double*)c.force_w.p : nullptr,
+                        atoms ? (double*)c.force_t.p : nullptr, s) != hipSuccess)
+        return TCM_EDEVICE;
+    Mol* ma = c.mols[a].get();
+    Mol* mb = c.mols[b].get();
+    const bool dev = (flags & TCM_DEVICE_IO) != 0;
+    double* FA = forces_A;
+    double* FB = forces_B;
+    if (atoms && !dev) {
+        if (forces_A && (rc = c.alloc(c.force_a, sizeof(double) * 3 * std::max<int64_t>(ma->n, 1))) != TCM_OK) return rc;
+        if (forces_B && (rc = c.alloc(c.force_b, sizeof(double) * 3 * std::max<int64_t>(mb->n, 1))) != TCM_OK) return rc;
+        FA = forces_A ? (double*)c.force_a.p : nullptr;
+        FB = forces_B ? (double*)c.force_b.p : nullptr;
+    }
+    double I9[9], Q9[9];
+    quat_matrix(nullptr, I9);
+    quat_matrix(quat_b, Q9);
+    const double* tabA = (const double*)c.force_t.p;
+    const double* tabB = tabA + 8 * (size_t)na;
+    // (at L = 0 the tables are empty and the kernel writes zero forces)
+    if (FA && launch_atom_forces(tabA, L, ma->x, ma->y, ma->z, ma->q, ma->n, (const double*)ma->meta.p, I9, FA, s) !=
+                  hipSuccess)
+        return TCM_EDEVICE;
+    if (FB && launch_atom_forces(tabB, L, mb->x, mb->y, mb->z, mb->q, mb->n, (const double*)mb->meta.p, Q9, FB, s) !=
+                  hipSuccess)
+        return TCM_EDEVICE;
+    double ft[FT_N];
+    int32_t st = TCM_OK;
+    if (hipMemcpyAsync(ft, c.force_ft.p, sizeof(ft), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&st, bp.P.status, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (atoms && !dev) {
+        if (forces_A && ma->n > 0 &&
+            hipMemcpyAsync(forces_A, FA, sizeof(double) * 3 * ma->n, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return TCM_EDEVICE;
+        if (forces_B && mb->n > 0 &&
+            hipMemcpyAsync(forces_B, FB, sizeof(double) * 3 * mb->n, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return TCM_EDEVICE;
+    }
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;    // synchronises the stream
+    mark_computed(rp);
+    if (st != TCM_OK) {
+        if (!dev) {
+            if (forces_A) std::fill(forces_A, forces_A + 3 * ma->n, std::nan(""));
+            if (forces_B) std::fill(forces_B, forces_B + 3 * mb->n, std::nan(""));
+        }
+        return st;
+    }
+    for (int k = 0; k < FT_N; ++k) out[k] = ft[k];
+    return TCM_OK;
+}
+
+extern "C" int tcm_batch_forces(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double* out, int32_t* status_out)
+{
+    if (!t || np < 0 || (np > 0 && (!reqs || !out || !status_out))) return TCM_EINVAL;
+    if (np > (1 << 26)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, np, true, rp);
+    if (rc != TCM_OK) return rc;
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    const int npj = (int)rp.pj.size();
+    std::vector<double> ft((size_t)FT_N * (npj > 0 ? npj : 1));
+    std::vector<int32_t> st(npj > 0 ? npj : 1);
+    if (npj > 0) {
+        if ((rc = c.alloc(c.force_ft, sizeof(double) * FT_N * npj)) != TCM_OK) return rc;
+        if (launch_pairs_ft(bp.P, 0, npj, (double*)c.force_ft.p, nullptr, nullptr, s) != hipSuccess ||
+            hipMemcpyAsync(ft.data(), c.force_ft.p, sizeof(double) * FT_N * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return TCM_EDEVICE;
+    }
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    mark_computed(rp);
+    for (int64_t i = 0; i < np; ++i) {
+        status_out[i] = rp.pre_status[i];
+        for (int k = 0; k < FT_N; ++k) out[FT_N * i + k] = std::nan("");
+    }
+    for (int k = 0; k < npj; ++k) {
+        const int64_t i = rp.pj_req[k];
+        status_out[i] = st[k];
+        if (st[k] == TCM_OK)
+            for (int j = 0; j < FT_N; ++j) out[FT_N * i + j] = ft[(size_t)FT_N * k + j];
+    }
+    return first_error(status_out, np);
 }
 
 // Batch-aware tuning: the tile launch of each (precision, L) group of the batch is timed for

@@ -28,6 +28,13 @@ hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, h
 hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
                        const double* invf, const double* rot, const double* quat, double* T, const double* R,
                        int64_t nR, double* U, int32_t* status, hipStream_t s);
+// Forces and torques: FT[out][10] per pair (U, F_B, tau_A, tau_B); wscr and atab (both or
+// neither) receive the per-atom coefficient tables of the pairs (one pair per call when set).
+hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, double* wscr, double* atab,
+                           hipStream_t s);
+hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
+                              const double* q, int64_t n, const double* centre, const double* rot9, double* F,
+                              hipStream_t s);
 
 struct Ctx;
 
@@ -126,6 +133,7 @@ struct Ctx {
     Workspace ws;                  // shared by the synchronous entry points
     DevBuf tmp_atoms, tmp_q;       // one-shot uploads
     DevBuf scan_g, scan_r, scan_u, scan_s;   // translation scan: pair-tensor table, host-side I/O
+    DevBuf force_ft, force_w, force_t, force_a, force_b;   // forces: outputs, coefficient tables, host-side I/O
     void* hpin = nullptr;          // pinned staging for one-shot uploads
     size_t hpin_cap = 0;
     std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper

@@ -77,6 +77,8 @@ _SIGS = {
     "tcm_scan_translations": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int, _dp, C.c_int, _dp, C.c_int64, _dp,
                                         _ip32]),
     "tcm_all_pairs": (C.c_int, [_vp, _ip64, C.c_int64, C.c_int, C.c_int, _dp, _ip32]),
+    "tcm_pair_forces": (C.c_int, [_vp, C.c_int64, C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
+    "tcm_batch_forces": (C.c_int, [_vp, _vp, C.c_int64, _dp, _ip32]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -375,6 +377,35 @@ def tcm_all_pairs(ctx, ids, L, flags=0):
     if rc in (TCM_EINVAL, TCM_ENOMEM, TCM_EDEVICE, TCM_ENOTFOUND) and np.all(st[:n] == 0):
         raise TCMError(rc, "tcm_all_pairs")
     return U[:n], st[:n]
+
+
+def tcm_pair_forces(ctx, a, b, R, L, quat_b=None, flags=0, atoms=False, nA=0, nB=0):
+    """Returns dict(U, F_B, tau_A, tau_B) and, with atoms=True, the per-atom forces FA[nA][3],
+    FB[nB][3] (host arrays; nA, nB the molecules' atom counts).  Raises TCMError on failure
+    (its code is the pair's status, e.g. TCM_EDOMAIN)."""
+    R = _f64(R, (3,))
+    q = _f64(quat_b, (4,)) if quat_b is not None else None
+    out = np.empty(10)
+    FA = np.empty((max(nA, 1), 3)) if atoms else None
+    FB = np.empty((max(nB, 1), 3)) if atoms else None
+    _check(lib().tcm_pair_forces(ctx, int(a), int(b), _p(R), _p(q), int(L), int(flags), _p(out),
+                                 _p(FA) if atoms else None, _p(FB) if atoms else None), "tcm_pair_forces")
+    res = dict(U=out[0], F_B=out[1:4].copy(), tau_A=out[4:7].copy(), tau_B=out[7:10].copy())
+    if atoms:
+        res["FA"], res["FB"] = FA[:nA], FB[:nB]
+    return res
+
+
+def tcm_batch_forces(ctx, reqs):
+    """Returns (out[n][10] = (U, F_B, tau_A, tau_B), status[n], rc)."""
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    n = len(reqs)
+    out = np.empty((max(n, 1), 10))
+    st = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib().tcm_batch_forces(ctx, reqs.ctypes.data if n else None, n, _p(out), st.ctypes.data_as(_ip32))
+    if rc in (TCM_EINVAL, TCM_ENOMEM, TCM_EDEVICE) and n and np.all(st[:n] == 0):
+        raise TCMError(rc, "tcm_batch_forces")
+    return out[:n], st[:n], rc
 
 
 def pair_index(i, j, K):
