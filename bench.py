@@ -311,6 +311,63 @@ def all_pairs_section(tcm, synth, K=256, L=8, reps=5):
     return out
 
 
+def forces_section(tcm, synth, torch, L=16, npose=4096, reps=10):
+    """Forces: (1) per-atom forces on two 100k-bead chains at L = 16 (B posed), device I/O,
+    resident FP32C moments; (2) force and torque on the centres for 4096 poses of the pair
+    (tcm_batch_forces) against the energy-only batch on the same requests."""
+    import ctypes as C
+    w = synth.chain_pair(seed=2, n=100_000)
+    xA, qA, xB, qB = w["xyzA"], w["qA"], w["xyzB_body"], w["qB"]
+    ctx = tcm.Context(0)
+    mA = tcm.tcm_mol_upload(ctx.h, xA, qA, precision=tcm.TCM_F32C)
+    mB = tcm.tcm_mol_upload(ctx.h, xB, qB, precision=tcm.TCM_F32C)
+    cA, cB = xA.mean(axis=0), xB.mean(axis=0)
+    R = np.ascontiguousarray(np.asarray(w["seps"][-1]) + (cB - cA))
+    quat = np.ascontiguousarray(synth.quaternions(15, 0, 1)[0])
+    FA = torch.empty((len(qA), 3), dtype=torch.float64, device="cuda")
+    FB = torch.empty((len(qB), 3), dtype=torch.float64, device="cuda")
+    out = np.empty(10)
+
+    def call(flags):
+        rc = tcm.lib().tcm_pair_forces(ctx.h, mA, mB, R.ctypes.data_as(tcm._dp), quat.ctypes.data_as(tcm._dp), L,
+                                       flags | tcm.TCM_DEVICE_IO, out.ctypes.data_as(tcm._dp),
+                                       C.cast(FA.data_ptr(), tcm._dp), C.cast(FB.data_ptr(), tcm._dp))
+        assert rc == tcm.TCM_OK, rc
+
+    call(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call(tcm.TCM_REUSE)
+    torch.cuda.synchronize()
+    t_atoms = (time.perf_counter() - t0) / reps
+    rng = np.random.default_rng(61)
+    d = rng.normal(size=(npose, 3))
+    Rs = d / np.linalg.norm(d, axis=1)[:, None] * np.linalg.norm(R)
+    req = tcm.make_requests(mA, mB, Rs, L, synth.quaternions(16, 0, npose), flags=tcm.TCM_REUSE)
+    tcm.tcm_batch_forces(ctx.h, req)
+    t0 = time.perf_counter()
+    o, st, _ = tcm.tcm_batch_forces(ctx.h, req)
+    t_ft = time.perf_counter() - t0
+    tcm.tcm_batch_energy(ctx.h, req)
+    t0 = time.perf_counter()
+    U, _, _ = tcm.tcm_batch_energy(ctx.h, req)
+    t_e = time.perf_counter() - t0
+    res = {"workload": f"two 100k-bead chains, L = {L}, FP32-compensated resident moments, FP64 derivatives",
+           "per_atom": {"atoms": len(qA) + len(qB), "ms_per_call": 1e3 * t_atoms,
+                        "atoms_per_s": (len(qA) + len(qB)) / t_atoms,
+                        "note": "tcm_pair_forces with device I/O: pair kernel (U, F_B, torques, per-atom tables) + "
+                                "two per-atom launches, one synchronisation"},
+           "batch": {"pairs": npose, "statuses_ok": int(np.sum(st == 0)), "ms": 1e3 * t_ft,
+                     "pairs_per_s": npose / t_ft, "energy_only_ms": 1e3 * t_e,
+                     "max_rel_diff_U_vs_energy_path": float(np.max(np.abs(o[:, 0] - U) / np.abs(U)))}}
+    tcm.tcm_mol_release(ctx.h, mA)
+    tcm.tcm_mol_release(ctx.h, mB)
+    del FA, FB
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +380,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--no-all-pairs", action="store_true")
+    ap.add_argument("--no-forces", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference "
                          "point for the HBM byte counters) and exit")
@@ -479,6 +537,14 @@ def main():
             f"{all_pairs['first_call_ms']:.1f} ms, reuse {all_pairs['reuse_call_ms']:.1f} ms "
             f"({all_pairs['pairs_per_s_reuse']:.3e} pairs/s)")
 
+    forces = None
+    if not args.no_forces:
+        t_s = time.time()
+        forces = forces_section(tcm, synth, torch)
+        log(f"bench: forces section in {time.time() - t_s:.1f}s: per-atom {forces['per_atom']['ms_per_call']:.3f} ms "
+            f"for {forces['per_atom']['atoms']} atoms; batch {forces['batch']['pairs']} pairs in "
+            f"{forces['batch']['ms']:.2f} ms (energy only {forces['batch']['energy_only_ms']:.2f} ms)")
+
     out = {
         "metric": "pair energies/s & p50/p99 latency at stated rel. err vs FP64 oracle",
         "value": args.npairs / (ms_step * 1e-3),
@@ -519,6 +585,7 @@ def main():
         "serving": serving,
         "scan": scan,
         "all_pairs": all_pairs,
+        "forces": forces,
     }
     print(json.dumps(out), flush=True)
 

@@ -200,6 +200,18 @@ int tcm_scan_translations(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, int L, const
                           int flags, const double *R, int64_t nR, double *U_out,
                           int32_t *status_out);
 
+/* Adaptive truncation: each request's L is its maximum order; the pair is contracted at the
+ * smallest order L' <= L whose rigorous truncation bound
+ *   S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L'+1} + (beta/(1-alpha))^{L'+1}]
+ * (alpha = a_A/R, beta = a_B/R, S = sum |q|; it bounds |eq. (1) - eq. (9) at L'|) is <= tol,
+ * or at L when none is.  The moments are computed (or reused with TCM_REUSE) at L and stay
+ * resident; sum |q| is computed once per molecule and cached with its moments.  U_out,
+ * status_out: as tcm_batch_energy; L_out (may be NULL): the order used (-1 on error);
+ * bound_out (may be NULL): the bound at that order (above tol when L was not enough; NaN on
+ * error).  The bound covers truncation only, not the rounding of the moment pass.  tol > 0. */
+int tcm_batch_energy_adaptive(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double tol,
+                              double *U_out, int32_t *L_out, double *bound_out, int32_t *status_out);
+
 /* Forces and torques of the truncated energy of one pair (the paper names forces between the
  * fragments as the other use of its final expression; the derivatives are those of eq. (9)
  * as truncated, l1, l2 <= L).  Request fields as in tcm_pair_req; flags: TCM_REUSE,

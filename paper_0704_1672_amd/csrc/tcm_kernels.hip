@@ -897,6 +897,28 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int e
     if (item < end) pair_item(P, item, smem);
 }
 
+// out[0] = sum |q_i| over n charges: one workgroup, each thread a strided subset in index
+// order, then a fixed-order tree (the same value on every run).
+__global__ __launch_bounds__(WG) void tcm_abs_sum(const double* q, int64_t n, double* out)
+{
+    __shared__ double red[WG];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += WG) a += fabs(q[i]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(tcm_abs_sum, dim3(1), dim3(WG), 0, s, q, n, out);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(PAIR_WG) void tcm_pairs_ft(DevPlan P, int begin, int end, double* FT, double* wscr,
                                                         double* atab)
 {

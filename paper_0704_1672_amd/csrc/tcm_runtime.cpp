@@ -681,6 +681,7 @@ extern "C" void tcm_destroy(tcm_ctx* t)
     c.release(c.tmp_q);
     c.release(c.scan_g); c.release(c.scan_r); c.release(c.scan_u); c.release(c.scan_s);
     c.release(c.force_ft); c.release(c.force_w); c.release(c.force_t); c.release(c.force_a); c.release(c.force_b);
+    c.release(c.absq);
     c.release(c.t_invk);
     c.release(c.t_invf);
     c.release(c.t_rot);
@@ -972,6 +973,7 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
         rp.computed.push_back({m, L});
         m->Lcached = -1;                      // invalid until this run completes
         m->radius_host = -1.0;
+        m->absq_host = -1.0;
     }
     for (int64_t i = 0; i < np; ++i) {
         if (rp.pre_status[i] != TCM_OK) continue;
@@ -1003,6 +1005,7 @@ void mark_computed(ReqPlan& rp)
     for (auto& pr : rp.computed) {
         pr.first->Lcached = pr.second;
         pr.first->radius_host = -1.0;
+        pr.first->absq_host = -1.0;
     }
 }
 }  // namespace tcm
@@ -1034,6 +1037,7 @@ extern "C" int tcm_mol_moments(tcm_ctx* t, tcm_mol_id id, int L, int flags, doub
         j.meta = (double*)m->meta.p;
         m->Lcached = -1;
         m->radius_host = -1.0;
+        m->absq_host = -1.0;
         BuiltPlan bp;
         if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) return rc;
         if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
@@ -1415,6 +1419,95 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
         hipStreamSynchronize(s) != hipSuccess)
         return TCM_EDEVICE;
     return TCM_OK;
+}
+
+// ---------------------------------------------------------------- adaptive truncation
+// Bound on |U_coulomb - U_L| for the square truncation: with alpha = a_A/R, beta = a_B/R and
+// S = sum |q|, the (l1, l2) term of the double Taylor series of 1/|R + r_B - r_A| is at most
+// C(l1+l2, l1) a_A^l1 a_B^l2 / R^{l1+l2+1}, and summing the terms outside the square gives
+// S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L+1} + (beta/(1-alpha))^{L+1}].
+static double trunc_bound(double SA, double SB, double aA, double aB, double R, int L)
+{
+    const double al = aA / R, be = aB / R;
+    if (!(al + be < 1.0)) return INFINITY;
+    return SA * SB / (R * (1.0 - al - be)) * (std::pow(al / (1.0 - be), L + 1) + std::pow(be / (1.0 - al), L + 1));
+}
+
+extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double tol, double* U_out,
+                                         int32_t* L_out, double* bound_out, int32_t* status_out)
+{
+    if (!t || np < 0 || (np > 0 && (!reqs || !U_out || !status_out)) || !(tol > 0.0)) return TCM_EINVAL;
+    if (np > (1 << 26)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    // 1. moments at each request's maximum order
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, np, true, rp);
+    if (rc != TCM_OK) return rc;
+    if (!rp.mj.empty()) {
+        BuiltPlan bp;
+        if ((rc = build_plan(&c, c.ws, rp.mj, {}, bp, s)) != TCM_OK) return rc;
+        if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+        if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+        mark_computed(rp);
+    }
+    // 2. radius and sum |q| of every molecule involved (read once per computation)
+    std::vector<Mol*> need;
+    for (int64_t i = 0; i < np; ++i) {
+        if (rp.pre_status[i] != TCM_OK) continue;
+        for (tcm_mol_id id : {reqs[i].a, reqs[i].b}) {
+            Mol* m = c.mols[id].get();
+            if ((m->radius_host < 0.0 || m->absq_host < 0.0) && std::find(need.begin(), need.end(), m) == need.end())
+                need.push_back(m);
+        }
+    }
+    if (!need.empty()) {
+        if ((rc = c.alloc(c.absq, sizeof(double) * need.size())) != TCM_OK) return rc;
+        std::vector<double> meta(need.size() * 8), sq(need.size());
+        for (size_t k = 0; k < need.size(); ++k) {
+            if (launch_abs_sum(need[k]->q, need[k]->n, (double*)c.absq.p + k, s) != hipSuccess ||
+                hipMemcpyAsync(&meta[8 * k], need[k]->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+                return TCM_EDEVICE;
+        }
+        if (hipMemcpyAsync(sq.data(), c.absq.p, sizeof(double) * need.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return TCM_EDEVICE;
+        for (size_t k = 0; k < need.size(); ++k) {
+            need[k]->radius_host = meta[8 * k + 3];
+            need[k]->absq_host = sq[k];
+        }
+    }
+    // 3. per pair, the smallest order whose bound meets tol (the maximum if none does)
+    std::vector<tcm_pair_req> rq(reqs, reqs + np);
+    std::vector<double> bnd((size_t)np, std::nan(""));
+    for (int64_t i = 0; i < np; ++i) {
+        if (rp.pre_status[i] != TCM_OK) continue;
+        const Mol* ma = c.mols[reqs[i].a].get();
+        const Mol* mb = c.mols[reqs[i].b].get();
+        const double R = std::sqrt(reqs[i].R[0] * reqs[i].R[0] + reqs[i].R[1] * reqs[i].R[1] + reqs[i].R[2] * reqs[i].R[2]);
+        int L = reqs[i].L;
+        double b = trunc_bound(ma->absq_host, mb->absq_host, ma->radius_host, mb->radius_host, R, L);
+        for (int l = 0; l < reqs[i].L; ++l) {
+            const double bl = trunc_bound(ma->absq_host, mb->absq_host, ma->radius_host, mb->radius_host, R, l);
+            if (bl <= tol) {
+                L = l;
+                b = bl;
+                break;
+            }
+        }
+        rq[i].L = L;
+        rq[i].flags |= TCM_REUSE;
+        bnd[i] = b;
+    }
+    // 4. the contractions at the chosen orders (moments resident at the maximum order)
+    rc = batch_energy_locked(c, rq.data(), np, U_out, status_out);
+    for (int64_t i = 0; i < np; ++i) {
+        if (L_out) L_out[i] = status_out[i] == TCM_OK ? rq[i].L : -1;
+        if (bound_out) bound_out[i] = status_out[i] == TCM_OK ? bnd[i] : std::nan("");
+    }
+    return rc;
 }
 
 // ---------------------------------------------------------------- forces and torques

@@ -32,6 +32,7 @@ hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, do
 // neither) receive the per-atom coefficient tables of the pairs (one pair per call when set).
 hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, double* wscr, double* atab,
                            hipStream_t s);
+hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s);
 hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
                               const double* q, int64_t n, const double* centre, const double* rot9, double* F,
                               hipStream_t s);
@@ -60,6 +61,7 @@ struct Mol {
     int Lcached = -1;              // order of valid resident moments (-1: none)
     double radius_host = -1.0;     // meta[3] read back to the host, -1 until then; reset
                                    // whenever the moments are recomputed
+    double absq_host = -1.0;       // sum |q_i| (truncation bound), -1 until computed; reset likewise
     uint64_t last_use = 0;
 };
 
@@ -134,6 +136,7 @@ struct Ctx {
     DevBuf tmp_atoms, tmp_q;       // one-shot uploads
     DevBuf scan_g, scan_r, scan_u, scan_s;   // translation scan: pair-tensor table, host-side I/O
     DevBuf force_ft, force_w, force_t, force_a, force_b;   // forces: outputs, coefficient tables, host-side I/O
+    DevBuf absq;                   // sum |q| of the molecules an adaptive batch needs
     void* hpin = nullptr;          // pinned staging for one-shot uploads
     size_t hpin_cap = 0;
     std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper

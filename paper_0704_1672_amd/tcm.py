@@ -79,6 +79,7 @@ _SIGS = {
     "tcm_all_pairs": (C.c_int, [_vp, _ip64, C.c_int64, C.c_int, C.c_int, _dp, _ip32]),
     "tcm_pair_forces": (C.c_int, [_vp, C.c_int64, C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
     "tcm_batch_forces": (C.c_int, [_vp, _vp, C.c_int64, _dp, _ip32]),
+    "tcm_batch_energy_adaptive": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, _dp, _ip32, _dp, _ip32]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -394,6 +395,21 @@ def tcm_pair_forces(ctx, a, b, R, L, quat_b=None, flags=0, atoms=False, nA=0, nB
     if atoms:
         res["FA"], res["FB"] = FA[:nA], FB[:nB]
     return res
+
+
+def tcm_batch_energy_adaptive(ctx, reqs, tol):
+    """Returns (U[n], L_used[n], bound[n], status[n], rc); each request's L is its maximum."""
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    n = len(reqs)
+    U = np.empty(max(n, 1))
+    Lu = np.empty(max(n, 1), dtype=np.int32)
+    b = np.empty(max(n, 1))
+    st = np.zeros(max(n, 1), dtype=np.int32)
+    rc = lib().tcm_batch_energy_adaptive(ctx, reqs.ctypes.data if n else None, n, float(tol), _p(U),
+                                         Lu.ctypes.data_as(_ip32), _p(b), st.ctypes.data_as(_ip32))
+    if rc in (TCM_EINVAL, TCM_ENOMEM, TCM_EDEVICE) and (n == 0 or np.all(st[:n] == 0)):
+        raise TCMError(rc, "tcm_batch_energy_adaptive")
+    return U[:n], Lu[:n], b[:n], st[:n], rc
 
 
 def tcm_batch_forces(ctx, reqs):
