@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--no-all-pairs", action="store_true")
     ap.add_argument("--no-forces", action="store_true")
+    ap.add_argument("--alu-calibration", action="store_true",
+                    help="only measure the sustained plain FP32 and FP64 FMA rates and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference "
                          "point for the HBM byte counters) and exit")
@@ -402,6 +404,13 @@ def main():
                           "launches": 3}), flush=True)
         return
     from paper_0704_1672_amd import synth, tcm
+    if args.alu_calibration:
+        ctx = tcm.Context(0)
+        r = {"fp32_fma_tflops": tcm.tcm_alu_calibrate(ctx.h, tcm.TCM_F32C),
+             "fp64_fma_tflops": tcm.tcm_alu_calibrate(ctx.h, tcm.TCM_F64)}
+        ctx.close()
+        print(json.dumps(r), flush=True)
+        return
 
     t0 = time.time()
     w = synth.uneven_batch(seed=4, npairs=args.npairs, nthreads=min(16, os.cpu_count() or 1))
@@ -470,6 +479,10 @@ def main():
     moment_tflops = info["moment_flops"] / (ph[1] * 1e-3) / 1e12
     log(f"bench: phase ms stats={ph[0]:.3f} tiles={ph[1]:.3f} finalise={ph[2]:.3f} pairs={ph[3]:.3f}; "
         f"moment pass {moment_tflops:.1f} TFLOP/s")
+    # the sustained plain-FMA rate of this device (outside the timed region): the ceiling the
+    # tile kernels can reach without packed FP32
+    fp32_ceiling = tcm.tcm_alu_calibrate(ctx.h, tcm.TCM_F32C)
+    log(f"bench: plain FP32 FMA ceiling {fp32_ceiling:.1f} TFLOP/s")
 
     # oracle on a bounded sample of pairs: throughput baseline and relative error
     cpu = None
@@ -580,7 +593,8 @@ def main():
                      "unit": "TFLOP/s", "frac": moment_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_tile_traffic(),
                      "kernel": "moment-pass tile kernels (FP32), 6(L+1)(L+2) flops per atom; achieved and "
-                               "traffic are per step (one launch of tcm_tiles<float, L> per order L)"},
+                               "traffic are per step (one launch of tcm_tiles<float, L> per order L)",
+                     "measured_plain_fp32_fma_tflops": fp32_ceiling},
         "cpu_baseline": cpu,
         "serving": serving,
         "scan": scan,

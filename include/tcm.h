@@ -245,6 +245,13 @@ int tcm_all_pairs(tcm_ctx *ctx, const tcm_mol_id *ids, int64_t K, int L, int fla
 
 /* ---- tuning ------------------------------------------------------------------------ */
 
+/* Sustained rate of plain (non-packed) vector FMA instructions on the context's device, in
+ * TFLOP/s (an FMA counts two): 16 independent chains per thread on 32 workgroups of 256
+ * threads per compute unit, five timed launches.  precision: TCM_F32C (FP32) or TCM_F64.
+ * The ceiling against which the ALU-bound kernels are read (the datasheet FP32 figure
+ * assumes packed FP32, which this library does not use). */
+int tcm_alu_calibrate(tcm_ctx *ctx, int precision, double *tflops_out);
+
 /* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */
 int tcm_tune_get(tcm_ctx *ctx, int precision, int L, int64_t n, int *kper_out);
 int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);

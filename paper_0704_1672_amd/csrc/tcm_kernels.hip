@@ -897,6 +897,33 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int e
     if (item < end) pair_item(P, item, smem);
 }
 
+// Calibration of the vector ALU: 16 independent FMA chains per thread (a = a * b + c), so the
+// sustained rate of plain (non-packed) FMA instructions is measured without latency limits.
+template <typename T>
+__global__ __launch_bounds__(WG) void tcm_alu_probe(T* out, int iters, T b, T c)
+{
+    T a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a[k] = (T)(threadIdx.x + k);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = a[k] * b + c;
+    }
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += a[k];
+    out[blockIdx.x * (int64_t)WG + threadIdx.x] = s;
+}
+
+hipError_t launch_alu_probe(int prec, void* out, int blocks, int iters, hipStream_t s)
+{
+    if (prec == 1)
+        hipLaunchKernelGGL(tcm_alu_probe<float>, dim3(blocks), dim3(WG), 0, s, (float*)out, iters, 0.999f, 0.001f);
+    else
+        hipLaunchKernelGGL(tcm_alu_probe<double>, dim3(blocks), dim3(WG), 0, s, (double*)out, iters, 0.999, 0.001);
+    return hipGetLastError();
+}
+
 // out[0] = sum |q_i| over n charges: one workgroup, each thread a strided subset in index
 // order, then a fixed-order tree (the same value on every run).
 __global__ __launch_bounds__(WG) void tcm_abs_sum(const double* q, int64_t n, double* out)

@@ -1421,6 +1421,38 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
     return TCM_OK;
 }
 
+// ---------------------------------------------------------------- ALU calibration
+extern "C" int tcm_alu_calibrate(tcm_ctx* t, int precision, double* tflops_out)
+{
+    if (!t || !tflops_out || (precision != TCM_F64 && precision != TCM_F32C)) return TCM_EINVAL;
+    Ctx& c = t->c;
+    std::lock_guard<std::mutex> g(c.mu);
+    (void)hipSetDevice(c.device);
+    hipStream_t s = c.stream;
+    const int blocks = 32 * c.num_cu, iters = 4096, reps = 5;
+    DevBuf buf;
+    int rc = c.alloc(buf, sizeof(double) * (size_t)blocks * WG);
+    if (rc != TCM_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.0f;
+    rc = TCM_EDEVICE;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+        launch_alu_probe(precision, buf.p, blocks, iters, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess) {
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) ok = launch_alu_probe(precision, buf.p, blocks, iters, s) == hipSuccess;
+        if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
+            const double flops = (double)reps * blocks * WG * 16.0 * iters * 2.0;
+            *tflops_out = flops / (ms * 1e-3) / 1e12;
+            rc = TCM_OK;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c.release(buf);
+    return rc;
+}
+
 // ---------------------------------------------------------------- adaptive truncation
 // Bound on |U_coulomb - U_L| for the square truncation: with alpha = a_A/R, beta = a_B/R and
 // S = sum |q|, the (l1, l2) term of the double Taylor series of 1/|R + r_B - r_A| is at most

@@ -32,6 +32,7 @@ hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, do
 // neither) receive the per-atom coefficient tables of the pairs (one pair per call when set).
 hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, double* wscr, double* atab,
                            hipStream_t s);
+hipError_t launch_alu_probe(int prec, void* out, int blocks, int iters, hipStream_t s);
 hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s);
 hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
                               const double* q, int64_t n, const double* centre, const double* rot9, double* F,

@@ -80,6 +80,7 @@ _SIGS = {
     "tcm_pair_forces": (C.c_int, [_vp, C.c_int64, C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
     "tcm_batch_forces": (C.c_int, [_vp, _vp, C.c_int64, _dp, _ip32]),
     "tcm_batch_energy_adaptive": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, _dp, _ip32, _dp, _ip32]),
+    "tcm_alu_calibrate": (C.c_int, [_vp, C.c_int, _dp]),
     "tcm_tune_save": (C.c_int, [_vp, C.c_char_p]),
     "tcm_tune_load": (C.c_int, [_vp, C.c_char_p]),
     "tcm_server_start": (C.c_int, [_vp, C.POINTER(tcm_server_cfg)]),
@@ -395,6 +396,12 @@ def tcm_pair_forces(ctx, a, b, R, L, quat_b=None, flags=0, atoms=False, nA=0, nB
     if atoms:
         res["FA"], res["FB"] = FA[:nA], FB[:nB]
     return res
+
+
+def tcm_alu_calibrate(ctx, precision):
+    t = C.c_double()
+    _check(lib().tcm_alu_calibrate(ctx, int(precision), C.byref(t)), "tcm_alu_calibrate")
+    return t.value
 
 
 def tcm_batch_energy_adaptive(ctx, reqs, tol):

@@ -58,6 +58,7 @@ hipError_t launch_scan(const double*, const double*, int, double, double, double
                        const double*, double*, const double*, int64_t nR, double* U, int32_t* status, hipStream_t) {
     for (int64_t k = 0; k < nR; ++k) { U[k] = 0.0; status[k] = 0; }
     return 0; }
+hipError_t launch_alu_probe(int, void*, int, int, hipStream_t) { return 0; }
 hipError_t launch_abs_sum(const double*, int64_t, double* out, hipStream_t) { out[0] = 1.0; return 0; }
 hipError_t launch_pairs_ft(const DevPlan&, int, int, double*, double*, double*, hipStream_t) { return 0; }
 hipError_t launch_atom_forces(const double*, int, const double*, const double*, const double*, const double*, int64_t,
