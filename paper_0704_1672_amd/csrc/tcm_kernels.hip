@@ -122,18 +122,16 @@ __device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol, char* 
 }
 
 // ------------------------------------------------------------------ PAIR items
-// LDS layout (doubles), sized for the largest order Lm of the launch's pairs:
-// sA[nh(Lm)], sB[nh(Lm)], sI[2 * ni(Lm)] (the rotation temporary aliases sI), spow[2Lm+2],
-// scs[3][Lm+1][2], red[WG].
-// One pair per workgroup of PAIR_WG threads, one contraction row per thread.  The size is the
-// same for every launch, so a pair's summation order -- and its energy, bit for bit -- does not
-// depend on how many pairs share the launch (1024-thread workgroups, which split each row's
-// l2 loop four ways, shortened a lone pair but summed in another order).
+// One pair per workgroup of PAIR_WG threads; the LDS layout is sized for the largest order Lm
+// of the launch's pairs.  The size is the same for every launch, so a pair's summation order --
+// and its energy, bit for bit -- does not depend on how many pairs share the launch.
 constexpr int PAIR_WG = 256;
 __host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2) / 2; }
+
 __host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
 {
-    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni(Lm) + (2 * Lm + 2) + 6 * (Lm + 1) + PAIR_WG);
+    // sA, sB, sT [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [WG]
+    return sizeof(double) * (3 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG);
 }
 
 __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
@@ -157,19 +155,20 @@ __device__ void rot_matvec(const double* tab, const double* in, double* out, int
     const int NHl = nh(L);
     for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
         const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
-        // tables for order l start at 2 * sum_{j<l} (2j+1)^2 = 2 l (4l^2-1)/3
-        const double* D = tab + (int64_t)2 * l * (4 * l * l - 1) / 3 + (inverse ? n * n : 0) + (int64_t)i * n;
+        // tables for order l start at 2 * sum_{j<l} (2j+1)^2 = 2 l (4l^2-1)/3, each matrix stored
+        // column by column: row i's element j at j n + i (consecutive lanes, consecutive rows)
+        const double* D = tab + (int64_t)2 * l * (4 * l * l - 1) / 3 + (inverse ? n * n : 0) + i;
         const double* v = in + l * l;
         // four independent partial sums so that the table loads are all in flight together
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int j = 0;
         for (; j + 4 <= n; j += 4) {
-            s0 += D[j] * v[j];
-            s1 += D[j + 1] * v[j + 1];
-            s2 += D[j + 2] * v[j + 2];
-            s3 += D[j + 3] * v[j + 3];
+            s0 += D[j * n] * v[j];
+            s1 += D[(j + 1) * n] * v[j + 1];
+            s2 += D[(j + 2) * n] * v[j + 2];
+            s3 += D[(j + 3) * n] * v[j + 3];
         }
-        for (; j < n; ++j) s0 += D[j] * v[j];
+        for (; j < n; ++j) s0 += D[j * n] * v[j];
         out[h] = (s0 + s1) + (s2 + s3);
     }
 }
@@ -208,9 +207,17 @@ __device__ inline void rotate_moments(const double* rot, double* v, double* t, i
     __syncthreads();
 }
 
-__device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
+// Contraction in the frame where R lies along the z axis.  Rotating A, B and R together leaves
+// eq. (9) unchanged; with R = |R| t, t = +-z, the irregular harmonics of t vanish for M != 0 and
+// I_{L'0}(t) = (+-1)^{L'} L'!, so with a, b the moments of A and B rotated into that frame and
+// divided by f R^l,
+//     U = (1/R) sum_{l1, l2} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! sum_{m >= 0} w_m (-1)^m Re(a_{l1 m} conj(b_{l2 m}))
+// (w_0 = 1, w_m = 2; b_{l,-m} = (-1)^m conj(b_lm) folds m < 0 in): O(L^3) after two O(L^3)
+// rotations, the pose of B folded into its rotation.  The frame rotation is the quaternion
+// taking n = R/|R| to t = sign(n_z) z, (1 + n.t, n x t) normalised (1 + |n_z| >= 1, so it is
+// well conditioned for every direction).
+__device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* smem)
 {
-    // the moment launches that precede this one have finalised every table it reads
     const PairWork& pw = P.pairs[p];
     const int tid = threadIdx.x;
     const int L = pw.L, NHl = nh(L);
@@ -227,100 +234,72 @@ __device__ __forceinline__ void pair_item(const DevPlan& P, int p, char* smem)
     const int Lm = P.pair_lmax;
     double* sA = reinterpret_cast<double*>(smem);
     double* sB = sA + nh(Lm);
-    double* sI = sB + nh(Lm);                // complex, index (L'(L'+1)/2 + M)
-    double* sT = sI;                         // rotation temporary (before sI is built)
-    double* spow = sI + 2 * ni(Lm);
-    double* scs = spow + (2 * Lm + 2);       // [3][Lm+1][2]
-    double* red = scs + 3 * (Lm + 1) * 2;
+    double* sT = sB + nh(Lm);                // rotation temporary
+    double* spow = sT + nh(Lm);              // R^-l, l <= Lm
+    double* fac = spow + (Lm + 1);           // (+-1)^k k!, k <= 2Lm
+    double* scsA = fac + (2 * Lm + 1);       // [3][Lm+1][2] each
+    double* scsB = scsA + 6 * (Lm + 1);
+    double* qq = scsB + 6 * (Lm + 1);        // frame quaternion, then B's
+    double* red = qq + 8;
     if (tid == 0) {
         const double ir = 1.0 / Rn;
         spow[0] = 1.0;
-        for (int l = 1; l <= 2 * L + 1; ++l) spow[l] = spow[l - 1] * ir;
+        for (int l = 1; l <= L; ++l) spow[l] = spow[l - 1] * ir;
+        const double nx = Rx * ir, ny = Ry * ir, nz = Rz * ir, sg = nz < 0.0 ? -1.0 : 1.0;
+        double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx;
+        const double qn = sqrt(w * w + x * x + y * y);
+        w /= qn; x /= qn; y /= qn;
+        qq[0] = w; qq[1] = x; qq[2] = y; qq[3] = 0.0;
+        if (pw.has_rot) {                    // frame (x) pose: the pose applied first
+            const double* q = pw.quat;
+            qq[4] = w * q[0] - x * q[1] - y * q[2];
+            qq[5] = w * q[1] + x * q[0] + y * q[3];
+            qq[6] = w * q[2] - x * q[3] + y * q[0];
+            qq[7] = w * q[3] + x * q[2] - y * q[1];
+        } else {
+            qq[4] = w; qq[5] = x; qq[6] = y; qq[7] = 0.0;
+        }
+        fac[0] = 1.0;
+        for (int k = 1; k <= 2 * L; ++k) fac[k] = fac[k - 1] * (sg * k);
     }
-    if (pw.has_rot && tid <= L) euler_phases(pw.quat, tid, Lm, scs);
     __syncthreads();
+    if (tid <= L) {
+        euler_phases(qq, tid, Lm, scsA);
+        euler_phases(qq + 4, tid, Lm, scsB);
+    }
     for (int h = tid; h < NHl; h += PAIR_WG) {
         const double sc = spow[l_of(h)];
-        sA[h] = pw.QA[h] * sc * P.invf[h];
+        sA[h] = pw.QA[h] * sc;
         sB[h] = pw.QB[h] * sc;
     }
     __syncthreads();
-    if (pw.has_rot) rotate_moments(P.rot, sB, sT, L, Lm, scs);
-    for (int h = tid; h < NHl; h += PAIR_WG) sB[h] *= P.invf[h];
-    // irregular harmonics of the unit vector n = R/|R|, factorial-scaled:
-    //   I_00 = 1, I_MM = -(2M-1)(nx + i ny) I_{M-1,M-1}, I_{M+1,M} = (2M+1) nz I_MM,
-    //   I_LM = (2L-1) nz I_{L-1,M} - ((L-1)^2 - M^2) I_{L-2,M}
-    const int L2 = 2 * L;
-    if (tid <= L2) {
-        const int M = tid;
-        const double nx = Rx / Rn, ny = Ry / Rn, nz = Rz / Rn;
-        double cr = 1.0, ci = 0.0;
-        for (int k = 1; k <= M; ++k) {
-            const double f = -(2.0 * k - 1.0);
-            const double tr = f * (cr * nx - ci * ny);
-            ci = f * (cr * ny + ci * nx);
-            cr = tr;
-        }
-        double pr = 0.0, pi = 0.0;         // I_{L-2,M}
-        double qr = cr, qi = ci;           // I_{L-1,M}
-        sI[2 * (M * (M + 1) / 2 + M)] = cr;
-        sI[2 * (M * (M + 1) / 2 + M) + 1] = ci;
-        for (int Lp = M + 1; Lp <= L2; ++Lp) {
-            const double a = 2.0 * Lp - 1.0, b = (Lp - 1.0) * (Lp - 1.0) - (double)M * M;
-            const double nr = a * nz * qr - b * pr, ni = a * nz * qi - b * pi;
-            pr = qr; pi = qi; qr = nr; qi = ni;
-            sI[2 * (Lp * (Lp + 1) / 2 + M)] = nr;
-            sI[2 * (Lp * (Lp + 1) / 2 + M) + 1] = ni;
-        }
+    rotate_moments(P.rot, sA, sT, L, Lm, scsA);
+    rotate_moments(P.rot, sB, sT, L, Lm, scsB);
+    for (int h = tid; h < NHl; h += PAIR_WG) {
+        sA[h] *= P.invf[h];
+        sB[h] *= P.invf[h];
     }
     __syncthreads();
-    // rows (l1, m1 >= 0): V = sum_{l2, m2} (-1)^{l2} b_{l2 m2} conj(I_{l1+l2, m1+m2})
-    // (negative m2 folded in through b_{l,-m} = (-1)^m conj(b_lm)); U = Re sum w a V.
+    // rows (m, l1 >= m), m-major
     double Upart = 0.0;
-    const int nrows = (L + 1) * (L + 2) / 2;
-    for (int r = tid; r < nrows; r += PAIR_WG) {
-        int l1 = 0;
-        while ((l1 + 1) * (l1 + 2) / 2 <= r) ++l1;
-        const int m1 = r - l1 * (l1 + 1) / 2;
-        double Vr = 0.0, Vi = 0.0;
-        for (int l2 = 0; l2 <= L; ++l2) {
-            const int Lp = l1 + l2;
-            const double* Irow = sI + 2 * (Lp * (Lp + 1) / 2);
-            double vr = 0.0, vi = 0.0;
-            {   // m2 = 0
-                const double br = sB[l2 * l2];
-                const double Ir = Irow[2 * m1], Ii = Irow[2 * m1 + 1];
-                vr += br * Ir;
-                vi -= br * Ii;
-            }
-            for (int m2 = 1; m2 <= l2; ++m2) {
-                const double br = sB[l2 * l2 + 2 * m2 - 1], bi = sB[l2 * l2 + 2 * m2];
-                // b * conj(I_{Lp, m1+m2})
-                const double Ir = Irow[2 * (m1 + m2)], Ii = Irow[2 * (m1 + m2) + 1];
-                vr += br * Ir + bi * Ii;
-                vi += bi * Ir - br * Ii;
-                // (-1)^{m2} conj(b) * conj(I_{Lp, m1-m2})
-                const int M = m1 - m2;
-                double Jr, Ji;                       // conj(I_{Lp, M})
-                if (M >= 0) {
-                    Jr = Irow[2 * M];
-                    Ji = -Irow[2 * M + 1];
-                } else {                             // = (-1)^M I_{Lp, -M}
-                    const double sg = ((-M) & 1) ? -1.0 : 1.0;
-                    Jr = sg * Irow[2 * (-M)];
-                    Ji = sg * Irow[2 * (-M) + 1];
-                }
-                const double sg2 = (m2 & 1) ? -1.0 : 1.0;
-                vr += sg2 * (br * Jr + bi * Ji);
-                vi += sg2 * (br * Ji - bi * Jr);
-            }
-            if (l2 & 1) { Vr -= vr; Vi -= vi; } else { Vr += vr; Vi += vi; }
+    const int nr = (L + 1) * (L + 2) / 2;
+    for (int r = tid; r < nr; r += PAIR_WG) {
+        int m = 0, k = r;
+        while (k >= L - m + 1) { k -= L - m + 1; ++m; }
+        const int l1 = m + k;
+        const double ar = m == 0 ? sA[l1 * l1] : sA[l1 * l1 + 2 * m - 1];
+        const double ai = m == 0 ? 0.0 : sA[l1 * l1 + 2 * m];
+        double cr = 0.0, ci = 0.0;           // sum_l2 (-1)^{l2} fac[l1+l2] conj(b_{l2 m})
+        for (int l2 = m; l2 <= L; ++l2) {
+            const double br = m == 0 ? sB[l2 * l2] : sB[l2 * l2 + 2 * m - 1];
+            const double bi = m == 0 ? 0.0 : sB[l2 * l2 + 2 * m];
+            const double f = (l2 & 1) ? -fac[l1 + l2] : fac[l1 + l2];
+            cr += f * br;
+            ci -= f * bi;
         }
-        double ar, ai;
-        if (m1 == 0) { ar = sA[l1 * l1]; ai = 0.0; }
-        else { ar = sA[l1 * l1 + 2 * m1 - 1]; ai = sA[l1 * l1 + 2 * m1]; }
-        const double t = ar * Vr - ai * Vi;
-        Upart += (m1 == 0) ? t : 2.0 * t;
+        const double t = ar * cr - ai * ci;
+        const double wt = m == 0 ? 1.0 : 2.0;
+        Upart += (m & 1) ? -wt * t : wt * t;
     }
     red[tid] = Upart;
     __syncthreads();
@@ -894,7 +873,7 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int e
 {
     extern __shared__ __align__(16) char smem[];         // pair_smem_bytes(P.pair_lmax)
     const int item = begin + (int)blockIdx.x;
-    if (item < end) pair_item(P, item, smem);
+    if (item < end) pair_item_axial(P, item, smem);
 }
 
 // Calibration of the vector ALU: 16 independent FMA chains per thread (a = a * b + c), so the

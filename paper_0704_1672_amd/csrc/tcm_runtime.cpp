@@ -159,7 +159,8 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 // equispaced phi: exact for the degree-2l integrands).  The inverse follows from the
 // orthogonality norms g = 4pi/(2l+1) * (1 for m = 0, 1/2 for the Re/Im parts of m > 0):
 // invariance of the sphere measure gives D G D^T = G, so (D^{-1})_ij = D_ji g_i / g_j.
-// Layout: for each l, D then D^{-1}, row-major (2l+1)^2.
+// Layout: for each l, D then D^{-1}, (2l+1)^2 each, stored column by column (element (i, j)
+// at j (2l+1) + i), so that the lanes computing consecutive rows read consecutive addresses.
 static std::vector<double> build_rotation_tables(int Lmax)
 {
     size_t total = 0;
@@ -191,9 +192,9 @@ static std::vector<double> build_rotation_tables(int Lmax)
         double* Dout = out.data() + off;
         double* Dinv = Dout + n * n;
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) Dout[i * n + j] = D[i * n + j] / g(j);
+            for (int j = 0; j < n; ++j) Dout[j * n + i] = D[i * n + j] / g(j);
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) Dinv[i * n + j] = Dout[j * n + i] * g(i) / g(j);
+            for (int j = 0; j < n; ++j) Dinv[j * n + i] = D[j * n + i] / g(i) * g(i) / g(j);
         off += 2 * (size_t)n * n;
     }
     return out;
