@@ -86,7 +86,7 @@ struct DevPlan {
     // FP64 coefficient tables (device)
     const double* invk;            // 1/k_lm of the normalised recurrence, per packed index
     const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
-    const double* rot;             // rotation tables: for each l, D then D^{-1}, (2l+1)^2 each
+    const double* rot;             // rotation tables (D and D^{-1} per l, compressed by sparsity)
 };
 
 // Packed index helpers (layout of every moment table at the boundary):

@@ -130,8 +130,8 @@ __host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2
 
 __host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
 {
-    // sA, sB, sT [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [WG]
-    return sizeof(double) * (3 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG);
+    // sA, sB, tA, tB [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [WG]
+    return sizeof(double) * (4 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG);
 }
 
 __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
@@ -150,26 +150,37 @@ __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
     }
 }
 
+// out = D v (or D^{-1} v) per order l from the compressed tables: row i's nonzero columns are
+// max(0, jb + 4k), k < cnt (the header, codes and slot layout are those the runtime writes).
+__device__ __forceinline__ void rot_row(const double* tab, int l, int i, bool inverse, int& jb, int& cnt,
+                                        const double*& val)
+{
+    const int n = 2 * l + 1, K = l / 2 + 1;
+    const double* blk = tab + (int64_t)tab[l];
+    const int code = (int)blk[(inverse ? n : 0) + i];
+    jb = (code & 0xffff) - 1;
+    cnt = code >> 16;
+    val = blk + 2 * n + (inverse ? K * n : 0) + i;
+}
+
 __device__ void rot_matvec(const double* tab, const double* in, double* out, int L, bool inverse)
 {
     const int NHl = nh(L);
     for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
         const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
-        // tables for order l start at 2 * sum_{j<l} (2j+1)^2 = 2 l (4l^2-1)/3, each matrix stored
-        // column by column: row i's element j at j n + i (consecutive lanes, consecutive rows)
-        const double* D = tab + (int64_t)2 * l * (4 * l * l - 1) / 3 + (inverse ? n * n : 0) + i;
+        int jb, cnt;
+        const double* val;
+        rot_row(tab, l, i, inverse, jb, cnt, val);
         const double* v = in + l * l;
-        // four independent partial sums so that the table loads are all in flight together
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {
-            s0 += D[j * n] * v[j];
-            s1 += D[(j + 1) * n] * v[j + 1];
-            s2 += D[(j + 2) * n] * v[j + 2];
-            s3 += D[(j + 3) * n] * v[j + 3];
+        // two independent partial sums so that the table loads are in flight together
+        double s0 = 0.0, s1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= cnt; k += 2) {
+            s0 += val[k * n] * v[max(0, jb + 4 * k)];
+            s1 += val[(k + 1) * n] * v[jb + 4 * k + 4];
         }
-        for (; j < n; ++j) s0 += D[j * n] * v[j];
-        out[h] = (s0 + s1) + (s2 + s3);
+        if (k < cnt) s0 += val[k * n] * v[max(0, jb + 4 * k)];
+        out[h] = s0 + s1;
     }
 }
 
@@ -207,6 +218,74 @@ __device__ inline void rotate_moments(const double* rot, double* v, double* t, i
     __syncthreads();
 }
 
+// rotate_moments on two tables at once (each with its own angles): every table row is loaded
+// once for both, and each table's arithmetic is exactly that of rotate_moments.
+__device__ void rot_phase2(double* va, double* vb, int L, const double* ca, const double* cb)
+{
+    const int NHl = nh(L);
+    for (int e = threadIdx.x; e < 2 * NHl; e += PAIR_WG) {
+        const bool b = e >= NHl;
+        const int h = b ? e - NHl : e;
+        const int l = l_of(h), off = h - l * l;
+        if (off & 1) {
+            const int m = (off + 1) >> 1;
+            const double* cs = b ? cb : ca;
+            double* v = b ? vb : va;
+            const double c = cs[2 * m], s = cs[2 * m + 1];
+            const double re = v[h], im = v[h + 1];
+            v[h] = c * re - s * im;
+            v[h + 1] = s * re + c * im;
+        }
+    }
+}
+
+__device__ void rot_matvec2(const double* tab, const double* ina, const double* inb, double* outa, double* outb,
+                            int L, bool inverse)
+{
+    const int NHl = nh(L);
+    for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
+        const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
+        int jb, cnt;
+        const double* val;
+        rot_row(tab, l, i, inverse, jb, cnt, val);
+        const double* va = ina + l * l;
+        const double* vb = inb + l * l;
+        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= cnt; k += 2) {
+            const int j0 = max(0, jb + 4 * k), j1 = jb + 4 * k + 4;
+            const double d0 = val[k * n], d1 = val[(k + 1) * n];
+            a0 += d0 * va[j0];
+            a1 += d1 * va[j1];
+            b0 += d0 * vb[j0];
+            b1 += d1 * vb[j1];
+        }
+        if (k < cnt) {
+            const int j0 = max(0, jb + 4 * k);
+            const double d0 = val[k * n];
+            a0 += d0 * va[j0];
+            b0 += d0 * vb[j0];
+        }
+        outa[h] = a0 + a1;
+        outb[h] = b0 + b1;
+    }
+}
+
+__device__ inline void rotate_moments2(const double* rot, double* va, double* vb, double* ta, double* tb, int L,
+                                       int Lm, const double* ca, const double* cb)
+{
+    rot_phase2(va, vb, L, ca, cb);
+    __syncthreads();
+    rot_matvec2(rot, va, vb, ta, tb, L, false);
+    __syncthreads();
+    rot_phase2(ta, tb, L, ca + 2 * (Lm + 1), cb + 2 * (Lm + 1));
+    __syncthreads();
+    rot_matvec2(rot, ta, tb, va, vb, L, true);
+    __syncthreads();
+    rot_phase2(va, vb, L, ca + 4 * (Lm + 1), cb + 4 * (Lm + 1));
+    __syncthreads();
+}
+
 // Contraction in the frame where R lies along the z axis.  Rotating A, B and R together leaves
 // eq. (9) unchanged; with R = |R| t, t = +-z, the irregular harmonics of t vanish for M != 0 and
 // I_{L'0}(t) = (+-1)^{L'} L'!, so with a, b the moments of A and B rotated into that frame and
@@ -234,8 +313,9 @@ __device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* s
     const int Lm = P.pair_lmax;
     double* sA = reinterpret_cast<double*>(smem);
     double* sB = sA + nh(Lm);
-    double* sT = sB + nh(Lm);                // rotation temporary
-    double* spow = sT + nh(Lm);              // R^-l, l <= Lm
+    double* tA = sB + nh(Lm);                // rotation temporaries
+    double* tB = tA + nh(Lm);
+    double* spow = tB + nh(Lm);              // R^-l, l <= Lm
     double* fac = spow + (Lm + 1);           // (+-1)^k k!, k <= 2Lm
     double* scsA = fac + (2 * Lm + 1);       // [3][Lm+1][2] each
     double* scsB = scsA + 6 * (Lm + 1);
@@ -273,8 +353,7 @@ __device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* s
         sB[h] = pw.QB[h] * sc;
     }
     __syncthreads();
-    rotate_moments(P.rot, sA, sT, L, Lm, scsA);
-    rotate_moments(P.rot, sB, sT, L, Lm, scsB);
+    rotate_moments2(P.rot, sA, sB, tA, tB, L, Lm, scsA, scsB);
     for (int h = tid; h < NHl; h += PAIR_WG) {
         sA[h] *= P.invf[h];
         sB[h] *= P.invf[h];

@@ -159,17 +159,54 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 // equispaced phi: exact for the degree-2l integrands).  The inverse follows from the
 // orthogonality norms g = 4pi/(2l+1) * (1 for m = 0, 1/2 for the Re/Im parts of m > 0):
 // invariance of the sphere measure gives D G D^T = G, so (D^{-1})_ij = D_ji g_i / g_j.
-// Layout: for each l, D then D^{-1}, (2l+1)^2 each, stored column by column (element (i, j)
-// at j (2l+1) + i), so that the lanes computing consecutive rows read consecutive addresses.
+// Both matrices are sparse: a 90 degree rotation about x maps each real basis function of one
+// cos / sin type and m parity onto functions of one type and one m parity, so row i's nonzero
+// columns are the packed indices max(0, jb_i + 4k), k = 0 .. cnt_i - 1 (a quarter of the
+// entries); every other entry is zero up to the quadrature's rounding, which is checked here.
+// Compressed layout (all doubles): hdr[l] = offset of order l's block, l = 0 .. Lmax; block l =
+// codes[2n] (rows of D, then of D^{-1}: (jb + 1) + 65536 cnt), then the nonzero values of D
+// and of D^{-1}, K = l/2 + 1 slots per row, stored slot by slot (row i's slot k at k n + i) so
+// that the lanes computing consecutive rows read consecutive addresses.
+static int compress_rotation(const std::vector<double>& dense, int n, double* codes, double* vals)
+{
+    const int l = (n - 1) / 2, K = l / 2 + 1;
+    double mx = 0.0;
+    for (double v : dense) mx = std::max(mx, std::fabs(v));
+    for (int i = 0; i < n; ++i) {
+        // the row's class from its largest entry: column 0 is (cos, m = 0), odd j is
+        // (cos, m = (j+1)/2), even j > 0 is (sin, m = j/2); the class holds every m of that
+        // parity and type (some members can vanish by accident, so they are kept)
+        int jm = 0;
+        for (int j = 1; j < n; ++j)
+            if (std::fabs(dense[i * n + j]) > std::fabs(dense[i * n + jm])) jm = j;
+        const bool sn = jm > 0 && !(jm & 1);
+        const int m = jm == 0 ? 0 : sn ? jm / 2 : (jm + 1) / 2;
+        const int m0 = sn ? ((m & 1) ? 1 : 2) : (m & 1);
+        const int jb = sn ? 2 * m0 : 2 * m0 - 1;
+        const int cnt = m0 <= l ? (l - m0) / 2 + 1 : 0;
+        if (cnt < 1 || cnt > K) return -1;
+        std::vector<char> in(n, 0);
+        for (int k = 0; k < cnt; ++k) {
+            const int j = std::max(0, jb + 4 * k);
+            in[j] = 1;
+            vals[(size_t)k * n + i] = dense[i * n + j];
+        }
+        for (int j = 0; j < n; ++j)          // nothing outside the class but rounding
+            if (!in[j] && std::fabs(dense[i * n + j]) > 1e-12 * mx) return -1;
+        codes[i] = (double)(jb + 1) + 65536.0 * (double)cnt;
+    }
+    return 0;
+}
+
 static std::vector<double> build_rotation_tables(int Lmax)
 {
-    size_t total = 0;
-    for (int l = 0; l <= Lmax; ++l) total += 2 * (size_t)(2 * l + 1) * (2 * l + 1);
-    std::vector<double> out(total, 0.0);
-    size_t off = 0;
+    std::vector<double> out((size_t)Lmax + 1, 0.0);
     std::vector<double> cp((Lmax + 1) * (Lmax + 1)), cx((Lmax + 1) * (Lmax + 1));
     for (int l = 0; l <= Lmax; ++l) {
-        const int n = 2 * l + 1;
+        const int n = 2 * l + 1, K = l / 2 + 1;
+        out[l] = (double)out.size();
+        const size_t base = out.size();
+        out.resize(base + 2 * (size_t)n + 2 * (size_t)K * n, 0.0);
         std::vector<double> gx, gw;
         gauss_legendre(l + 1, gx, gw);
         std::vector<double> D(n * n, 0.0);
@@ -189,13 +226,15 @@ static std::vector<double> build_rotation_tables(int Lmax)
         }
         const double g0 = 4.0 * M_PI / n;
         auto g = [&](int i) { return i == 0 ? g0 : 0.5 * g0; };
-        double* Dout = out.data() + off;
-        double* Dinv = Dout + n * n;
+        std::vector<double> Dd(n * n), Di(n * n);
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) Dout[j * n + i] = D[i * n + j] / g(j);
+            for (int j = 0; j < n; ++j) Dd[i * n + j] = D[i * n + j] / g(j);
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) Dinv[j * n + i] = D[j * n + i] / g(i) * g(i) / g(j);
-        off += 2 * (size_t)n * n;
+            for (int j = 0; j < n; ++j) Di[i * n + j] = Dd[j * n + i] * g(i) / g(j);
+        double* blk = out.data() + base;
+        if (compress_rotation(Dd, n, blk, blk + 2 * n) != 0 ||
+            compress_rotation(Di, n, blk + n, blk + 2 * n + (size_t)K * n) != 0)
+            return {};
     }
     return out;
 }
@@ -645,6 +684,10 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
     std::vector<double> invk, invf;
     build_norm_tables(LMAX, invk, invf);
     std::vector<double> rot = build_rotation_tables(LMAX);
+    if (rot.empty()) {                       // the rotation matrices lost their sparsity pattern
+        tcm_destroy(t);
+        return TCM_EDEVICE;
+    }
     int rc;
     if ((rc = c.alloc(c.t_invk, invk.size() * sizeof(double))) != TCM_OK ||
         (rc = c.alloc(c.t_invf, invf.size() * sizeof(double))) != TCM_OK ||
