@@ -610,22 +610,33 @@ hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, do
 // W_{l2 m2} = sum (-1)^{l2} a conj(I_{L'M}) (U = (1/R) Re sum b W), and likewise for A with
 // V_{l1 m1} = sum (-1)^{l2} b conj(I_{L'M}).
 //
+// All of it is evaluated in the frame where R lies along t = +-z (the pair kernel's frame:
+// A and B rotated there, B's pose folded in), where I_{L'M}(t) = delta_{M0} (+-1)^{L'} L'!:
+// Z keeps the M = 0 terms and S the M = -1 terms,
+//     S = sum (-1)^{l2} (+-1)^{L'+1} (L'+1)! sum_{k>=0} (-1)^{k+1} (a_{l1 k} conj(b_{l2,k+1}) + conj(a_{l1,k+1}) b_{l2 k}),
+// W_{l2 m2} = (-1)^{l2} sum_{l1} (+-1)^{L'} L'! a_{l1,-m2}, V_{l1 m1} = sum_{l2} (-1)^{l2} (+-1)^{L'} L'! b_{l2,-m1}:
+// O(L^3) in all.  Forces and torques are rotated back to the lab frame at the end.
+//
 // Per-atom forces at fixed centres: with What = W / R^{l+1} (the coefficients of U in the
 // moments of eq. (8) divided by f) and the factorial-scaled regular harmonics Rh of the
 // atom's position about its centre (d/dz Rh_lm = Rh_{l-1,m}, (d/dx + i d/dy) Rh_lm =
 // Rh_{l-1,m+1}, (d/dx - i d/dy) Rh_lm = -Rh_{l-1,m-1}), the force on atom i is
 //     F_i = -q_i sum_{l' < L, m' >= 0} (Re(X Rh), Im(Y Rh), Re(Z Rh))_{l' m'},
 // X = P - N, Y = P + N, Z = w_m' What_{l'+1, m'}, P = What_{l'+1, m'-1} (m' = 0:
-// -conj(What_{l'+1, 1})), N = What_{l'+1, m'+1} (m' >= 1, else 0), w = 1 (m' = 0) or 2.
+// -conj(What_{l'+1, 1})), N = What_{l'+1, m'+1} (m' >= 1, else 0), w = 1 (m' = 0) or 2.  The
+// tables hold the rotated frame's What, so the atoms are rotated into that frame (with B's
+// pose) and their forces rotated back.
 constexpr int FT_NSUM = 10;        // U, Z, Re S, Im S, dU/dtheta_B (3), dU/dtheta_A (3)
 constexpr int ATAB_ROW = 8;        // Xr Xi Yr Yi Zr Zi c1 c2
+constexpr int ATAB_HDR = 36;       // per side: position rotation [9], output rotation [9]
 
-__host__ __device__ constexpr int ni1(int Lm) { return (2 * Lm + 2) * (2 * Lm + 3) / 2; }
 __host__ __device__ constexpr int nrows(int L) { return (L + 1) * (L + 2) / 2; }
 __host__ __device__ constexpr int atab_rows(int L) { return L * (L + 1) / 2; }
 __host__ __device__ constexpr size_t ft_smem_bytes(int Lm)
 {
-    return sizeof(double) * (2 * (size_t)nh(Lm) + 2 * (size_t)ni1(Lm) + (2 * Lm + 3) + 6 * (Lm + 1) +
+    // sA, sB, tA, tB [nh], spow [Lm+3], fac [2Lm+2], scsA, scsB [6(Lm+1)], qq [8], rot [9],
+    // red [waves][FT_NSUM]
+    return sizeof(double) * (4 * (size_t)nh(Lm) + (Lm + 3) + (2 * Lm + 2) + 12 * (Lm + 1) + 8 + 9 +
                              (PAIR_WG / 64) * FT_NSUM);
 }
 
@@ -640,20 +651,6 @@ __device__ __forceinline__ void cget(const double* v, int l, int m, double& re, 
     if (m < 0) {
         im = -im;
         if (am & 1) { re = -re; im = -im; }
-    }
-}
-
-// conj(I_{Lp, M}) for any M (I_{L,-M} = (-1)^M conj(I_LM)); sI indexed Lp(Lp+1)/2 + M, M >= 0.
-__device__ __forceinline__ void iconj(const double* sI, int Lp, int M, double& re, double& im)
-{
-    const int aM = M < 0 ? -M : M;
-    if (aM > Lp) { re = 0.0; im = 0.0; return; }
-    const double* e = sI + 2 * (Lp * (Lp + 1) / 2 + aM);
-    re = e[0];
-    im = -e[1];
-    if (M < 0) {                           // conj((-1)^M conj(I)) = (-1)^M I
-        im = -im;
-        if (aM & 1) { re = -re; im = -im; }
     }
 }
 
@@ -675,9 +672,19 @@ __device__ __forceinline__ void jvec(const double* v, int l, int m, double* j)
     j[5] = m * br;
 }
 
+__device__ inline void quat_to_matrix(const double* q, double* M)
+{
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    M[0] = 1 - 2 * (y * y + z * z); M[1] = 2 * (x * y - w * z);     M[2] = 2 * (x * z + w * y);
+    M[3] = 2 * (x * y + w * z);     M[4] = 1 - 2 * (x * x + z * z); M[5] = 2 * (y * z - w * x);
+    M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
+}
+
 // One workgroup per pair: FT[out][10] = (U, F_B, tau_A, tau_B); wscr (when not null) gets
 // What (side B) then Vhat (side A), nrows(L) complex each, for the per-atom tables atab
-// (when not null: side A then side B, atab_rows(L) rows of ATAB_ROW doubles each).
+// (when not null: ATAB_HDR doubles of rotations, then side A then side B, atab_rows(L) rows of
+// ATAB_ROW doubles each).
 __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem, double* FT, double* wscr,
                                              double* atab)
 {
@@ -695,47 +702,52 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
     const int Lm = P.pair_lmax;
     double* sA = reinterpret_cast<double*>(smem);
     double* sB = sA + nh(Lm);
-    double* sI = sB + nh(Lm);                // complex, index L'(L'+1)/2 + M, L' <= 2L + 1
-    double* sT = sI;                         // rotation temporary (before sI is built)
-    double* spow = sI + 2 * ni1(Lm);         // R^-k, k <= 2L + 2
-    double* scs = spow + (2 * Lm + 3);
-    double* red = scs + 6 * (Lm + 1);        // [waves][FT_NSUM]
+    double* tA = sB + nh(Lm);
+    double* tB = tA + nh(Lm);
+    double* spow = tB + nh(Lm);              // R^-k, k <= L + 2
+    double* fac = spow + (Lm + 3);           // (+-1)^k k!, k <= 2L + 1
+    double* scsA = fac + (2 * Lm + 2);
+    double* scsB = scsA + 6 * (Lm + 1);
+    double* qq = scsB + 6 * (Lm + 1);        // frame quaternion, then B's
+    double* rot = qq + 8;                    // frame rotation matrix
+    double* red = rot + 9;                   // [waves][FT_NSUM]
     if (tid == 0) {
         const double ir = 1.0 / Rn;
         spow[0] = 1.0;
-        for (int l = 1; l <= 2 * L + 2; ++l) spow[l] = spow[l - 1] * ir;
+        for (int l = 1; l <= L + 2; ++l) spow[l] = spow[l - 1] * ir;
+        const double nx = Rx * ir, ny = Ry * ir, nz = Rz * ir, sg = nz < 0.0 ? -1.0 : 1.0;
+        double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx;
+        const double qn = sqrt(w * w + x * x + y * y);
+        w /= qn; x /= qn; y /= qn;
+        qq[0] = w; qq[1] = x; qq[2] = y; qq[3] = 0.0;
+        if (pw.has_rot) {
+            const double* q = pw.quat;
+            qq[4] = w * q[0] - x * q[1] - y * q[2];
+            qq[5] = w * q[1] + x * q[0] + y * q[3];
+            qq[6] = w * q[2] - x * q[3] + y * q[0];
+            qq[7] = w * q[3] + x * q[2] - y * q[1];
+        } else {
+            qq[4] = w; qq[5] = x; qq[6] = y; qq[7] = 0.0;
+        }
+        quat_to_matrix(qq, rot);
+        fac[0] = 1.0;
+        for (int k = 1; k <= 2 * L + 1; ++k) fac[k] = fac[k - 1] * (sg * k);
     }
-    if (pw.has_rot && tid <= L) euler_phases(pw.quat, tid, Lm, scs);
     __syncthreads();
+    if (tid <= L) {
+        euler_phases(qq, tid, Lm, scsA);
+        euler_phases(qq + 4, tid, Lm, scsB);
+    }
     for (int h = tid; h < NHl; h += PAIR_WG) {
         const double sc = spow[l_of(h)];
-        sA[h] = pw.QA[h] * sc * P.invf[h];
+        sA[h] = pw.QA[h] * sc;
         sB[h] = pw.QB[h] * sc;
     }
     __syncthreads();
-    if (pw.has_rot) rotate_moments(P.rot, sB, sT, L, Lm, scs);
-    for (int h = tid; h < NHl; h += PAIR_WG) sB[h] *= P.invf[h];
-    const int L2 = 2 * L + 1;
-    if (tid <= L2) {                         // column M of the irregular harmonics, L' = M .. 2L+1
-        const int M = tid;
-        const double nx = Rx / Rn, ny = Ry / Rn, nz = Rz / Rn;
-        double cr = 1.0, ci = 0.0;
-        for (int k = 1; k <= M; ++k) {
-            const double f = -(2.0 * k - 1.0);
-            const double tr = f * (cr * nx - ci * ny);
-            ci = f * (cr * ny + ci * nx);
-            cr = tr;
-        }
-        double pr = 0.0, pi = 0.0, qr = cr, qi = ci;
-        sI[2 * (M * (M + 1) / 2 + M)] = cr;
-        sI[2 * (M * (M + 1) / 2 + M) + 1] = ci;
-        for (int Lp = M + 1; Lp <= L2; ++Lp) {
-            const double a = 2.0 * Lp - 1.0, b = (Lp - 1.0) * (Lp - 1.0) - (double)M * M;
-            const double nr = a * nz * qr - b * pr, nim = a * nz * qi - b * pi;
-            pr = qr; pi = qi; qr = nr; qi = nim;
-            sI[2 * (Lp * (Lp + 1) / 2 + M)] = nr;
-            sI[2 * (Lp * (Lp + 1) / 2 + M) + 1] = nim;
-        }
+    rotate_moments2(P.rot, sA, sB, tA, tB, L, Lm, scsA, scsB);
+    for (int h = tid; h < NHl; h += PAIR_WG) {
+        sA[h] *= P.invf[h];
+        sB[h] *= P.invf[h];
     }
     __syncthreads();
     double acc[FT_NSUM];
@@ -749,62 +761,54 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
         const int m = rr - l * (l + 1) / 2;
         const double w = m == 0 ? 1.0 : 2.0;
         double j[6];
-        if (sideB) {                         // row (l2, m2) = (l, m): W, Wz, Wp, Wm
-            double Wr = 0, Wi = 0, Zr = 0, Zi = 0, Pr = 0, Pi = 0, Nr = 0, Ni = 0;
-            for (int l1 = 0; l1 <= L; ++l1) {
-                const int Lp = l1 + l;
-                for (int m1 = -l1; m1 <= l1; ++m1) {
-                    double ar, ai, cr, ci;
-                    cget(sA, l1, m1, ar, ai);
-                    const int M = m1 + m;
-                    iconj(sI, Lp, M, cr, ci);
-                    Wr += ar * cr - ai * ci;
-                    Wi += ar * ci + ai * cr;
-                    iconj(sI, Lp + 1, M, cr, ci);
-                    Zr += ar * cr - ai * ci;
-                    Zi += ar * ci + ai * cr;
-                    iconj(sI, Lp + 1, M + 1, cr, ci);
-                    Pr += ar * cr - ai * ci;
-                    Pi += ar * ci + ai * cr;
-                    iconj(sI, Lp + 1, M - 1, cr, ci);
-                    Nr += ar * cr - ai * ci;
-                    Ni += ar * ci + ai * cr;
-                }
+        if (sideB) {                         // W_{l m} = (-1)^l sum_{l1 >= m} fac[l1+l] a_{l1,-m}
+            double Wr = 0.0, Wi = 0.0;
+            for (int l1 = m; l1 <= L; ++l1) {
+                double ar, ai;
+                cget(sA, l1, -m, ar, ai);
+                Wr += fac[l1 + l] * ar;
+                Wi += fac[l1 + l] * ai;
             }
-            if (l & 1) { Wr = -Wr; Wi = -Wi; Zr = -Zr; Zi = -Zi; Pr = -Pr; Pi = -Pi; Nr = -Nr; Ni = -Ni; }
+            if (l & 1) { Wr = -Wr; Wi = -Wi; }
             double br, bi;
             cget(sB, l, m, br, bi);
             acc[0] += w * (br * Wr - bi * Wi);
-            acc[1] += w * (br * Zr - bi * Zi);
-            double sr = br * Pr - bi * Pi, si = br * Pi + bi * Pr;
-            if (m > 0) {                     // - conj(b Wm)
-                sr -= br * Nr - bi * Ni;
-                si += br * Ni + bi * Nr;
-            }
-            acc[2] += sr;
-            acc[3] += si;
             jvec(sB, l, m, j);
             for (int d = 0; d < 3; ++d) acc[4 + d] += w * (Wr * j[2 * d] - Wi * j[2 * d + 1]);
             if (wscr) {
                 wscr[2 * rr] = Wr * spow[l + 1];
                 wscr[2 * rr + 1] = Wi * spow[l + 1];
             }
-        } else {                             // row (l1, m1) = (l, m): V
-            double Vr = 0, Vi = 0;
-            for (int l2 = 0; l2 <= L; ++l2) {
-                const int Lp = l + l2;
-                double vr = 0, vi = 0;
-                for (int m2 = -l2; m2 <= l2; ++m2) {
-                    double br, bi, cr, ci;
-                    cget(sB, l2, m2, br, bi);
-                    iconj(sI, Lp, m + m2, cr, ci);
-                    vr += br * cr - bi * ci;
-                    vi += br * ci + bi * cr;
-                }
-                if (l2 & 1) { Vr -= vr; Vi -= vi; } else { Vr += vr; Vi += vi; }
+        } else {                             // V_{l m} = sum_{l2 >= m} (-1)^{l2} fac[l+l2] b_{l2,-m}; Z, S rows
+            double Vr = 0.0, Vi = 0.0, zr = 0.0, zi = 0.0, pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+            double ar, ai, ur, ui;           // a_{l m}, a_{l,m+1}
+            cget(sA, l, m, ar, ai);
+            cget(sA, l, m + 1, ur, ui);
+            for (int l2 = m; l2 <= L; ++l2) {
+                double br, bi, cr, ci;
+                cget(sB, l2, -m, br, bi);
+                const double f0 = (l2 & 1) ? -fac[l + l2] : fac[l + l2];
+                const double f1 = (l2 & 1) ? -fac[l + l2 + 1] : fac[l + l2 + 1];
+                Vr += f0 * br;
+                Vi += f0 * bi;
+                cget(sB, l2, m, br, bi);      // b_{l2 m}
+                zr += f1 * br;                // sum f1 conj(b_{l2 m})
+                zi -= f1 * bi;
+                qr += f1 * br;                // sum f1 b_{l2 m} (for conj(a_{l,m+1}) b_{l2 m})
+                qi += f1 * bi;
+                cget(sB, l2, m + 1, cr, ci);  // conj(b_{l2,m+1}) (zero when m + 1 > l2)
+                pr += f1 * cr;
+                pi -= f1 * ci;
             }
             jvec(sA, l, m, j);
             for (int d = 0; d < 3; ++d) acc[7 + d] += w * (Vr * j[2 * d] - Vi * j[2 * d + 1]);
+            const double zt = ar * zr - ai * zi;                  // Re(a_{l m} sum f1 conj(b_{l2 m}))
+            acc[1] += (m & 1) ? -w * zt : w * zt;
+            // S row: (-1)^{m+1} (a_{l m} sum f1 conj(b_{l2,m+1}) + conj(a_{l,m+1}) sum f1 b_{l2 m})
+            double sr = ar * pr - ai * pi, si = ar * pi + ai * pr;
+            sr += ur * qr + ui * qi;
+            si += ur * qi - ui * qr;
+            if (m & 1) { acc[2] += sr; acc[3] += si; } else { acc[2] -= sr; acc[3] -= si; }
             if (wscr) {
                 wscr[2 * (nr + rr)] = Vr * spow[l + 1];
                 wscr[2 * (nr + rr) + 1] = Vi * spow[l + 1];
@@ -823,18 +827,34 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
             for (int wv = 0; wv < PAIR_WG / 64; ++wv) t[k] += red[wv * FT_NSUM + k];
         }
         const double ir = spow[1], ir2 = spow[2];
+        // rotated frame: F_B = -(Re S, -Im S, -Z) / R^2, tau = -dU/dtheta / R
+        const double fp[3] = {-t[2] * ir2, t[3] * ir2, t[1] * ir2};
+        const double ta[3] = {-t[7] * ir, -t[8] * ir, -t[9] * ir};
+        const double tb[3] = {-t[4] * ir, -t[5] * ir, -t[6] * ir};
         out[0] = t[0] * ir;
-        out[1] = -t[2] * ir2;                // F_B = -grad U = -(Re S, -Im S, -Z) / R^2
-        out[2] = t[3] * ir2;
-        out[3] = t[1] * ir2;
-        for (int d = 0; d < 3; ++d) {
-            out[4 + d] = -t[7 + d] * ir;     // tau_A
-            out[7 + d] = -t[4 + d] * ir;     // tau_B
+        for (int d = 0; d < 3; ++d) {         // lab = rot^T rotated
+            out[1 + d] = rot[d] * fp[0] + rot[3 + d] * fp[1] + rot[6 + d] * fp[2];
+            out[4 + d] = rot[d] * ta[0] + rot[3 + d] * ta[1] + rot[6 + d] * ta[2];
+            out[7 + d] = rot[d] * tb[0] + rot[3 + d] * tb[1] + rot[6 + d] * tb[2];
+        }
+        if (atab) {                          // rotations for the per-atom kernel
+            double mb[9];
+            quat_to_matrix(qq + 4, mb);
+            for (int k = 0; k < 9; ++k) {
+                atab[k] = rot[k];             // A: positions into the frame
+                atab[18 + k] = mb[k];         // B: pose, then into the frame
+            }
+            for (int r2 = 0; r2 < 3; ++r2)
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    atab[9 + 3 * r2 + c2] = rot[3 * c2 + r2];    // forces back: rot^T
+                    atab[27 + 3 * r2 + c2] = rot[3 * c2 + r2];
+                }
         }
     }
     if (!atab || !wscr || L == 0) return;
     // per-atom tables, column by column (m' = 0 .. L-1, l' = m' .. L-1)
     const int na = atab_rows(L);
+    double* tabs = atab + ATAB_HDR;
     for (int e = tid; e < 2 * na; e += PAIR_WG) {
         const int side = e < na ? 0 : 1;     // 0: A (Vhat), 1: B (What)
         const int k = side ? e - na : e;
@@ -857,7 +877,7 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
         if (mp >= 1) W(lp + 1, mp + 1, Nr, Ni);
         W(lp + 1, mp, Zr, Zi);
         const double wz = mp == 0 ? 1.0 : 2.0;
-        double* row = atab + (size_t)ATAB_ROW * (side * na + k);
+        double* row = tabs + (size_t)ATAB_ROW * (side * na + k);
         row[0] = Pr - Nr;
         row[1] = Pi - Ni;
         row[2] = Pr + Nr;
@@ -881,18 +901,18 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
 __global__ __launch_bounds__(WG) void tcm_atom_forces(const double* __restrict__ T, int L,
                                                       const double* __restrict__ X, const double* __restrict__ Y,
                                                       const double* __restrict__ Zc, const double* __restrict__ Q,
-                                                      int64_t n, const double* __restrict__ centre, double r00,
-                                                      double r01, double r02, double r10, double r11, double r12,
-                                                      double r20, double r21, double r22, double* __restrict__ F)
+                                                      int64_t n, const double* __restrict__ centre,
+                                                      const double* __restrict__ mats, double* __restrict__ F)
 {
     const int64_t k = blockIdx.x * (int64_t)WG + threadIdx.x;
     if (k >= n) return;
-    const double dx = X[k] - centre[0], dy = Y[k] - centre[1], dz = Zc[k] - centre[2];
-    const double x = r00 * dx + r01 * dy + r02 * dz;
-    const double y = r10 * dx + r11 * dy + r12 * dz;
-    const double z = r20 * dx + r21 * dy + r22 * dz;
-    const double r2 = x * x + y * y + z * z;
     using crow = const __attribute__((address_space(4))) double*;
+    crow M = (crow)mats;                     // [9] into the table's frame, [9] back to the lab
+    const double dx = X[k] - centre[0], dy = Y[k] - centre[1], dz = Zc[k] - centre[2];
+    const double x = M[0] * dx + M[1] * dy + M[2] * dz;
+    const double y = M[3] * dx + M[4] * dy + M[5] * dz;
+    const double z = M[6] * dx + M[7] * dy + M[8] * dz;
+    const double r2 = x * x + y * y + z * z;
     crow row = (crow)T;
     double fx = 0.0, fy = 0.0, fz = 0.0, dr = 1.0, di = 0.0;       // Rh_mm
     for (int m = 0; m < L; ++m) {
@@ -916,10 +936,10 @@ __global__ __launch_bounds__(WG) void tcm_atom_forces(const double* __restrict__
             fz += row[4] * pr - row[5] * pi;
         }
     }
-    const double q = Q[k];
-    F[3 * k] = -q * fx;
-    F[3 * k + 1] = -q * fy;
-    F[3 * k + 2] = -q * fz;
+    const double q = -Q[k];
+    F[3 * k] = q * (M[9] * fx + M[10] * fy + M[11] * fz);
+    F[3 * k + 1] = q * (M[12] * fx + M[13] * fy + M[14] * fz);
+    F[3 * k + 2] = q * (M[15] * fx + M[16] * fy + M[17] * fz);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -1076,14 +1096,14 @@ hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, dou
     return hipGetLastError();
 }
 
-hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
-                              const double* q, int64_t n, const double* centre, const double* rot9, double* F,
-                              hipStream_t s)
+hipError_t launch_atom_forces(const double* atab, int side, int L, const double* x, const double* y, const double* z,
+                              const double* q, int64_t n, const double* centre, double* F, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + WG - 1) / WG;
+    const double* T = atab + ATAB_HDR + (size_t)ATAB_ROW * atab_rows(L) * side;
     hipLaunchKernelGGL(tcm_atom_forces, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, x, y, z, q, n, centre,
-                       rot9[0], rot9[1], rot9[2], rot9[3], rot9[4], rot9[5], rot9[6], rot9[7], rot9[8], F);
+                       atab + 18 * side, F);
     return hipGetLastError();
 }
 

@@ -1587,19 +1587,6 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
 }
 
 // ---------------------------------------------------------------- forces and torques
-static void quat_matrix(const double* quat, double* M)
-{
-    double w = 1, x = 0, y = 0, z = 0;
-    if (quat) {
-        const double qn = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
-        w = quat[0] / qn; x = quat[1] / qn; y = quat[2] / qn; z = quat[3] / qn;
-    }
-    const double m[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-    for (int k = 0; k < 9; ++k) M[k] = m[k];
-}
-
 constexpr int FT_N = 10;
 
 extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const double* R, const double* quat_b, int L,
@@ -1632,7 +1619,7 @@ extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const dou
     const int nr = (L + 1) * (L + 2) / 2, na = L * (L + 1) / 2;
     if ((rc = c.alloc(c.force_ft, sizeof(double) * FT_N)) != TCM_OK) return rc;
     if (atoms && ((rc = c.alloc(c.force_w, sizeof(double) * 4 * nr)) != TCM_OK ||
-                  (rc = c.alloc(c.force_t, sizeof(double) * 16 * (na > 0 ? na : 1))) != TCM_OK))
+                  (rc = c.alloc(c.force_t, sizeof(double) * (36 + 16 * (size_t)na))) != TCM_OK))
         return rc;
     if (launch_pairs_ft(bp.P, 0, 1, (double*)c.force_ft.p, atoms ? (double*)c.force_w.p : nullptr,
                         atoms ? (double*)c.force_t.p : nullptr, s) != hipSuccess)
@@ -1648,16 +1635,12 @@ extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const dou
         FA = forces_A ? (double*)c.force_a.p : nullptr;
         FB = forces_B ? (double*)c.force_b.p : nullptr;
     }
-    double I9[9], Q9[9];
-    quat_matrix(nullptr, I9);
-    quat_matrix(quat_b, Q9);
-    const double* tabA = (const double*)c.force_t.p;
-    const double* tabB = tabA + 8 * (size_t)na;
     // (at L = 0 the tables are empty and the kernel writes zero forces)
-    if (FA && launch_atom_forces(tabA, L, ma->x, ma->y, ma->z, ma->q, ma->n, (const double*)ma->meta.p, I9, FA, s) !=
+    const double* atab = (const double*)c.force_t.p;
+    if (FA && launch_atom_forces(atab, 0, L, ma->x, ma->y, ma->z, ma->q, ma->n, (const double*)ma->meta.p, FA, s) !=
                   hipSuccess)
         return TCM_EDEVICE;
-    if (FB && launch_atom_forces(tabB, L, mb->x, mb->y, mb->z, mb->q, mb->n, (const double*)mb->meta.p, Q9, FB, s) !=
+    if (FB && launch_atom_forces(atab, 1, L, mb->x, mb->y, mb->z, mb->q, mb->n, (const double*)mb->meta.p, FB, s) !=
                   hipSuccess)
         return TCM_EDEVICE;
     double ft[FT_N];

@@ -34,9 +34,9 @@ hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, dou
                            hipStream_t s);
 hipError_t launch_alu_probe(int prec, void* out, int blocks, int iters, hipStream_t s);
 hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s);
-hipError_t launch_atom_forces(const double* T, int L, const double* x, const double* y, const double* z,
-                              const double* q, int64_t n, const double* centre, const double* rot9, double* F,
-                              hipStream_t s);
+// Per-atom forces of side 0 (A) or 1 (B) from the tables launch_pairs_ft wrote to atab.
+hipError_t launch_atom_forces(const double* atab, int side, int L, const double* x, const double* y, const double* z,
+                              const double* q, int64_t n, const double* centre, double* F, hipStream_t s);
 
 struct Ctx;
 

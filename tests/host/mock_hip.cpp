@@ -61,8 +61,8 @@ hipError_t launch_scan(const double*, const double*, int, double, double, double
 hipError_t launch_alu_probe(int, void*, int, int, hipStream_t) { return 0; }
 hipError_t launch_abs_sum(const double*, int64_t, double* out, hipStream_t) { out[0] = 1.0; return 0; }
 hipError_t launch_pairs_ft(const DevPlan&, int, int, double*, double*, double*, hipStream_t) { return 0; }
-hipError_t launch_atom_forces(const double*, int, const double*, const double*, const double*, const double*, int64_t,
-                              const double*, const double*, double*, hipStream_t) { return 0; }
+hipError_t launch_atom_forces(const double*, int, int, const double*, const double*, const double*, const double*,
+                              int64_t, const double*, double*, hipStream_t) { return 0; }
 hipError_t launch_pairs(const DevPlan& P, int b, int e, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; double s = w.QA[0] + 1e-3 * w.QB[0];
         double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
