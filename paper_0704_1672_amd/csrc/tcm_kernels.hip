@@ -895,33 +895,43 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
     }
 }
 
-// One thread per atom: F[i][3] = -q_i sum over the table rows of (Re(X Rh), Im(Y Rh), Re(Z Rh))
-// with Rh the factorial-scaled regular harmonics of Rot (x_i - c); the rows are the same for
-// every lane (scalar loads).
+// F[i][3] = -q_i sum over the table rows of (Re(X Rh), Im(Y Rh), Re(Z Rh)) with Rh the
+// factorial-scaled regular harmonics of M (x_i - c), rotated back by M's second half.  A
+// workgroup takes 64 atoms; its four wavefronts split the m columns (column m holds L - m rows)
+// in snake order (waves 0 1 2 3 3 2 1 0 0 1 ...), each following the diagonal recurrence up to
+// its last column, and the four partial sums are added in wave order.  The table rows are the
+// same for every lane (scalar loads).
 __global__ __launch_bounds__(WG) void tcm_atom_forces(const double* __restrict__ T, int L,
                                                       const double* __restrict__ X, const double* __restrict__ Y,
                                                       const double* __restrict__ Zc, const double* __restrict__ Q,
                                                       int64_t n, const double* __restrict__ centre,
                                                       const double* __restrict__ mats, double* __restrict__ F)
 {
-    const int64_t k = blockIdx.x * (int64_t)WG + threadIdx.x;
-    if (k >= n) return;
+    __shared__ double part[WG / 64][3][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar table loads
+    const int64_t k = blockIdx.x * (int64_t)64 + lane;
+    const bool live = k < n;
     using crow = const __attribute__((address_space(4))) double*;
     crow M = (crow)mats;                     // [9] into the table's frame, [9] back to the lab
-    const double dx = X[k] - centre[0], dy = Y[k] - centre[1], dz = Zc[k] - centre[2];
+    const int64_t kk = live ? k : 0;
+    const double dx = X[kk] - centre[0], dy = Y[kk] - centre[1], dz = Zc[kk] - centre[2];
     const double x = M[0] * dx + M[1] * dy + M[2] * dz;
     const double y = M[3] * dx + M[4] * dy + M[5] * dz;
     const double z = M[6] * dx + M[7] * dy + M[8] * dz;
     const double r2 = x * x + y * y + z * z;
-    crow row = (crow)T;
+    crow tab = (crow)T;
     double fx = 0.0, fy = 0.0, fz = 0.0, dr = 1.0, di = 0.0;       // Rh_mm
     for (int m = 0; m < L; ++m) {
+        crow row = tab + (size_t)ATAB_ROW * (m * L - m * (m - 1) / 2);   // column m's diagonal row
         if (m > 0) {
             const double c2 = row[7];
             const double tr = (x * dr - y * di) * c2;
             di = (x * di + y * dr) * c2;
             dr = tr;
         }
+        const int g = m % 8;
+        if ((g < 4 ? g : 7 - g) != wave) continue;
         double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
         fx += row[0] * p1r - row[1] * p1i;
         fy += row[2] * p1i + row[3] * p1r;
@@ -936,10 +946,18 @@ __global__ __launch_bounds__(WG) void tcm_atom_forces(const double* __restrict__
             fz += row[4] * pr - row[5] * pi;
         }
     }
-    const double q = -Q[k];
-    F[3 * k] = q * (M[9] * fx + M[10] * fy + M[11] * fz);
-    F[3 * k + 1] = q * (M[12] * fx + M[13] * fy + M[14] * fz);
-    F[3 * k + 2] = q * (M[15] * fx + M[16] * fy + M[17] * fz);
+    part[wave][0][lane] = fx;
+    part[wave][1][lane] = fy;
+    part[wave][2][lane] = fz;
+    __syncthreads();
+    if (wave == 0 && live) {
+        double f[3];
+        for (int d = 0; d < 3; ++d) f[d] = ((part[0][d][lane] + part[1][d][lane]) + part[2][d][lane]) + part[3][d][lane];
+        const double q = -Q[k];
+        F[3 * k] = q * (M[9] * f[0] + M[10] * f[1] + M[11] * f[2]);
+        F[3 * k + 1] = q * (M[12] * f[0] + M[13] * f[1] + M[14] * f[2]);
+        F[3 * k + 2] = q * (M[15] * f[0] + M[16] * f[1] + M[17] * f[2]);
+    }
 }
 
 // ------------------------------------------------------------------ kernels
@@ -1100,7 +1118,7 @@ hipError_t launch_atom_forces(const double* atab, int side, int L, const double*
                               const double* q, int64_t n, const double* centre, double* F, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + WG - 1) / WG;
+    const int64_t blocks = (n + 63) / 64;    // 64 atoms per workgroup
     const double* T = atab + ATAB_HDR + (size_t)ATAB_ROW * atab_rows(L) * side;
     hipLaunchKernelGGL(tcm_atom_forces, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, x, y, z, q, n, centre,
                        atab + 18 * side, F);
