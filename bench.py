@@ -54,7 +54,8 @@ def measured_tile_traffic():
     return int(m.group(1)) if m else None
 
 
-def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, fractions=(0.5, 0.9)):
+def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, fractions=(0.5, 0.9), inflight=3,
+                    batch=64):
     """Serving workload: a pool of chain fragments (log-uniform 1e3..1e6 atoms) resident in HBM,
     a trace of nreq pair requests with L ~ U{8..24}; 70% name two new fragments (new keys, atoms
     referenced in place), 30% reuse the fragments of an earlier request with a new pose and
@@ -100,7 +101,7 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
     reqs = [make(i) for i in range(nreq)]
 
     def run(ctx, arrivals):
-        tcm.tcm_server_start(ctx.h, max_inflight_batches=3, max_batch_pairs=64, queue_capacity=nreq + 16)
+        tcm.tcm_server_start(ctx.h, max_inflight_batches=inflight, max_batch_pairs=batch, queue_capacity=nreq + 16)
         tickets = [None] * nreq
         lat = np.zeros(nreq)
         U = np.zeros(nreq)
@@ -138,6 +139,7 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
     out = {"workload": f"serving trace: {nreq} requests, pool of {pool} chain fragments ({ntot} atoms), "
                        "log-uniform 1e3..1e6 atoms, L ~ U{8..24}, 30% reuse of resident fragments, "
                        "R0 = 1.5(a_A+a_B), random poses; inputs resident in HBM (borrowed)",
+           "server": {"max_inflight_batches": inflight, "max_batch_pairs": batch},
            "saturation_pairs_per_s": sat, "burst_stats": stats, "statuses_ok": int(np.sum(st == 0))}
     rng = np.random.default_rng(55)
     gaps = rng.exponential(1.0, nreq)
@@ -381,6 +383,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-inflight", type=int, default=3, help="serving launches in flight at once")
+    ap.add_argument("--serve-batch", type=int, default=64, help="requests admitted into one serving launch")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--no-all-pairs", action="store_true")
     ap.add_argument("--no-forces", action="store_true")
@@ -534,7 +538,8 @@ def main():
     serving = None
     if not args.no_serve:
         t_s = time.time()
-        serving = serving_section(tcm, synth, torch, nreq=args.serve_requests)
+        serving = serving_section(tcm, synth, torch, nreq=args.serve_requests, inflight=args.serve_inflight,
+                                  batch=args.serve_batch)
         log(f"bench: serving section in {time.time() - t_s:.1f}s: "
             f"saturation {serving['saturation_pairs_per_s']:.0f} pairs/s, open loop {serving['open_loop']}")
 
