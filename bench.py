@@ -90,17 +90,18 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
     ext = w["extent"]
     dirs = w["R"] / np.linalg.norm(w["R"], axis=1)[:, None]
 
-    def make(i):
+    def make(i, borrow=True):
         ka, fa, kb, fb, new = recs[i]
         R = 1.5 * (ext[fa] + ext[fb]) * dirs[i]
         return tcm.make_request(ka, kb, R, int(w["L"][i]), w["quats"][i],
                                 atoms_a=ptrs(fa) if new else None, n_a=int(w["counts"][fa]),
                                 atoms_b=ptrs(fb) if new else None, n_b=int(w["counts"][fb]),
-                                flags=tcm.TCM_BORROW_ATOMS)
+                                flags=tcm.TCM_BORROW_ATOMS if borrow else 0)
 
     reqs = [make(i) for i in range(nreq)]
 
-    def run(ctx, arrivals):
+    def run(ctx, arrivals, rq=None):
+        rq = reqs if rq is None else rq
         tcm.tcm_server_start(ctx.h, max_inflight_batches=inflight, max_batch_pairs=batch, queue_capacity=nreq + 16)
         tickets = [None] * nreq
         lat = np.zeros(nreq)
@@ -113,7 +114,7 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
         while done < nreq:
             now = time.perf_counter() - t0
             while i < nreq and (arrivals is None or arrivals[i] <= now):
-                rc, tk = tcm.tcm_submit(ctx.h, reqs[i])
+                rc, tk = tcm.tcm_submit(ctx.h, rq[i])
                 assert rc == 0
                 tickets[i] = tk
                 pending.append(i)
@@ -153,6 +154,21 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
     out["open_loop"] = loads
     # alone vs in the mix: every served result equals the burst's bit for bit
     out["alone_vs_mix_bitwise_equal"] = bool(np.array_equal(Uf, U))
+    # a binding HBM budget: the atoms copied into server memory (not borrowed), 512 MiB for
+    # atoms, moment tables and launch workspaces, so fragments are evicted least recently used
+    # first; a request whose resident fragment was evicted reports TCM_ENOTFOUND
+    budget = 512 << 20
+    ctxb = tcm.Context(0)
+    tcm.tcm_set_budget(ctxb.h, budget)
+    reqs_c = [make(i, borrow=False) for i in range(nreq)]
+    Ub, stb, latb, elb, stsb = run(ctxb, None, reqs_c)
+    ok = stb == 0
+    out["binding_budget"] = {
+        "budget_bytes": budget, "atoms": "copied into server memory",
+        "saturation_pairs_per_s": nreq / elb, "server_stats": stsb,
+        "statuses": {str(int(v)): int(np.sum(stb == v)) for v in np.unique(stb)},
+        "ok_results_equal_unbounded_bitwise": bool(np.array_equal(Ub[ok], U[ok]))}
+    ctxb.close()
     # plain single-pair GPU path on the same trace
     ids = {}
     for f in range(pool):
@@ -395,8 +411,8 @@ def main():
                          "point for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU path is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
