@@ -761,11 +761,12 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
         const int m = rr - l * (l + 1) / 2;
         const double w = m == 0 ? 1.0 : 2.0;
         double j[6];
+        const double sm = (m & 1) ? -1.0 : 1.0;  // v_{l,-m} = (-1)^m conj(v_{l m})
+        const int om = m == 0 ? 0 : 2 * m - 1;    // offset of (Re, Im) of m in an order's block
         if (sideB) {                         // W_{l m} = (-1)^l sum_{l1 >= m} fac[l1+l] a_{l1,-m}
             double Wr = 0.0, Wi = 0.0;
             for (int l1 = m; l1 <= L; ++l1) {
-                double ar, ai;
-                cget(sA, l1, -m, ar, ai);
+                const double ar = sm * sA[l1 * l1 + om], ai = m == 0 ? 0.0 : -sm * sA[l1 * l1 + om + 1];
                 Wr += fac[l1 + l] * ar;
                 Wi += fac[l1 + l] * ai;
             }
@@ -785,20 +786,20 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
             cget(sA, l, m, ar, ai);
             cget(sA, l, m + 1, ur, ui);
             for (int l2 = m; l2 <= L; ++l2) {
-                double br, bi, cr, ci;
-                cget(sB, l2, -m, br, bi);
+                const double* bl = sB + l2 * l2;
+                const double br = bl[om], bi = m == 0 ? 0.0 : bl[om + 1];     // b_{l2 m}
                 const double f0 = (l2 & 1) ? -fac[l + l2] : fac[l + l2];
                 const double f1 = (l2 & 1) ? -fac[l + l2 + 1] : fac[l + l2 + 1];
-                Vr += f0 * br;
-                Vi += f0 * bi;
-                cget(sB, l2, m, br, bi);      // b_{l2 m}
+                Vr += f0 * (sm * br);         // b_{l2,-m}
+                Vi += f0 * (-sm * bi);
                 zr += f1 * br;                // sum f1 conj(b_{l2 m})
                 zi -= f1 * bi;
                 qr += f1 * br;                // sum f1 b_{l2 m} (for conj(a_{l,m+1}) b_{l2 m})
                 qi += f1 * bi;
-                cget(sB, l2, m + 1, cr, ci);  // conj(b_{l2,m+1}) (zero when m + 1 > l2)
-                pr += f1 * cr;
-                pi -= f1 * ci;
+                if (m + 1 <= l2) {            // conj(b_{l2,m+1})
+                    pr += f1 * bl[2 * m + 1];
+                    pi -= f1 * bl[2 * m + 2];
+                }
             }
             jvec(sA, l, m, j);
             for (int d = 0; d < 3; ++d) acc[7 + d] += w * (Vr * j[2 * d] - Vi * j[2 * d + 1]);
