@@ -36,6 +36,33 @@ int Ctx::alloc(DevBuf& b, size_t bytes)
     return TCM_OK;
 }
 
+int Ctx::alloc_async(DevBuf& b, size_t bytes, hipStream_t s)
+{
+    if (bytes <= b.cap && b.p) return TCM_OK;
+    release_async(b, s);
+    const size_t want = bytes < 256 ? 256 : bytes;
+    if (budget && used.load() + want > budget) return TCM_ENOMEM;
+    void* p = nullptr;
+    if (hipMallocAsync(&p, want, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return TCM_ENOMEM;
+    }
+    b.p = p;
+    b.cap = want;
+    used += want;
+    return TCM_OK;
+}
+
+void Ctx::release_async(DevBuf& b, hipStream_t s)
+{
+    if (b.p) {
+        (void)hipFreeAsync(b.p, s);
+        used -= b.cap;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+}
+
 void Ctx::release(DevBuf& b)
 {
     if (b.p) {
@@ -681,6 +708,14 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
         return TCM_EDEVICE;
     }
     c.stream = c.own_stream;
+    {   // stream-ordered allocations return to a pool that keeps up to the budget's worth of
+        // freed memory, so that freeing and re-allocating fragments costs no device sync
+        hipMemPool_t pool;
+        uint64_t keep = budget ? (uint64_t)budget : UINT64_MAX;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess)
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        (void)hipGetLastError();
+    }
     std::vector<double> invk, invf;
     build_norm_tables(LMAX, invk, invf);
     std::vector<double> rot = build_rotation_tables(LMAX);

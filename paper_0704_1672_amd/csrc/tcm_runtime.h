@@ -146,6 +146,10 @@ struct Ctx {
 
     int alloc(DevBuf& b, size_t bytes);      // grow-only, budget checked
     void release(DevBuf& b);
+    // Stream-ordered variants (the device's default pool keeps freed memory cached), for
+    // buffers allocated and freed while other launches run: no device-wide synchronisation.
+    int alloc_async(DevBuf& b, size_t bytes, hipStream_t s);
+    void release_async(DevBuf& b, hipStream_t s);
     int ensure_pinned(size_t bytes);
     int kper_for(int prec, int L, int64_t n);
 };

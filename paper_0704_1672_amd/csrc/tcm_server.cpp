@@ -100,9 +100,11 @@ static double seconds_since(clock_t_::time_point t)
     return std::chrono::duration<double>(clock_t_::now() - t).count();
 }
 
-static void free_mol(Server* S, SMol* m)
+// Copied atoms are freed in stream order on `s`: no launch still reads them (refs == 0 or the
+// fragment was never launched), and the pool orders any reuse behind this point of `s`.
+static void free_mol(Server* S, SMol* m, hipStream_t s)
 {
-    S->c->release(m->atoms);
+    S->c->release_async(m->atoms, s);
     if (m->slot >= 0) S->free_slots.push_back(m->slot);
     m->slot = -1;
     m->moments = nullptr;
@@ -136,7 +138,7 @@ static bool evictable(const SMol* m) { return m->refs == 0 && m->pin == 0 && !m-
 
 // Evict idle fragments (least recently used first) until `need` more bytes fit the budget.
 // Evicts nothing when even evicting every idle fragment would not make enough room.
-static bool make_room(Server* S, size_t need)
+static bool make_room(Server* S, size_t need, hipStream_t s)
 {
     Ctx* c = S->c;
     const size_t budget = c->budget;
@@ -153,7 +155,7 @@ static bool make_room(Server* S, size_t need)
         auto f = S->cache.find(*it);
         SMol* m = f->second.get();
         if (evictable(m)) {
-            free_mol(S, m);
+            free_mol(S, m, s);
             it = S->lru.erase(it);
             S->cache.erase(f);
             ++S->evictions;
@@ -163,10 +165,10 @@ static bool make_room(Server* S, size_t need)
 }
 
 // Remove a fragment created by the current admission pass that will not be used.
-static void destroy_mol(Server* S, SMol* m)
+static void destroy_mol(Server* S, SMol* m, hipStream_t s)
 {
     const int64_t key = m->key;
-    free_mol(S, m);
+    free_mol(S, m, s);
     S->lru.erase(m->lru);
     S->cache.erase(key);
 }
@@ -267,13 +269,13 @@ static void admit_and_launch(Server* S, Slot& sl)
         if (flags & TCM_BORROW_ATOMS) {
             for (int k = 0; k < 4; ++k) m->src[k] = atoms[k];
         } else {
-            if (c->alloc(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1)) != TCM_OK) {
-                free_mol(S, m.get());
+            if (c->alloc_async(m->atoms, sizeof(double) * 4 * (size_t)(n > 0 ? n : 1), sl.stream) != TCM_OK) {
+                free_mol(S, m.get(), sl.stream);
                 *status = TCM_EAGAIN;
                 return nullptr;
             }
             if (copy_atoms(m.get(), atoms, (flags & TCM_HOST_ATOMS) != 0, sl.stream) != TCM_OK) {
-                free_mol(S, m.get());
+                free_mol(S, m.get(), sl.stream);
                 *status = TCM_EDEVICE;
                 return nullptr;
             }
@@ -333,7 +335,7 @@ static void admit_and_launch(Server* S, Slot& sl)
             // resident sides of this request must survive the eviction
             if (sa.m) ++sa.m->pin;
             if (sb.m) ++sb.m->pin;
-            const bool ok = make_room(S, bytes);
+            const bool ok = make_room(S, bytes, sl.stream);
             if (sa.m) --sa.m->pin;
             if (sb.m) --sb.m->pin;
             if (!ok) return TCM_EAGAIN;
@@ -347,7 +349,7 @@ static void admit_and_launch(Server* S, Slot& sl)
             b = create(r.key_b, r.atoms_b, r.n_b, r.precision, r.flags, &st);
             --a->pin;
             if (!b) {
-                if (sa.fresh) destroy_mol(S, a);      // no copy may outlive a deferred request
+                if (sa.fresh) destroy_mol(S, a, sl.stream);      // no copy may outlive a deferred request
                 return st;
             }
         }
@@ -462,7 +464,7 @@ static void admit_and_launch(Server* S, Slot& sl)
     }
     int rc = sl.cap >= cap ? TCM_OK : TCM_ENOMEM;
     // the launch's workspace comes out of the same budget: evict idle fragments first
-    if (rc == TCM_OK) (void)make_room(S, workspace_growth(c, sl.ws, mj, pj));
+    if (rc == TCM_OK) (void)make_room(S, workspace_growth(c, sl.ws, mj, pj), sl.stream);
     if (rc == TCM_OK) rc = build_plan(c, sl.ws, mj, pj, sl.bp, sl.stream);
     if (rc == TCM_OK) rc = run_plan(c, sl.bp, sl.stream, false, nullptr);
     double* hU = (double*)sl.hpin;
@@ -536,7 +538,8 @@ void server_destroy(Ctx* c)
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
-    for (auto& kv : S->cache) free_mol(S, kv.second.get());
+    for (auto& kv : S->cache) free_mol(S, kv.second.get(), nullptr);
+    (void)hipStreamSynchronize(nullptr);
     for (DevBuf& b : S->arena) c->release(b);
     delete S;
     c->server = nullptr;

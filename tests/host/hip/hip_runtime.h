@@ -19,11 +19,17 @@ typedef struct ihipEvent_t* hipEvent_t;
 typedef struct ihipGraph_t* hipGraph_t;
 typedef struct ihipGraphExec_t* hipGraphExec_t;
 typedef struct { int multiProcessorCount; } hipDeviceProp_t;
+typedef struct ihipMemPool_t* hipMemPool_t;
+enum hipMemPoolAttr { hipMemPoolAttrReleaseThreshold = 4 };
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
 enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0, hipEventDisableTiming = 2, hipStreamCaptureModeThreadLocal = 1 };
 extern "C" {
 hipError_t hipMalloc(void** p, size_t n);
 hipError_t hipFree(void* p);
+hipError_t hipMallocAsync(void** p, size_t n, hipStream_t s);
+hipError_t hipFreeAsync(void* p, hipStream_t s);
+hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t* pool, int device);
+hipError_t hipMemPoolSetAttribute(hipMemPool_t pool, hipMemPoolAttr attr, void* value);
 hipError_t hipHostMalloc(void** p, size_t n, unsigned f);
 hipError_t hipHostFree(void* p);
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st);

@@ -14,6 +14,10 @@ static const int g_delay = getenv("MOCK_DELAY") ? atoi(getenv("MOCK_DELAY")) : 3
 extern "C" {
 hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); if (*p) memset(*p, 0xAB, n); return *p ? 0 : 2; }
 hipError_t hipFree(void* p) { free(p); return 0; }
+hipError_t hipMallocAsync(void** p, size_t n, hipStream_t) { return hipMalloc(p, n); }
+hipError_t hipFreeAsync(void* p, hipStream_t) { free(p); return 0; }
+hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t* pool, int) { *pool = nullptr; return 0; }
+hipError_t hipMemPoolSetAttribute(hipMemPool_t, hipMemPoolAttr, void*) { return 0; }
 hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = malloc(n); return *p ? 0 : 2; }
 hipError_t hipHostFree(void* p) { free(p); return 0; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { memcpy(d, s, n); return 0; }
