@@ -1001,11 +1001,16 @@ struct ReqPlan {
     std::vector<int> pj_req;                 // request index of each pair job
     std::vector<std::pair<Mol*, int>> computed;
     std::vector<int32_t> pre_status;         // per request: TCM_OK or a host-side error
+    std::vector<Mol*> side;                  // per request: its two molecules (null on error)
 };
 
 int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse, ReqPlan& rp)
 {
-    std::map<int64_t, int> need;             // mol id -> required order (-1 = reuse)
+    // one pass over the requests: each molecule's required order kept in its planning scratch
+    // (touched lists the molecules in first-use order; ordered by id below)
+    std::vector<Mol*> touched;
+    std::vector<Mol*>& side = rp.side;
+    side.assign((size_t)2 * np, nullptr);
     rp.pre_status.assign(np, TCM_OK);
     for (int64_t i = 0; i < np; ++i) {
         const tcm_pair_req& r = reqs[i];
@@ -1020,24 +1025,27 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
             rp.pre_status[i] = TCM_ENOTFOUND;
             continue;
         }
-        for (Mol* m : {ia->second.get(), ib->second.get()}) {
+        side[2 * i] = ia->second.get();
+        side[2 * i + 1] = ib->second.get();
+        for (Mol* m : {side[2 * i], side[2 * i + 1]}) {
             const bool reuse = allow_reuse && (r.flags & TCM_REUSE) && m->Lcached >= r.L;
             const int want = reuse ? -1 : r.L;
-            auto it = need.find(m->id);
-            if (it == need.end()) need[m->id] = want;
-            else if (want > it->second) it->second = want;
+            if (m->plan_want == INT32_MIN) {
+                touched.push_back(m);
+                m->plan_want = want;
+            } else if (want > m->plan_want) {
+                m->plan_want = want;
+            }
         }
     }
-    std::map<int64_t, int> jobidx;
-    for (auto& kv : need) {
-        if (kv.second < 0) continue;
-        Mol* m = c.mols[kv.first].get();
-        int L = kv.second;
+    std::sort(touched.begin(), touched.end(), [](const Mol* u, const Mol* v) { return u->id < v->id; });
+    int rc = TCM_OK;
+    for (Mol* m : touched) {
+        if (m->plan_want < 0) continue;
+        int L = m->plan_want;
         if (m->Lcached > L) L = m->Lcached;
-        if (m->moments.cap < sizeof(double) * nh(L)) {
-            int rc = c.alloc(m->moments, sizeof(double) * nh(L));
-            if (rc != TCM_OK) return rc;
-        }
+        if (m->moments.cap < sizeof(double) * nh(L) && (rc = c.alloc(m->moments, sizeof(double) * nh(L))) != TCM_OK)
+            break;
         MolJob j{};
         j.x = m->x; j.y = m->y; j.z = m->z; j.q = m->q;
         j.n = m->n;
@@ -1047,36 +1055,43 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
         for (int d = 0; d < 3; ++d) j.centre[d] = m->centre[d];
         j.Q = (double*)m->moments.p;
         j.meta = (double*)m->meta.p;
-        jobidx[m->id] = (int)rp.mj.size();
+        m->plan_job = (int)rp.mj.size();
         rp.mj.push_back(j);
         rp.computed.push_back({m, L});
         m->Lcached = -1;                      // invalid until this run completes
         m->radius_host = -1.0;
         m->absq_host = -1.0;
     }
-    for (int64_t i = 0; i < np; ++i) {
-        if (rp.pre_status[i] != TCM_OK) continue;
-        const tcm_pair_req& r = reqs[i];
-        Mol* a = c.mols[r.a].get();
-        Mol* b = c.mols[r.b].get();
-        PairJob j{};
-        j.QA = (const double*)a->moments.p;
-        j.QB = (const double*)b->moments.p;
-        j.metaA = (const double*)a->meta.p;
-        j.metaB = (const double*)b->meta.p;
-        auto fa = jobidx.find(a->id), fb = jobidx.find(b->id);
-        j.depA = fa == jobidx.end() ? -1 : fa->second;
-        j.depB = fb == jobidx.end() ? -1 : fb->second;
-        j.L = r.L;
-        j.flags = r.flags;
-        for (int d = 0; d < 3; ++d) j.R[d] = r.R[d];
-        for (int d = 0; d < 4; ++d) j.quat[d] = r.quat_b[d];
-        j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
-        rp.pj.push_back(j);
-        rp.pj_req.push_back((int)i);
-        a->last_use = b->last_use = ++c.use_clock;
+    if (rc == TCM_OK) {
+        rp.pj.reserve(np);
+        rp.pj_req.reserve(np);
+        for (int64_t i = 0; i < np; ++i) {
+            if (rp.pre_status[i] != TCM_OK) continue;
+            const tcm_pair_req& r = reqs[i];
+            Mol* a = side[2 * i];
+            Mol* b = side[2 * i + 1];
+            PairJob j{};
+            j.QA = (const double*)a->moments.p;
+            j.QB = (const double*)b->moments.p;
+            j.metaA = (const double*)a->meta.p;
+            j.metaB = (const double*)b->meta.p;
+            j.depA = a->plan_job;
+            j.depB = b->plan_job;
+            j.L = r.L;
+            j.flags = r.flags;
+            for (int d = 0; d < 3; ++d) j.R[d] = r.R[d];
+            for (int d = 0; d < 4; ++d) j.quat[d] = r.quat_b[d];
+            j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
+            rp.pj.push_back(j);
+            rp.pj_req.push_back((int)i);
+            a->last_use = b->last_use = ++c.use_clock;
+        }
     }
-    return TCM_OK;
+    for (Mol* m : touched) {
+        m->plan_want = INT32_MIN;
+        m->plan_job = -1;
+    }
+    return rc;
 }
 
 void mark_computed(ReqPlan& rp)
@@ -1142,12 +1157,11 @@ static int first_error(const int32_t* st, int64_t n)
 }
 
 // The batch path with the context locked and current.
-static int batch_energy_locked(Ctx& c, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
+// Run planned requests (moment jobs and pair jobs) and scatter the results to request order.
+static int run_requests(Ctx& c, ReqPlan& rp, int64_t np, double* U_out, int32_t* status_out)
 {
     hipStream_t s = c.stream;
-    ReqPlan rp;
-    int rc = plan_requests(c, reqs, np, true, rp);
-    if (rc != TCM_OK) return rc;
+    int rc;
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
     if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
@@ -1168,6 +1182,14 @@ static int batch_energy_locked(Ctx& c, const tcm_pair_req* reqs, int64_t np, dou
         U_out[rp.pj_req[k]] = st[k] == TCM_OK ? U[k] : std::nan("");
     }
     return first_error(status_out, np);
+}
+
+static int batch_energy_locked(Ctx& c, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
+{
+    ReqPlan rp;
+    int rc = plan_requests(c, reqs, np, true, rp);
+    if (rc != TCM_OK) return rc;
+    return run_requests(c, rp, np, U_out, status_out);
 }
 
 extern "C" int tcm_batch_energy(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double* U_out, int32_t* status_out)
@@ -1536,13 +1558,8 @@ extern "C" int tcm_alu_calibrate(tcm_ctx* t, int precision, double* tflops_out)
 // Bound on |U_coulomb - U_L| for the square truncation: with alpha = a_A/R, beta = a_B/R and
 // S = sum |q|, the (l1, l2) term of the double Taylor series of 1/|R + r_B - r_A| is at most
 // C(l1+l2, l1) a_A^l1 a_B^l2 / R^{l1+l2+1}, and summing the terms outside the square gives
-// S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L+1} + (beta/(1-alpha))^{L+1}].
-static double trunc_bound(double SA, double SB, double aA, double aB, double R, int L)
-{
-    const double al = aA / R, be = aB / R;
-    if (!(al + be < 1.0)) return INFINITY;
-    return SA * SB / (R * (1.0 - al - be)) * (std::pow(al / (1.0 - be), L + 1) + std::pow(be / (1.0 - al), L + 1));
-}
+// S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L+1} + (beta/(1-alpha))^{L+1}]
+// (infinite when alpha + beta >= 1).
 
 extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double tol, double* U_out,
                                          int32_t* L_out, double* bound_out, int32_t* status_out)
@@ -1563,17 +1580,19 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
         if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
         if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
         mark_computed(rp);
+        rp.mj.clear();                       // resident from here on: the pair jobs depend on none
+        rp.computed.clear();
+        for (PairJob& j : rp.pj) j.depA = j.depB = -1;
     }
     // 2. radius and sum |q| of every molecule involved (read once per computation)
     std::vector<Mol*> need;
     for (int64_t i = 0; i < np; ++i) {
         if (rp.pre_status[i] != TCM_OK) continue;
-        for (tcm_mol_id id : {reqs[i].a, reqs[i].b}) {
-            Mol* m = c.mols[id].get();
-            if ((m->radius_host < 0.0 || m->absq_host < 0.0) && std::find(need.begin(), need.end(), m) == need.end())
-                need.push_back(m);
-        }
+        for (Mol* m : {rp.side[2 * i], rp.side[2 * i + 1]})
+            if (m->radius_host < 0.0 || m->absq_host < 0.0) need.push_back(m);
     }
+    std::sort(need.begin(), need.end(), [](const Mol* u, const Mol* v) { return u->id < v->id; });
+    need.erase(std::unique(need.begin(), need.end()), need.end());
     if (!need.empty()) {
         if ((rc = c.alloc(c.absq, sizeof(double) * need.size())) != TCM_OK) return rc;
         std::vector<double> meta(need.size() * 8), sq(need.size());
@@ -1590,32 +1609,39 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
             need[k]->absq_host = sq[k];
         }
     }
-    // 3. per pair, the smallest order whose bound meets tol (the maximum if none does)
-    std::vector<tcm_pair_req> rq(reqs, reqs + np);
+    // 3. per pair, the smallest order whose bound meets tol (the maximum if none does), set
+    //    in the planned pair jobs, which then run against the resident moments
+    std::vector<int32_t> Lch((size_t)np, -1);
     std::vector<double> bnd((size_t)np, std::nan(""));
-    for (int64_t i = 0; i < np; ++i) {
-        if (rp.pre_status[i] != TCM_OK) continue;
-        const Mol* ma = c.mols[reqs[i].a].get();
-        const Mol* mb = c.mols[reqs[i].b].get();
+    for (size_t k = 0; k < rp.pj.size(); ++k) {
+        const int64_t i = rp.pj_req[k];
+        const Mol* ma = rp.side[2 * i];
+        const Mol* mb = rp.side[2 * i + 1];
         const double R = std::sqrt(reqs[i].R[0] * reqs[i].R[0] + reqs[i].R[1] * reqs[i].R[1] + reqs[i].R[2] * reqs[i].R[2]);
+        // the bound at l = 0, 1, ... by running products of the two ratios (no pow per order)
         int L = reqs[i].L;
-        double b = trunc_bound(ma->absq_host, mb->absq_host, ma->radius_host, mb->radius_host, R, L);
-        for (int l = 0; l < reqs[i].L; ++l) {
-            const double bl = trunc_bound(ma->absq_host, mb->absq_host, ma->radius_host, mb->radius_host, R, l);
-            if (bl <= tol) {
-                L = l;
-                b = bl;
-                break;
+        double b = INFINITY;
+        const double al = ma->radius_host / R, be = mb->radius_host / R;
+        if (al + be < 1.0) {
+            const double pre = ma->absq_host * mb->absq_host / (R * (1.0 - al - be));
+            const double r1 = al / (1.0 - be), r2 = be / (1.0 - al);
+            double p1 = r1, p2 = r2;
+            for (int l = 0;; ++l, p1 *= r1, p2 *= r2) {
+                b = pre * (p1 + p2);
+                if (b <= tol || l == reqs[i].L) {
+                    L = l;
+                    break;
+                }
             }
         }
-        rq[i].L = L;
-        rq[i].flags |= TCM_REUSE;
+        rp.pj[k].L = L;
+        Lch[i] = L;
         bnd[i] = b;
     }
-    // 4. the contractions at the chosen orders (moments resident at the maximum order)
-    rc = batch_energy_locked(c, rq.data(), np, U_out, status_out);
+    // 4. the contractions at the chosen orders
+    rc = run_requests(c, rp, np, U_out, status_out);
     for (int64_t i = 0; i < np; ++i) {
-        if (L_out) L_out[i] = status_out[i] == TCM_OK ? rq[i].L : -1;
+        if (L_out) L_out[i] = status_out[i] == TCM_OK ? Lch[i] : -1;
         if (bound_out) bound_out[i] = status_out[i] == TCM_OK ? bnd[i] : std::nan("");
     }
     return rc;

@@ -64,6 +64,8 @@ struct Mol {
                                    // whenever the moments are recomputed
     double absq_host = -1.0;       // sum |q_i| (truncation bound), -1 until computed; reset likewise
     uint64_t last_use = 0;
+    int plan_want = INT32_MIN;     // scratch of one request planning pass (under the context
+    int plan_job = -1;             // lock): required order (-1 = reuse) and moment job index
 };
 
 // Everything one launch needs, described on the host.

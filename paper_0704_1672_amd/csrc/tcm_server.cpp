@@ -540,6 +540,11 @@ void server_destroy(Ctx* c)
     }
     for (auto& kv : S->cache) free_mol(S, kv.second.get(), nullptr);
     (void)hipStreamSynchronize(nullptr);
+    {   // hand the pool's cached fragment memory back to the device
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+        (void)hipGetLastError();
+    }
     for (DevBuf& b : S->arena) c->release(b);
     delete S;
     c->server = nullptr;

@@ -30,6 +30,7 @@ hipError_t hipMallocAsync(void** p, size_t n, hipStream_t s);
 hipError_t hipFreeAsync(void* p, hipStream_t s);
 hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t* pool, int device);
 hipError_t hipMemPoolSetAttribute(hipMemPool_t pool, hipMemPoolAttr attr, void* value);
+hipError_t hipMemPoolTrimTo(hipMemPool_t pool, size_t keep);
 hipError_t hipHostMalloc(void** p, size_t n, unsigned f);
 hipError_t hipHostFree(void* p);
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st);

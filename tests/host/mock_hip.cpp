@@ -18,6 +18,7 @@ hipError_t hipMallocAsync(void** p, size_t n, hipStream_t) { return hipMalloc(p,
 hipError_t hipFreeAsync(void* p, hipStream_t) { free(p); return 0; }
 hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t* pool, int) { *pool = nullptr; return 0; }
 hipError_t hipMemPoolSetAttribute(hipMemPool_t, hipMemPoolAttr, void*) { return 0; }
+hipError_t hipMemPoolTrimTo(hipMemPool_t, size_t) { return 0; }
 hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = malloc(n); return *p ? 0 : 2; }
 hipError_t hipHostFree(void* p) { free(p); return 0; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { memcpy(d, s, n); return 0; }
