@@ -681,7 +681,8 @@ __device__ inline void quat_to_matrix(const double* q, double* M)
     M[6] = 2 * (x * z - w * y);     M[7] = 2 * (y * z + w * x);     M[8] = 1 - 2 * (x * x + y * y);
 }
 
-// One workgroup per pair: FT[out][10] = (U, F_B, tau_A, tau_B); wscr (when not null) gets
+// One workgroup per pair: FT[out][10] = (U, F_B, tau_A, tau_B) and the pair's status;
+// wscr (when not null) gets
 // What (side B) then Vhat (side A), nrows(L) complex each, for the per-atom tables atab
 // (when not null: ATAB_HDR doubles of rotations, then side A then side B, atab_rows(L) rows of
 // ATAB_ROW doubles each).
@@ -697,6 +698,7 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
     double* out = FT + (size_t)FT_NSUM * pw.out;
     if (!(Rn > 0.0) || (!(pw.flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
         if (tid < FT_NSUM) out[tid] = __builtin_nan("");
+        if (tid == 0) P.status[pw.out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
         return;
     }
     const int Lm = P.pair_lmax;
@@ -833,6 +835,7 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
         const double ta[3] = {-t[7] * ir, -t[8] * ir, -t[9] * ir};
         const double tb[3] = {-t[4] * ir, -t[5] * ir, -t[6] * ir};
         out[0] = t[0] * ir;
+        P.status[pw.out] = TCM_OK;
         for (int d = 0; d < 3; ++d) {         // lab = rot^T rotated
             out[1 + d] = rot[d] * fp[0] + rot[3 + d] * fp[1] + rot[6 + d] * fp[2];
             out[4 + d] = rot[d] * ta[0] + rot[3 + d] * ta[1] + rot[6 + d] * ta[2];

@@ -589,7 +589,7 @@ static void destroy_streams(Workspace& ws)
 //     tail of a large one instead of running alone on a half-empty device.  Two streams, not
 //     one per group: the process's streams share four hardware queues, and with one stream
 //     per group some groups queued behind others.
-int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev)
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev, bool energy)
 {
     (void)c;
     const int S = bp.n_stats;
@@ -639,7 +639,7 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
     if (ev && hipEventRecord(ev[2], s) != hipSuccess) return TCM_EDEVICE;
     if (launch_moments_finalize(bp.P, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[3], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_pairs(bp.P, 0, bp.npairs, s) != hipSuccess) return TCM_EDEVICE;
+    if (energy && launch_pairs(bp.P, 0, bp.npairs, s) != hipSuccess) return TCM_EDEVICE;
     if (ev && hipEventRecord(ev[4], s) != hipSuccess) return TCM_EDEVICE;
     return TCM_OK;
 }
@@ -1675,7 +1675,7 @@ extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const dou
     if (rp.pre_status[0] != TCM_OK) return rp.pre_status[0];
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
-    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;   // the force kernel writes U
     const bool atoms = forces_A || forces_B;
     const int nr = (L + 1) * (L + 2) / 2, na = L * (L + 1) / 2;
     if ((rc = c.alloc(c.force_ft, sizeof(double) * FT_N)) != TCM_OK) return rc;
@@ -1743,7 +1743,7 @@ extern "C" int tcm_batch_forces(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np
     if (rc != TCM_OK) return rc;
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
-    if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
+    if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;   // the force kernel writes U
     const int npj = (int)rp.pj.size();
     std::vector<double> ft((size_t)FT_N * (npj > 0 ? npj : 1));
     std::vector<int32_t> st(npj > 0 ? npj : 1);

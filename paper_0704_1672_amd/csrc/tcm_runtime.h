@@ -159,7 +159,8 @@ struct Ctx {
 // planning / running (tcm_runtime.cpp)
 int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols,
                const std::vector<PairJob>& pairs, BuiltPlan& bp, hipStream_t s);
-int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev);
+// energy = false leaves out the energy pair launch (callers that launch their own pair kernel)
+int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev, bool energy = true);
 size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols,
                         const std::vector<PairJob>& pairs);
 int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s);

@@ -65,7 +65,13 @@ hipError_t launch_scan(const double*, const double*, int, double, double, double
     return 0; }
 hipError_t launch_alu_probe(int, void*, int, int, hipStream_t) { return 0; }
 hipError_t launch_abs_sum(const double*, int64_t, double* out, hipStream_t) { out[0] = 1.0; return 0; }
-hipError_t launch_pairs_ft(const DevPlan&, int, int, double*, double*, double*, hipStream_t) { return 0; }
+hipError_t launch_pairs_ft(const DevPlan& P, int b, int e, double* FT, double*, double*, hipStream_t) {
+    for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p];
+        double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
+        const bool ok = (w.flags & TCM_UNCHECKED) || R > w.metaA[3] + w.metaB[3];
+        P.status[w.out] = ok ? 0 : TCM_EDOMAIN;
+        for (int k = 0; k < 10; ++k) FT[10 * w.out + k] = ok ? w.QA[0] + 1e-3 * w.QB[0] : NAN; }
+    return 0; }
 hipError_t launch_atom_forces(const double*, int, int, const double*, const double*, const double*, const double*,
                               int64_t, const double*, double*, hipStream_t) { return 0; }
 hipError_t launch_pairs(const DevPlan& P, int b, int e, hipStream_t) {
