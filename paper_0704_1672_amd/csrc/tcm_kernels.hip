@@ -821,8 +821,8 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
     for (int k = 0; k < FT_NSUM; ++k) acc[k] = wave_sum(acc[k]);
     if ((tid & 63) == 0)
         for (int k = 0; k < FT_NSUM; ++k) red[(tid >> 6) * FT_NSUM + k] = acc[k];
-    __threadfence();
-    __syncthreads();
+    __syncthreads();                         // red is in LDS: the barrier orders it (a device-scope
+                                             // fence here would write back and drop the L2 per pair)
     if (tid == 0) {
         double t[FT_NSUM];
         for (int k = 0; k < FT_NSUM; ++k) {
