@@ -1046,6 +1046,22 @@ hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s
     return hipGetLastError();
 }
 
+// dst[k][0..7] = src[k][0..7] for k < K (one thread per value): the per-molecule records of
+// many molecules gathered for one read-back.
+__global__ __launch_bounds__(WG) void tcm_gather8(const double* const* src, int64_t K, double* dst)
+{
+    const int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x;
+    if (i < 8 * K) dst[i] = src[i >> 3][i & 7];
+}
+
+hipError_t launch_gather8(const double* const* src, int64_t K, double* dst, hipStream_t s)
+{
+    if (K <= 0) return hipSuccess;
+    const int64_t blocks = (8 * K + WG - 1) / WG;
+    hipLaunchKernelGGL(tcm_gather8, dim3((unsigned)blocks), dim3(WG), 0, s, src, K, dst);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(PAIR_WG) void tcm_pairs_ft(DevPlan P, int begin, int end, double* FT, double* wscr,
                                                         double* atab)
 {

@@ -354,13 +354,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         mols[i] = mols_in[order[i]];
         newidx[order[i]] = i;
     }
-    std::vector<PairJob> pairs(pairs_in);
-    for (PairJob& pj : pairs) {
-        if (pj.depA >= 0) pj.depA = newidx[pj.depA];
-        if (pj.depB >= 0) pj.depB = newidx[pj.depB];
-    }
     std::vector<MolWork> mw(nmol);
-    std::vector<PairWork> pw(npairs);
     std::vector<int32_t> sp(nmol + 1, 0), tp(nmol + 1, 0);
     int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0;
     double flops = 0.0;
@@ -402,22 +396,19 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         flops += 6.0 * (j.L + 1) * (j.L + 2) * (double)j.n;
         atoms += j.n;
     }
-    for (int p = 0; p < npairs; ++p) {
-        const PairJob& j = pairs[p];
-        PairWork& w = pw[p];
-        w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
-        w.depA = j.depA; w.depB = j.depB;
-        w.L = j.L; w.flags = j.flags;
-        for (int d = 0; d < 3; ++d) w.R[d] = j.R[d];
-        for (int d = 0; d < 4; ++d) w.quat[d] = j.quat[d];
-        w.has_rot = j.has_rot;
-        w.out = p;
-    }
-    // largest contractions first (cost ~ (L+1)^4 plus the rotation): the pair launch's tail
-    // holds the cheap ones; every pair writes U[out], so the order changes no result
-    std::stable_sort(pw.begin(), pw.end(), [](const PairWork& u, const PairWork& v) { return u.L > v.L; });
+    // pair launch order: largest contractions first (cost ~ (L+1)^4 plus the rotation), so the
+    // launch's tail holds the cheap ones; a stable counting sort by L (every pair writes
+    // U[out], so the order changes no result).  The records are written in this order
+    // straight into the staging buffer below.
     int pair_lmax = 0;
-    for (const PairWork& w : pw) pair_lmax = std::max(pair_lmax, (int)w.L);
+    for (const PairJob& j : pairs_in) pair_lmax = std::max(pair_lmax, j.L);
+    std::vector<int32_t> porder(npairs);
+    {
+        std::vector<int32_t> start(pair_lmax + 2, 0);
+        for (const PairJob& j : pairs_in) ++start[pair_lmax - j.L + 1];
+        for (int k = 1; k <= pair_lmax + 1; ++k) start[k] += start[k - 1];
+        for (int p = 0; p < npairs; ++p) porder[start[pair_lmax - pairs_in[p].L]++] = p;
+    }
     // tile items of each (precision, L) group in decreasing estimated cost (per-thread
     // instructions: atoms x (recurrence + set-up) + the compensated reduction)
     const int64_t nitems = tp[nmol];
@@ -484,7 +475,22 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
-    if (npairs) std::memcpy(h + o_pw, pw.data(), sizeof(PairWork) * npairs);
+    {
+        PairWork* pw = (PairWork*)(h + o_pw);
+        for (int k = 0; k < npairs; ++k) {
+            const int p = porder[k];
+            const PairJob& j = pairs_in[p];
+            PairWork& w = pw[k];
+            w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
+            w.depA = j.depA >= 0 ? newidx[j.depA] : -1;
+            w.depB = j.depB >= 0 ? newidx[j.depB] : -1;
+            w.L = j.L; w.flags = j.flags;
+            for (int d = 0; d < 3; ++d) w.R[d] = j.R[d];
+            for (int d = 0; d < 4; ++d) w.quat[d] = j.quat[d];
+            w.has_rot = j.has_rot;
+            w.out = p;
+        }
+    }
     {
         int32_t* si = (int32_t*)(h + o_sp);                // (molecule, chunk) of each STATS item
         for (int i = 0; i < nmol; ++i)
@@ -761,6 +767,7 @@ extern "C" void tcm_destroy(tcm_ctx* t)
     c.release(c.scan_g); c.release(c.scan_r); c.release(c.scan_u); c.release(c.scan_s);
     c.release(c.force_ft); c.release(c.force_w); c.release(c.force_t); c.release(c.force_a); c.release(c.force_b);
     c.release(c.absq);
+    c.release(c.gather);
     c.release(c.t_invk);
     c.release(c.t_invf);
     c.release(c.t_rot);
@@ -1239,12 +1246,19 @@ extern "C" int tcm_all_pairs(tcm_ctx* t, const tcm_mol_id* ids, int64_t K, int L
         if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
         mark_computed(rp);
     }
+    // the K centre records gathered on the device and read back in one copy
     std::vector<double> meta((size_t)K * 8);
-    for (int64_t i = 0; i < K; ++i)
-        if (hipMemcpyAsync(&meta[(size_t)i * 8], c.mols[ids[i]]->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost,
-                           s) != hipSuccess)
-            return TCM_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    std::vector<const double*> src((size_t)K);
+    for (int64_t i = 0; i < K; ++i) src[i] = (const double*)c.mols[ids[i]]->meta.p;
+    const size_t pbytes = align_up(sizeof(double*) * (size_t)K, 256);
+    if ((rc = c.alloc(c.gather, pbytes + sizeof(double) * 8 * (size_t)K)) != TCM_OK) return rc;
+    const double* const* dsrc = (const double* const*)c.gather.p;
+    double* dmeta = (double*)((char*)c.gather.p + pbytes);
+    if (hipMemcpyAsync((void*)dsrc, src.data(), sizeof(double*) * (size_t)K, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_gather8(dsrc, K, dmeta, s) != hipSuccess ||
+        hipMemcpyAsync(meta.data(), dmeta, sizeof(double) * 8 * (size_t)K, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TCM_EDEVICE;
     std::vector<tcm_pair_req> reqs((size_t)np);
     int64_t k = 0;
     for (int64_t i = 0; i < K; ++i)

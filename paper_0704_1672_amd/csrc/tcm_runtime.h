@@ -34,6 +34,7 @@ hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, dou
                            hipStream_t s);
 hipError_t launch_alu_probe(int prec, void* out, int blocks, int iters, hipStream_t s);
 hipError_t launch_abs_sum(const double* q, int64_t n, double* out, hipStream_t s);
+hipError_t launch_gather8(const double* const* src, int64_t K, double* dst, hipStream_t s);
 // Per-atom forces of side 0 (A) or 1 (B) from the tables launch_pairs_ft wrote to atab.
 hipError_t launch_atom_forces(const double* atab, int side, int L, const double* x, const double* y, const double* z,
                               const double* q, int64_t n, const double* centre, double* F, hipStream_t s);
@@ -140,6 +141,7 @@ struct Ctx {
     DevBuf scan_g, scan_r, scan_u, scan_s;   // translation scan: pair-tensor table, host-side I/O
     DevBuf force_ft, force_w, force_t, force_a, force_b;   // forces: outputs, coefficient tables, host-side I/O
     DevBuf absq;                   // sum |q| of the molecules an adaptive batch needs
+    DevBuf gather;                 // K record pointers, then K gathered 8-double records
     void* hpin = nullptr;          // pinned staging for one-shot uploads
     size_t hpin_cap = 0;
     std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper

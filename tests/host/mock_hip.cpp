@@ -65,6 +65,9 @@ hipError_t launch_scan(const double*, const double*, int, double, double, double
     return 0; }
 hipError_t launch_alu_probe(int, void*, int, int, hipStream_t) { return 0; }
 hipError_t launch_abs_sum(const double*, int64_t, double* out, hipStream_t) { out[0] = 1.0; return 0; }
+hipError_t launch_gather8(const double* const* src, int64_t K, double* dst, hipStream_t) {
+    for (int64_t i = 0; i < 8 * K; ++i) dst[i] = src[i >> 3][i & 7];
+    return 0; }
 hipError_t launch_pairs_ft(const DevPlan& P, int b, int e, double* FT, double*, double*, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p];
         double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
