@@ -93,9 +93,21 @@ struct DevPlan {
 //   m = 0: l*l ; m > 0: Re at l*l + 2m - 1, Im at l*l + 2m.
 __host__ __device__ inline int l_of(int h)
 {
-    int l = 0;
-    while ((l + 1) * (l + 1) <= h) ++l;
+    int l = (int)sqrtf((float)h);             // exact after the corrections (h <= 2^24)
+    if (l * l > h) --l;
+    if ((l + 1) * (l + 1) <= h) ++l;
     return l;
+}
+
+// Offset of order l's block in the rotation tables: a header of LMAX + 1 offsets, then per
+// order l' (n = 2l'+1, K = l'/2 + 1 value slots per row) 2n row codes and 2Kn values, i.e.
+// sum_{l' < l} 2 (2l'+1)(l'/2 + 2) after the header, in closed form.
+__host__ __device__ constexpr int rot_block_offset(int l)
+{
+    const int p = l / 2;                       // pairs of orders (2a, 2a+1), a < p
+    int s = 16 * (p - 1) * p * (2 * p - 1) / 6 + 20 * p * (p - 1) + 16 * p;
+    if (l & 1) s += 8 * p * p + 18 * p + 4;    // the even order 2p
+    return (LMAX + 1) + s;
 }
 
 // m-block partition of the (l, m >= 0) harmonics for the moment tile.  Accumulator cost

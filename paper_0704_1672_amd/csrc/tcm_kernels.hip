@@ -152,14 +152,16 @@ __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
 
 // out = D v (or D^{-1} v) per order l from the compressed tables: row i's nonzero columns are
 // max(0, jb + 4k), k < cnt (the header, codes and slot layout are those the runtime writes).
-__device__ __forceinline__ void rot_row(const double* tab, int l, int i, bool inverse, int& jb, int& cnt,
-                                        const double*& val)
+// Every row has K = l/2 + 1 value slots, those past cnt holding zeros, so the products run
+// over all K slots: the value loads then depend only on (l, i), not on the row's code, and
+// are issued together with it (the zero slots add exact zeros to the partial sums; their
+// columns are clamped into the row).
+__device__ __forceinline__ void rot_row(const double* tab, int l, int i, bool inverse, int& jb, const double*& val)
 {
     const int n = 2 * l + 1, K = l / 2 + 1;
-    const double* blk = tab + (int64_t)tab[l];
+    const double* blk = tab + rot_block_offset(l);
     const int code = (int)blk[(inverse ? n : 0) + i];
     jb = (code & 0xffff) - 1;
-    cnt = code >> 16;
     val = blk + 2 * n + (inverse ? K * n : 0) + i;
 }
 
@@ -167,19 +169,23 @@ __device__ void rot_matvec(const double* tab, const double* in, double* out, int
 {
     const int NHl = nh(L);
     for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
-        const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
-        int jb, cnt;
+        const int l = l_of(h), i = h - l * l, n = 2 * l + 1, K = l / 2 + 1;
+        int jb;
         const double* val;
-        rot_row(tab, l, i, inverse, jb, cnt, val);
+        rot_row(tab, l, i, inverse, jb, val);
         const double* v = in + l * l;
-        // two independent partial sums so that the table loads are in flight together
+        // two partial sums (even and odd slots), four slots' loads in flight at a time
         double s0 = 0.0, s1 = 0.0;
-        int k = 0;
-        for (; k + 2 <= cnt; k += 2) {
-            s0 += val[k * n] * v[max(0, jb + 4 * k)];
-            s1 += val[(k + 1) * n] * v[jb + 4 * k + 4];
+        for (int k = 0; k < K; k += 4) {
+            double d[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u] = k + u < K ? val[(k + u) * n] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double x = d[u] * v[min(n - 1, max(0, jb + 4 * (k + u)))];
+                if (u & 1) s1 += x; else s0 += x;
+            }
         }
-        if (k < cnt) s0 += val[k * n] * v[max(0, jb + 4 * k)];
         out[h] = s0 + s1;
     }
 }
@@ -190,12 +196,31 @@ __device__ inline void euler_phases(const double* quat, int m, int Lm, double* s
 {
     const double qn = sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
     const double w = quat[0] / qn, x = quat[1] / qn, y = quat[2] / qn, z = quat[3] / qn;
-    const double beta = 2.0 * atan2(sqrt(x * x + y * y), sqrt(w * w + z * z));
-    const double ap = atan2(z, w), am = atan2(-x, y);
-    const double ang[3] = {ap - am /*gamma*/, beta, ap + am /*alpha*/};
+    // With r1 = |(w, z)| and r2 = |(x, y)|: e^{i a+} = (w + i z)/r1, e^{i a-} = (y - i x)/r2 (the
+    // angles atan2(z, w) and atan2(-x, y); either is free, taken as 0, when its modulus vanishes,
+    // since the rotation then depends only on the other), gamma = a+ - a-, alpha = a+ + a-, and
+    // beta = 2 atan2(r2, r1): e^{i beta} = (r1^2 - r2^2 + 2 i r1 r2) / (r1^2 + r2^2).
+    const double r1 = sqrt(w * w + z * z), r2 = sqrt(x * x + y * y);
+    double pc = 1.0, ps = 0.0, mc = 1.0, ms = 0.0;
+    if (r1 > 0.0) { pc = w / r1; ps = z / r1; }
+    if (r2 > 0.0) { mc = y / r2; ms = -x / r2; }
+    const double rr = r1 * r1 + r2 * r2;
+    const double e[3][2] = {{pc * mc + ps * ms, ps * mc - pc * ms},       // gamma
+                            {(r1 * r1 - r2 * r2) / rr, 2.0 * r1 * r2 / rr}, // beta
+                            {pc * mc - ps * ms, ps * mc + pc * ms}};      // alpha
     for (int k = 0; k < 3; ++k) {
-        double s, c;
-        sincos(m * ang[k], &s, &c);
+        // e^{i m angle} by binary powering (at most 2 log2(m) complex products)
+        double c = 1.0, s = 0.0, bc = e[k][0], bs = e[k][1];
+        for (int t = m; t > 0; t >>= 1) {
+            if (t & 1) {
+                const double nc = c * bc - s * bs;
+                s = c * bs + s * bc;
+                c = nc;
+            }
+            const double nb = bc * bc - bs * bs;
+            bs = 2.0 * bc * bs;
+            bc = nb;
+        }
         scs[(k * (Lm + 1) + m) * 2] = c;
         scs[(k * (Lm + 1) + m) * 2 + 1] = s;
     }
@@ -244,27 +269,28 @@ __device__ void rot_matvec2(const double* tab, const double* ina, const double* 
 {
     const int NHl = nh(L);
     for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
-        const int l = l_of(h), i = h - l * l, n = 2 * l + 1;
-        int jb, cnt;
+        const int l = l_of(h), i = h - l * l, n = 2 * l + 1, K = l / 2 + 1;
+        int jb;
         const double* val;
-        rot_row(tab, l, i, inverse, jb, cnt, val);
+        rot_row(tab, l, i, inverse, jb, val);
         const double* va = ina + l * l;
         const double* vb = inb + l * l;
         double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-        int k = 0;
-        for (; k + 2 <= cnt; k += 2) {
-            const int j0 = max(0, jb + 4 * k), j1 = jb + 4 * k + 4;
-            const double d0 = val[k * n], d1 = val[(k + 1) * n];
-            a0 += d0 * va[j0];
-            a1 += d1 * va[j1];
-            b0 += d0 * vb[j0];
-            b1 += d1 * vb[j1];
-        }
-        if (k < cnt) {
-            const int j0 = max(0, jb + 4 * k);
-            const double d0 = val[k * n];
-            a0 += d0 * va[j0];
-            b0 += d0 * vb[j0];
+        for (int k = 0; k < K; k += 4) {
+            double d[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u] = k + u < K ? val[(k + u) * n] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = min(n - 1, max(0, jb + 4 * (k + u)));
+                if (u & 1) {
+                    a1 += d[u] * va[j];
+                    b1 += d[u] * vb[j];
+                } else {
+                    a0 += d[u] * va[j];
+                    b0 += d[u] * vb[j];
+                }
+            }
         }
         outa[h] = a0 + a1;
         outb[h] = b0 + b1;
@@ -380,14 +406,13 @@ __device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* s
         const double wt = m == 0 ? 1.0 : 2.0;
         Upart += (m & 1) ? -wt * t : wt * t;
     }
-    red[tid] = Upart;
+    Upart = wave_sum(Upart);                 // then the waves' sums in wave order
+    if ((tid & 63) == 0) red[tid >> 6] = Upart;
     __syncthreads();
-    for (int s = PAIR_WG / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
     if (tid == 0) {
-        P.U[pw.out] = red[0] / Rn;
+        double u = 0.0;
+        for (int wv = 0; wv < PAIR_WG / 64; ++wv) u += red[wv];
+        P.U[pw.out] = u / Rn;
         P.status[pw.out] = TCM_OK;
     }
     __syncthreads();

@@ -231,6 +231,7 @@ static std::vector<double> build_rotation_tables(int Lmax)
     std::vector<double> cp((Lmax + 1) * (Lmax + 1)), cx((Lmax + 1) * (Lmax + 1));
     for (int l = 0; l <= Lmax; ++l) {
         const int n = 2 * l + 1, K = l / 2 + 1;
+        if (Lmax != LMAX || out.size() != (size_t)rot_block_offset(l)) return {};   // the kernels' layout
         out[l] = (double)out.size();
         const size_t base = out.size();
         out.resize(base + 2 * (size_t)n + 2 * (size_t)K * n, 0.0);
