@@ -164,6 +164,27 @@ def test_pair_energy_pose_matches_recomputed_moments(ctx, orc, synth, L):
         assert abs(U - d["U"]) <= 1e-11 * d["abs_sum"], (L, qv, U, d["U"])
 
 
+@pytest.mark.parametrize("L", [8, 16])
+def test_pair_energy_degenerate_euler_poses(ctx, orc, synth, L):
+    """R along +-z (the frame rotation is the identity, so B's rotation is its pose exactly)
+    with poses whose Euler decomposition is degenerate: half turns about axes in the xy-plane
+    (w = z = 0) and rotations about z (x = y = 0), against the oracle's rotated atoms."""
+    xA, qA, cA, xB, qB, cB = _two_balls(synth, 60 + L, t=0.45)
+    R = np.linalg.norm(cB - cA)
+    QA = orc.moments(xA, qA, cA, L)
+    pA = orc.complex_to_packed(QA)
+    pB = orc.complex_to_packed(orc.moments(xB, qB, cB, L))
+    poses = [[0.0, 1.0, 0, 0], [0.0, 0, 1.0, 0], [0.0, 0.6, 0.8, 0], [0.0, -0.8, 0.6, 0],
+             [1.0, 0, 0, 0], [0.0, 0, 0, 1.0], [0.8, 0, 0, -0.6]]
+    for sgn in (1, -1):
+        Rv = np.array([0.0, 0.0, sgn * R])
+        for qv in map(np.array, poses):
+            xBr = orc.pose(xB, cB, qv, cB)
+            d = orc.energy(QA, orc.moments(xBr, qB, cB, L), Rv, L, full=True)
+            U = tcm.tcm_pair_energy(ctx, pA, 3.0, pB, 4.0, Rv, L, quat_b=qv)
+            assert abs(U - d["U"]) <= 1e-11 * d["abs_sum"], (L, sgn, qv, U, d["U"])
+
+
 def test_domain_and_flags(ctx, orc, synth):
     xA, qA, cA, xB, qB, cB = _two_balls(synth, 3, t=0.5)
     L = 6
