@@ -113,7 +113,9 @@ int tcm_pair_energy(tcm_ctx *ctx, const double *QA, double aA, const double *QB,
 
 /* Copy a molecule's atoms (host AoS FP64) to the device, in the library's resident layout
  * (FP64 structure of arrays).  centre: FP64[3] or NULL (centroid).  precision: the moment
- * pass used for this molecule.  The id stays valid until tcm_mol_release / tcm_destroy. */
+ * pass used for this molecule.  Its resident moment table (33^2 FP64, every order the
+ * library accepts) is allocated here too, so later computations on it allocate nothing for
+ * it.  The id stays valid until tcm_mol_release / tcm_destroy. */
 int tcm_mol_upload(tcm_ctx *ctx, const double *coords, const double *charges, int64_t n,
                    const double *centre, int precision, tcm_mol_id *id_out);
 

@@ -930,10 +930,14 @@ extern "C" int tcm_pair_energy(tcm_ctx* t, const double* QA, double aA, const do
 }
 
 // ---------------------------------------------------------------- resident molecules
+// The molecule's record and its moment table at the largest order (8.7 KB) are allocated
+// here, once, so that no computation on it allocates device memory.
 static int add_mol(Ctx& c, std::unique_ptr<Mol> m, tcm_mol_id* id_out)
 {
     int rc = c.alloc(m->meta, sizeof(double) * 8);
+    if (rc == TCM_OK) rc = c.alloc(m->moments, sizeof(double) * nh(LMAX));
     if (rc != TCM_OK) {
+        c.release(m->meta);
         c.release(m->atoms);
         return rc;
     }
