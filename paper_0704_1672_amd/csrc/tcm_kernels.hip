@@ -130,8 +130,8 @@ __host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2
 
 __host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
 {
-    // sA, sB, tA, tB [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [WG]
-    return sizeof(double) * (4 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG);
+    // sA, sB, tA, tB [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [waves]
+    return sizeof(double) * (4 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG / 64);
 }
 
 __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
