@@ -54,8 +54,8 @@ def measured_tile_traffic():
     return int(m.group(1)) if m else None
 
 
-def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, fractions=(0.5, 0.9), inflight=3,
-                    batch=64):
+def serving_section(tcm, synth, torch, nreq=10000, pool=48, oracle_seconds=8.0, fractions=(0.25, 0.5, 0.75, 0.9, 1.1),
+                    inflight=3, batch=64):
     """Serving workload: a pool of chain fragments (log-uniform 1e3..1e6 atoms) resident in HBM,
     a trace of nreq pair requests with L ~ U{8..24}; 70% name two new fragments (new keys, atoms
     referenced in place), 30% reuse the fragments of an earlier request with a new pose and
@@ -134,12 +134,13 @@ def serving_section(tcm, synth, torch, nreq=2000, pool=48, oracle_seconds=8.0, f
         return U, st, lat, elapsed, stats
 
     ctx = tcm.Context(0)
+    tcm.tcm_set_budget(ctx.h, 64 << 30)                       # a realistic, non-binding HBM budget
     run(ctx, None)                                            # warm-up (allocations, code load)
     U, st, lat, elapsed, stats = run(ctx, None)
     sat = nreq / elapsed
     out = {"workload": f"serving trace: {nreq} requests, pool of {pool} chain fragments ({ntot} atoms), "
                        "log-uniform 1e3..1e6 atoms, L ~ U{8..24}, 30% reuse of resident fragments, "
-                       "R0 = 1.5(a_A+a_B), random poses; inputs resident in HBM (borrowed)",
+                       "R0 = 1.5(a_A+a_B), random poses; inputs resident in HBM (borrowed); 64 GiB budget",
            "server": {"max_inflight_batches": inflight, "max_batch_pairs": batch},
            "saturation_pairs_per_s": sat, "burst_stats": stats, "statuses_ok": int(np.sum(st == 0))}
     rng = np.random.default_rng(55)
@@ -459,7 +460,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle sample time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-inflight", type=int, default=3, help="serving launches in flight at once")
     ap.add_argument("--serve-batch", type=int, default=64, help="requests admitted into one serving launch")
     ap.add_argument("--no-scan", action="store_true")
