@@ -11,8 +11,29 @@
 static std::mutex g_mu;
 static std::mt19937 g_rng(getenv("MOCK_SEED") ? atoi(getenv("MOCK_SEED")) : 1);
 static const int g_delay = getenv("MOCK_DELAY") ? atoi(getenv("MOCK_DELAY")) : 3;
+// Fault injection for the failure-handling tests: with mock_set_faults(a, k), every a-th
+// device allocation and every k-th tile launch fails (0 = never).
+static std::atomic<int> g_fail_alloc{0}, g_fail_launch{0};
+static std::atomic<long> g_alloc_calls{0}, g_launch_calls{0}, g_faults{0};
+static bool fail_now(std::atomic<int>& every, std::atomic<long>& calls)
+{
+    const int e = every.load();
+    if (e <= 0 || ++calls % e != 0) return false;
+    ++g_faults;
+    return true;
+}
 extern "C" {
-hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); if (*p) memset(*p, 0xAB, n); return *p ? 0 : 2; }
+void mock_set_faults(int alloc_every, int launch_every)
+{
+    g_alloc_calls = 0; g_launch_calls = 0; g_faults = 0;
+    g_fail_alloc = alloc_every; g_fail_launch = launch_every;
+}
+long mock_faults_fired() { return g_faults.load(); }
+hipError_t hipMalloc(void** p, size_t n)
+{
+    if (fail_now(g_fail_alloc, g_alloc_calls)) { *p = nullptr; return 2; }
+    *p = malloc(n); if (*p) memset(*p, 0xAB, n); return *p ? 0 : 2;
+}
 hipError_t hipFree(void* p) { free(p); return 0; }
 hipError_t hipMallocAsync(void** p, size_t n, hipStream_t) { return hipMalloc(p, n); }
 hipError_t hipFreeAsync(void* p, hipStream_t) { free(p); return 0; }
@@ -58,7 +79,7 @@ hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t) {
     for (int m = 0; m < P.nmol; ++m) { const MolWork& w = P.mols[m];
         for (int h = 0; h < nh(w.L); ++h) w.Q[h] = w.n; w.meta[3] = 0.5; }
     return 0; }
-hipError_t launch_tiles(int, int, const DevPlan&, int, int, hipStream_t) { return 0; }
+hipError_t launch_tiles(int, int, const DevPlan&, int, int, hipStream_t) { return fail_now(g_fail_launch, g_launch_calls) ? 1 : 0; }
 hipError_t launch_scan(const double*, const double*, int, double, double, double, int, const double*, const double*,
                        const double*, double*, const double*, int64_t nR, double* U, int32_t* status, hipStream_t) {
     for (int64_t k = 0; k < nR; ++k) { U[k] = 0.0; status[k] = 0; }

@@ -38,8 +38,84 @@ static int plan_lifecycle() {
     return 0;
 }
 
+extern "C" void mock_set_faults(int alloc_every, int launch_every);
+extern "C" long mock_faults_fired();
+
+// Injected failures: every 13th device allocation and every 29th tile launch fail while 400
+// requests are served (new fragments copied or borrowed, resident ones reused).  Every ticket
+// must complete; a request either succeeds with the right value or fails alone with
+// TCM_ENOMEM / TCM_EDEVICE; with the faults off again a fresh batch must succeed entirely;
+// and after the server stops the context's device memory is back where it started.
+static int fault_injection() {
+    tcm_ctx* ctx; if (tcm_create(&ctx, 0, 0, 0)) return 1;
+    size_t base; tcm_mem_info(ctx, &base, nullptr);
+    std::mt19937 rng(99);
+    const int nfr = 16;
+    std::vector<std::vector<double>> fr(nfr);
+    std::vector<int64_t> nat(nfr);
+    for (int f = 0; f < nfr; ++f) { nat[f] = 1 + rng() % 5000; fr[f].assign(4 * nat[f], 1.0); }
+    tcm_server_cfg cfg{3, 8, 1024, 0};
+    if (tcm_server_start(ctx, &cfg)) return 2;
+    auto serve = [&](int nreq, int64_t key0, int& ok, int& failed, int& bad) -> int {
+        std::vector<uint64_t> tk; std::vector<int> fa, fb;
+        for (int i = 0; i < nreq; ++i) {
+            tcm_request r{}; int a = rng() % nfr, b = rng() % nfr;
+            const bool fresh = (rng() % 3) != 0;
+            r.key_a = fresh ? key0 + 2 * i : a; r.key_b = fresh ? key0 + 2 * i + 1 : b;
+            if (!fresh) { a = (int)r.key_a; b = (int)r.key_b; }
+            for (int k = 0; k < 4; ++k) { r.atoms_a[k] = fr[a].data() + k * nat[a]; r.atoms_b[k] = fr[b].data() + k * nat[b]; }
+            r.n_a = nat[a]; r.n_b = nat[b];
+            r.R[0] = 100.0; r.quat_b[0] = 1; r.L = rng() % 17; r.precision = rng() % 2;
+            r.flags = (rng() % 2) ? TCM_BORROW_ATOMS : 0;
+            uint64_t t; int rc;
+            while ((rc = tcm_submit(ctx, &r, &t)) == TCM_EAGAIN) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            if (rc) { printf("faults: submit rc %d\n", rc); return 3; }
+            tk.push_back(t); fa.push_back(a); fb.push_back(b);
+        }
+        int done = 0;
+        std::vector<char> got(nreq, 0);
+        auto t0 = std::chrono::steady_clock::now();
+        while (done < nreq) {
+            for (int i = 0; i < nreq; ++i) {
+                if (got[i]) continue;
+                double U, lat; int32_t st;
+                const int rc = tcm_poll(ctx, tk[i], &U, &st, &lat);
+                if (rc == TCM_EAGAIN) continue;
+                if (rc != TCM_OK) { printf("faults: poll rc %d\n", rc); return 4; }
+                got[i] = 1; ++done;
+                if (st == TCM_OK) {
+                    const double want = nat[fa[i]] + 1e-3 * nat[fb[i]];
+                    if (std::fabs(U - want) > 1e-9 * want) ++bad; else ++ok;
+                } else if (st == TCM_ENOMEM || st == TCM_EDEVICE) {
+                    ++failed;
+                } else {
+                    ++bad;
+                }
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(20)) { printf("faults: stuck at %d/%d\n", done, nreq); return 5; }
+        }
+        return 0;
+    };
+    int ok = 0, failed = 0, bad = 0;
+    mock_set_faults(13, 29);
+    if (int rc = serve(400, 1000, ok, failed, bad)) return rc;
+    const long fired = mock_faults_fired();
+    mock_set_faults(0, 0);
+    int ok2 = 0, failed2 = 0, bad2 = 0;
+    if (int rc = serve(100, 100000, ok2, failed2, bad2)) return rc;
+    tcm_server_stop(ctx);
+    size_t used; tcm_mem_info(ctx, &used, nullptr);
+    tcm_destroy(ctx);
+    printf("faults: fired %ld | ok %d failed %d bad %d | after: ok %d failed %d bad %d | used %zu base %zu %s\n",
+           fired, ok, failed, bad, ok2, failed2, bad2, used, base,
+           (fired > 0 && failed > 0 && ok > 0 && bad == 0 && ok2 == 100 && used == base) ? "ok" : "FAIL");
+    if (!(fired > 0 && failed > 0 && ok > 0 && bad == 0 && ok2 == 100 && used == base)) return 6;
+    return 0;
+}
+
 int main(int argc, char** argv) {
     if (int rc = plan_lifecycle()) return 10 + rc;
+    if (int rc = fault_injection()) return 20 + rc;
     int seeds = argc > 1 ? atoi(argv[1]) : 20;
     for (int seed = 0; seed < seeds; ++seed) {
         std::mt19937 rng(seed);

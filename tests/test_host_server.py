@@ -32,6 +32,10 @@ def test_server_stress_asan_ubsan(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([exe, "12"], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    # injected allocation and launch failures fail their own requests only, leak nothing,
+    # and the server serves a clean batch afterwards
+    faults = [l for l in r.stdout.splitlines() if l.startswith("faults:")]
+    assert len(faults) == 1 and faults[0].endswith(" ok"), faults
     lines = [l for l in r.stdout.splitlines() if l.startswith("seed")]
     assert len(lines) == 12
     assert all(" bad 0 " in l and l.endswith("ok") for l in lines), lines
