@@ -515,7 +515,9 @@ static void server_loop(Server* S)
                 std::this_thread::sleep_for(std::chrono::microseconds(10));
                 lk.lock();
             } else {
-                S->cv.wait_for(lk, std::chrono::milliseconds(5));
+                // a system-clock deadline (pthread_cond_timedwait), which thread sanitizers
+                // intercept, unlike the steady-clock wait; the 5 ms is only a re-check period
+                S->cv.wait_until(lk, std::chrono::system_clock::now() + std::chrono::milliseconds(5));
             }
         }
     }

@@ -39,3 +39,15 @@ def test_server_stress_asan_ubsan(tmp_path):
     lines = [l for l in r.stdout.splitlines() if l.startswith("seed")]
     assert len(lines) == 12
     assert all(" bad 0 " in l and l.endswith("ok") for l in lines), lines
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_server_stress_tsan(tmp_path):
+    """The serving loop (server thread, submitting and polling thread, launch slots) under
+    ThreadSanitizer: no data race or lock misuse is reported."""
+    exe = _build(tmp_path, "thread")
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe, "4"], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert len([l for l in r.stdout.splitlines() if l.startswith("seed")]) == 4
