@@ -451,6 +451,44 @@ def adaptive_section(tcm, synth, L=24, npose=4096, fracs=(1e-3, 1e-5)):
     return res
 
 
+def single_pair_section(tcm, synth, reps=1000):
+    """One pair at a time (two balls of 500 charges, q ~ U[-1, 1], radius 10, centres 60 apart,
+    L = 10, FP64 moments): p50/p99 of tcm_batch_energy over `reps` synchronous calls, with the
+    moments recomputed in every call and with resident moments, and the error of the result
+    against the FP64 oracle and against the direct Coulomb sum of eq. (1)."""
+    import oracle
+    w = synth.ball_pair(seed=1)
+    L = int(w["L"])
+    ctx = tcm.Context(0)
+    mA = tcm.tcm_mol_upload(ctx.h, w["xyzA"], w["qA"], centre=w["cA"], precision=tcm.TCM_F64)
+    mB = tcm.tcm_mol_upload(ctx.h, w["xyzB"], w["qB"], centre=w["cB"], precision=tcm.TCM_F64)
+    out = {"workload": "two balls of 500 charges (q ~ U[-1, 1], radius 10), centres 60 apart, L = 10, "
+                       "FP64 moments and contraction, one synchronous call per pair", "calls": reps}
+    U = None
+    for name, flags in (("moments_recomputed", 0), ("resident_moments", tcm.TCM_REUSE)):
+        req = tcm.make_requests(mA, mB, w["R"], L, flags=flags)
+        tcm.tcm_batch_energy(ctx.h, req)                      # warm-up
+        ts = np.empty(reps)
+        for i in range(reps):
+            t0 = time.perf_counter()
+            u, st, _ = tcm.tcm_batch_energy(ctx.h, req)
+            ts[i] = time.perf_counter() - t0
+        assert st[0] == 0
+        U = float(u[0])
+        out[name] = {"p50_ms": 1e3 * float(np.percentile(ts, 50)), "p99_ms": 1e3 * float(np.percentile(ts, 99)),
+                     "pairs_per_s": reps / float(ts.sum())}
+    d = oracle.energy(oracle.moments(w["xyzA"], w["qA"], w["cA"], L), oracle.moments(w["xyzB"], w["qB"], w["cB"], L),
+                      w["R"], L, full=True)
+    Uc = oracle.coulomb(w["xyzA"], w["qA"], w["xyzB"], w["qB"])
+    out["U"] = U
+    out["rel_err_vs_oracle"] = abs(U - d["U"]) / abs(d["U"])
+    out["rel_truncation_vs_coulomb"] = abs(U - Uc) / abs(Uc)
+    tcm.tcm_mol_release(ctx.h, mA)
+    tcm.tcm_mol_release(ctx.h, mB)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +505,7 @@ def main():
     ap.add_argument("--no-all-pairs", action="store_true")
     ap.add_argument("--no-forces", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--alu-calibration", action="store_true",
                     help="only measure the sustained plain FP32 and FP64 FMA rates and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -655,6 +694,15 @@ def main():
                       f"mean L {v['L_used']['mean']:.1f}, "
                       f"diff/bounds {v['max_diff_over_bounds']:.2e}" for k, v in adaptive["adaptive"].items()))
 
+    single = None
+    if not args.no_single:
+        t_s = time.time()
+        single = single_pair_section(tcm, synth)
+        log(f"bench: single-pair section in {time.time() - t_s:.1f}s: recomputed p50 "
+            f"{single['moments_recomputed']['p50_ms']:.3f} ms p99 {single['moments_recomputed']['p99_ms']:.3f} ms; "
+            f"resident p50 {single['resident_moments']['p50_ms']:.3f} ms p99 {single['resident_moments']['p99_ms']:.3f} ms; "
+            f"rel err vs oracle {single['rel_err_vs_oracle']:.1e}")
+
     out = {
         "metric": "pair energies/s & p50/p99 latency at stated rel. err vs FP64 oracle",
         "value": args.npairs / (ms_step * 1e-3),
@@ -698,6 +746,7 @@ def main():
         "all_pairs": all_pairs,
         "forces": forces,
         "adaptive": adaptive,
+        "single_pair": single,
     }
     print(json.dumps(out), flush=True)
 
