@@ -72,6 +72,34 @@ def test_all_pairs_match_oracle_and_batch(ctx, orc, synth):
             tcm.tcm_mol_release(ctx, i)
 
 
+def test_all_pairs_many_fragments_bitwise(ctx, synth):
+    """300 small fragments (44850 pairs; the centres gathered by several workgroups): every
+    entry equals the batch path given the device centres, bit for bit, and its index order is
+    the documented upper triangle."""
+    K, L = 300, 4
+    rng = np.random.default_rng(73)
+    side = 7
+    ids = []
+    try:
+        for k in range(K):
+            x, q, _ = synth.chain(73, 100 + k, int(rng.integers(20, 60)))
+            g = np.array([k % side, (k // side) % side, k // (side * side)], dtype=float) * 120.0
+            ids.append(tcm.tcm_mol_upload(ctx, x - x.mean(axis=0) + g, q,
+                                          precision=tcm.TCM_F64 if k % 2 else tcm.TCM_F32C))
+        U, st = tcm.tcm_all_pairs(ctx, ids, L)
+        assert len(U) == K * (K - 1) // 2 and np.all(st == 0)
+        cen = [tcm.tcm_mol_moments(ctx, i, L, flags=tcm.TCM_REUSE)[2] for i in ids]
+        ii, jj = np.triu_indices(K, 1)                # row-major upper triangle
+        assert np.array_equal(tcm.pair_index(ii, jj, K), np.arange(len(ii)))
+        Rd = np.array([cen[j] - cen[i] for i, j in zip(ii, jj)])
+        Ub, stb, _ = tcm.tcm_batch_energy(ctx, tcm.make_requests(np.array(ids)[ii], np.array(ids)[jj], Rd, L,
+                                                                flags=tcm.TCM_REUSE))
+        assert np.all(stb == 0) and np.array_equal(U, Ub)
+    finally:
+        for i in ids:
+            tcm.tcm_mol_release(ctx, i)
+
+
 def test_all_pairs_overlap_and_errors(ctx, synth):
     K = 5
     fr = fragments(synth, K, 32, 400.0, close=3)
