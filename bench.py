@@ -500,6 +500,28 @@ def single_pair_section(tcm, synth, reps=1000, check=True):
     return out
 
 
+def large_molecule(tcm, torch, n, L=8, reps=8):
+    """Phase times (HIP events) of the moment pass of one molecule of n atoms: the statistics
+    and centre/scale, the tile launch, and the finalisation that merges the tiles' partials
+    (the pair launch is a single pair with itself, unchecked)."""
+    stride = n + 64
+    buf = torch.rand(4 * stride, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ctx = tcm.Context(0)
+    base = buf.data_ptr()
+    mid = tcm.tcm_mol_register_device(ctx.h, *[base + 8 * stride * k for k in range(4)], n)
+    pl = tcm.tcm_plan_create(ctx.h, tcm.make_requests(mid, mid, [1e9, 0.0, 0.0], L, flags=tcm.TCM_UNCHECKED),
+                             use_graph=False)
+    ms = np.array([tcm.tcm_plan_run_timed(ctx.h, pl) for _ in range(reps)])[2:]
+    tcm.tcm_plan_destroy(pl)
+    tcm.tcm_mol_release(ctx.h, mid)
+    ctx.close()
+    med = np.median(ms, axis=0)
+    return {"workload": f"one molecule of {n} atoms (uniform random in device memory), L = {L}, FP32 moments",
+            "phase_ms": {"stats": float(med[0]), "moment_tiles": float(med[1]), "moment_finalise": float(med[2]),
+                         "pairs": float(med[3])}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +539,9 @@ def main():
     ap.add_argument("--no-forces", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--large-molecule", type=int, default=0, metavar="N",
+                    help="only time the moment pass of one molecule of N atoms (L = 8, uniform random "
+                         "coordinates and charges in device memory) by phase, and exit")
     ap.add_argument("--alu-calibration", action="store_true",
                     help="only measure the sustained plain FP32 and FP64 FMA rates and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -540,6 +565,9 @@ def main():
                           "launches": 3}), flush=True)
         return
     from paper_0704_1672_amd import synth, tcm
+    if args.large_molecule > 0:
+        print(json.dumps(large_molecule(tcm, torch, args.large_molecule)), flush=True)
+        return
     if args.alu_calibration:
         ctx = tcm.Context(0)
         r = {"fp32_fma_tflops": tcm.tcm_alu_calibrate(ctx.h, tcm.TCM_F32C),

@@ -403,7 +403,7 @@ __device__ inline void finalize_moments(const DevPlan& P, int mol, char* smem)
     const int tid = threadIdx.x;
     const int L = mw.L, NHl = nh(L);
     double* spow = reinterpret_cast<double*>(smem);       // s^l, l = 0..L
-    double* red = spow + (LMAX + 2);
+    double* red = spow + (LMAX + 2);                      // [WG]
     if (tid == 0) {
         const double s = mw.meta[4];
         spow[0] = 1.0;
@@ -417,23 +417,87 @@ __device__ inline void finalize_moments(const DevPlan& P, int mol, char* smem)
         if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
         __syncthreads();
     }
+    const double r2max = red[0];
+    __syncthreads();
+    // Tile partials.  Up to FIN_SERIAL_MAX tiles, one thread per harmonic sums them in tile
+    // order; beyond, FIN_H harmonics at a time: thread (hl, g) sums the tiles t = g, g + FIN_G,
+    // ... of harmonic h0 + hl (four tiles' loads in flight before they are added), then the
+    // FIN_G group sums are added in group order.  A fixed order per molecule, whatever else
+    // shares the launch; a molecule of thousands of tiles no longer waits on one dependent
+    // chain of loads per harmonic.
+    constexpr int FIN_H = 32, FIN_G = WG / FIN_H, FIN_SERIAL_MAX = 256;
+    const int hl = tid % FIN_H, g = tid / FIN_H;
     const int64_t nt = mw.ntiles;
-    for (int h = tid; h < NHl; h += WG) {
-        double v;
+    if (nt <= FIN_SERIAL_MAX) {
+        // few tiles (every molecule of a typical batch): one thread per harmonic, tiles in order
+        for (int h = tid; h < NHl; h += WG) {
+            double v;
+            if (mw.prec == TCM_F32C) {
+                const float* hi = P.part_f + mw.part_off;
+                const float* lo = P.part_f + mw.part_off + nt * NHl;
+                float H = 0.0f, Lo = 0.0f;
+                for (int64_t t = 0; t < nt; ++t) df_add(H, Lo, hi[t * NHl + h], lo[t * NHl + h]);
+                v = (double)H + (double)Lo;
+            } else {
+                const double* pd = P.part_d + mw.part_off;
+                v = 0.0;
+                for (int64_t t = 0; t < nt; ++t) v += pd[t * NHl + h];
+            }
+            mw.Q[h] = v * P.invk[h] * spow[l_of(h)];
+        }
+    }
+    for (int h0 = 0; nt > FIN_SERIAL_MAX && h0 < NHl; h0 += FIN_H) {
+        const int h = h0 + hl;
         if (mw.prec == TCM_F32C) {
             const float* hi = P.part_f + mw.part_off;
             const float* lo = P.part_f + mw.part_off + nt * NHl;
             float H = 0.0f, Lo = 0.0f;
-            for (int64_t t = 0; t < nt; ++t) df_add(H, Lo, hi[t * NHl + h], lo[t * NHl + h]);
-            v = (double)H + (double)Lo;
+            if (h < NHl) {
+                int64_t t = g;
+                for (; t + 3 * FIN_G < nt; t += 4 * FIN_G) {
+                    float a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = hi[(t + u * FIN_G) * NHl + h];
+                        b[u] = lo[(t + u * FIN_G) * NHl + h];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) df_add(H, Lo, a[u], b[u]);
+                }
+                for (; t < nt; t += FIN_G) df_add(H, Lo, hi[t * NHl + h], lo[t * NHl + h]);
+            }
+            float* rf = reinterpret_cast<float*>(red);     // [WG] highs, then [WG] lows
+            rf[tid] = H;
+            rf[WG + tid] = Lo;
+            __syncthreads();
+            if (g == 0 && h < NHl) {
+                for (int q = 1; q < FIN_G; ++q) df_add(H, Lo, rf[q * FIN_H + hl], rf[WG + q * FIN_H + hl]);
+                mw.Q[h] = ((double)H + (double)Lo) * P.invk[h] * spow[l_of(h)];
+            }
         } else {
             const double* pd = P.part_d + mw.part_off;
-            v = 0.0;
-            for (int64_t t = 0; t < nt; ++t) v += pd[t * NHl + h];
+            double v = 0.0;
+            if (h < NHl) {
+                int64_t t = g;
+                for (; t + 3 * FIN_G < nt; t += 4 * FIN_G) {
+                    double a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = pd[(t + u * FIN_G) * NHl + h];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v += a[u];
+                }
+                for (; t < nt; t += FIN_G) v += pd[t * NHl + h];
+            }
+            red[tid] = v;
+            __syncthreads();
+            if (g == 0 && h < NHl) {
+                for (int q = 1; q < FIN_G; ++q) v += red[q * FIN_H + hl];
+                mw.Q[h] = v * P.invk[h] * spow[l_of(h)];
+            }
         }
-        mw.Q[h] = v * P.invk[h] * spow[l_of(h)];
+        __syncthreads();
     }
-    if (tid == 0) mw.meta[3] = sqrt(red[0]);
+    if (tid == 0) mw.meta[3] = sqrt(r2max);
     __syncthreads();
 }
 
