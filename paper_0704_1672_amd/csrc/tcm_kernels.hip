@@ -75,6 +75,64 @@ __device__ __forceinline__ void stats_item(const DevPlan& P, int mol, int chunk,
     __syncthreads();
 }
 
+// An item covering a run of consecutive chunks (molecules with more chunks than the planner's
+// item cap): the same record over all of the run's atoms.
+__device__ __forceinline__ void stats_run(const DevPlan& P, int mol, int item, char* smem)
+{
+    const MolWork& mw = P.mols[mol];
+    const int tid = threadIdx.x;
+    // the molecule's chunks of STATS_CHUNK atoms, split over its nstats items in runs of
+    // consecutive chunks (one chunk per item unless the planner capped the item count)
+    const int64_t nch = (mw.n + STATS_CHUNK - 1) / STATS_CHUNK;
+    double v[9] = {0, 0, 0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    auto chunk_stats = [&](int64_t chunk) __attribute__((always_inline)) {
+        const int64_t first = chunk * STATS_CHUNK;
+        const int span = (int)min(mw.n - first, (int64_t)STATS_CHUNK);   // >= 1
+        const uint32_t bytes = (uint32_t)span * 8u;
+        const rsrc_t rx = tile_rsrc(mw.x, first, bytes), ry = tile_rsrc(mw.y, first, bytes),
+                     rz = tile_rsrc(mw.z, first, bytes);
+        double x[STATS_PER_THREAD], y[STATS_PER_THREAD], z[STATS_PER_THREAD];
+        const uint32_t last = (uint32_t)(span - 1) * 8u;
+#pragma unroll
+        for (int j = 0; j < STATS_PER_THREAD; ++j) {     // past the chunk's end: clamped, masked below
+            const uint32_t off = min((uint32_t)(tid + j * WG) * 8u, last);
+            x[j] = bload(rx, off);
+            y[j] = bload(ry, off);
+            z[j] = bload(rz, off);
+        }
+#pragma unroll
+        for (int j = 0; j < STATS_PER_THREAD; ++j) {
+            if (tid + j * WG >= span) break;
+            v[0] += x[j]; v[1] += y[j]; v[2] += z[j];
+            v[3] = fmin(v[3], x[j]); v[4] = fmin(v[4], y[j]); v[5] = fmin(v[5], z[j]);
+            v[6] = fmax(v[6], x[j]); v[7] = fmax(v[7], y[j]); v[8] = fmax(v[8], z[j]);
+        }
+    };
+    const int64_t per = (nch + mw.nstats - 1) / mw.nstats;
+    const int64_t c1 = min(nch, (int64_t)(item + 1) * per);
+    for (int64_t chunk = (int64_t)item * per; chunk < c1; ++chunk) chunk_stats(chunk);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = wave_min(v[k]);
+#pragma unroll
+    for (int k = 6; k < 9; ++k) v[k] = wave_max(v[k]);
+    double* red = reinterpret_cast<double*>(smem);   // [WG / 64][9]
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0)
+        for (int k = 0; k < 9; ++k) red[wave * 9 + k] = v[k];
+    __syncthreads();
+    if (tid < 9) {
+        double a = red[tid];
+        for (int w = 1; w < WG / 64; ++w) {
+            const double b = red[w * 9 + tid];
+            a = tid < 3 ? a + b : tid < 6 ? fmin(a, b) : fmax(a, b);
+        }
+        P.stats_part[(mw.stats_off + item) * 10 + tid] = a;
+    }
+    __syncthreads();
+}
+
 // Centre (the given one, else the centroid) and scale s >= max |r_i - c| of one molecule from
 // its chunk records: one workgroup per molecule, each thread merges a strided subset of the
 // records, then a fixed-order tree over the threads.
@@ -999,7 +1057,13 @@ __global__ __launch_bounds__(WG) void tcm_stats(DevPlan P, int begin, int end)
     const int item = begin + (int)blockIdx.x;
     if (item >= end) return;
     const int mol = __builtin_amdgcn_readfirstlane(P.stats_items[2 * item]);
-    stats_item(P, mol, __builtin_amdgcn_readfirstlane(P.stats_items[2 * item + 1]), smem);
+    const int k = __builtin_amdgcn_readfirstlane(P.stats_items[2 * item + 1]);
+    const MolWork& mw = P.mols[mol];
+    // one chunk per item unless the molecule has more chunks than the planner's item cap
+    if ((mw.n + STATS_CHUNK - 1) / STATS_CHUNK <= mw.nstats)
+        stats_item(P, mol, k, smem);
+    else
+        stats_run(P, mol, k, smem);
 }
 
 __global__ __launch_bounds__(WG) void tcm_stats_finalize(DevPlan P, int mol_begin, int mol_end)

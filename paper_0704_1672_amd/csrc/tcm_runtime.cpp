@@ -309,6 +309,17 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Device bytes build_plan would add to ws for these jobs (growth of each buffer beyond its
 // current capacity), so that a caller can make room under its HBM budget first.
+// Statistics items of a molecule: one per chunk of STATS_CHUNK atoms, at most STATS_ITEMS_MAX;
+// a larger molecule gives each item a run of consecutive chunks (the kernel derives the run
+// length from the chunk and item counts), so its centre/scale merge reads few records.
+constexpr int64_t STATS_ITEMS_MAX = 8192;
+static int64_t stats_items_for(int64_t n)
+{
+    const int64_t nch = n > 0 ? (n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
+    const int64_t per = (nch + STATS_ITEMS_MAX - 1) / STATS_ITEMS_MAX;
+    return (nch + per - 1) / per;
+}
+
 size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& mols, const std::vector<PairJob>& pairs)
 {
     int64_t off_f = 0, off_d = 0, off_s = 0, off_r2 = 0, nitems = 0;
@@ -317,7 +328,7 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
         const int64_t ta = (int64_t)WG * kper;
         const int64_t nt = j.n > 0 ? (j.n + ta - 1) / ta : 1;
         nitems += nt * num_blocks_for(j.prec, j.L);
-        const int64_t ns = j.n > 0 ? (j.n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
+        const int64_t ns = stats_items_for(j.n);
         if (j.prec == TCM_F32C) off_f += 2 * nt * nh(j.L); else off_d += nt * nh(j.L);
         off_s += ns;
         off_r2 += nt;
@@ -371,7 +382,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         w.nblk = num_blocks_for(j.prec, j.L);
         const int64_t tile_atoms = (int64_t)WG * w.kper;
         const int64_t nt = j.n > 0 ? (j.n + tile_atoms - 1) / tile_atoms : 1;
-        const int64_t ns = j.n > 0 ? (j.n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
+        const int64_t ns = stats_items_for(j.n);
         if (nt > (1 << 24) || ns > (1 << 24)) return TCM_EINVAL;
         w.ntiles = (int)nt;
         w.nstats = (int)ns;
