@@ -133,3 +133,23 @@ def test_uneven_batch_full_size(ctx, orc, synth):
             tcm.tcm_mol_release(ctx, i)
         del soa
         torch.cuda.empty_cache()
+
+
+def test_very_large_molecule_capped_statistics_items(ctx, orc, synth):
+    """17M charges: more chunks than the planner's statistics-item cap, so each item covers a
+    run of chunks.  Centre (centroid), radius and the FP64 moments at L = 4 against the oracle
+    and the direct definitions."""
+    n = 17_000_000
+    x, q = synth.ball(91, 1, n, 5000.0)
+    mid = tcm.tcm_mol_upload(ctx, x, q, precision=tcm.TCM_F64)
+    try:
+        Q, radius, centre = tcm.tcm_mol_moments(ctx, mid, 4)
+        c = orc.centroid(x)
+        assert np.allclose(centre, c, rtol=0, atol=1e-9 * 5000.0), (centre, c)
+        assert abs(radius - orc.radius(x, centre)) <= 1e-12 * radius
+        Qo = orc.complex_to_packed(orc.moments(x, q, centre, 4))
+        _, qa = orc.moments(x, q, centre, 4, with_abs=True)
+        scale = np.max(qa)
+        assert np.max(np.abs(Q - Qo)) <= 1e-10 * scale, np.max(np.abs(Q - Qo)) / scale
+    finally:
+        tcm.tcm_mol_release(ctx, mid)
