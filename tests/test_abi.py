@@ -53,3 +53,15 @@ def test_make_requests_broadcasts_scalars_and_rows():
     assert np.all(req["flags"] == tcm.TCM_REUSE) and list(req["L"]) == [8, 8, 16, 16, 20]
     with pytest.raises(ValueError):
         tcm.make_requests([1, 2, 3], 0, np.zeros((2, 3)), 8)  # incompatible lengths
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: asked for more it says so and exits non-zero, before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU only" in (r.stdout + r.stderr)
