@@ -37,6 +37,12 @@ def load():
     lib.oracle_moments.restype = C.c_int
     lib.oracle_energy.argtypes = [_dp, C.c_int, _dp, C.c_int, _dp, C.c_int, _dp, _dp, _dp, _dp]
     lib.oracle_energy.restype = C.c_int
+    lib.oracle_energy_shape.argtypes = [_dp, C.c_int, _dp, C.c_int, _dp, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+    lib.oracle_energy_shape.restype = C.c_int
+    lib.oracle_energy_sensitivity.argtypes = [_dp, _dp, C.c_int, _dp, _dp, C.c_int, _dp, C.c_int, C.c_int, _dp]
+    lib.oracle_energy_sensitivity.restype = C.c_int
+    lib.oracle_trunc_bound_tri.argtypes = [C.c_double] * 5 + [C.c_int]
+    lib.oracle_trunc_bound_tri.restype = C.c_double
     lib.oracle_coulomb.argtypes = [_dp, _dp, C.c_int64, _dp, _dp, C.c_int64]
     lib.oracle_coulomb.restype = C.c_double
     lib.oracle_pose.argtypes = [_dp, C.c_int64, _dp, _dp, _dp, _dp]
@@ -112,8 +118,12 @@ def order_of(Q):
     return L
 
 
-def energy(QA, QB, R, L, full=False):
-    """eq. (9) with square truncation l1, l2 <= L.  Returns Re U (and diagnostics if full)."""
+SQUARE, TRIANGULAR = 0, 1      # truncation shapes: l1, l2 <= L  /  l1 + l2 <= L
+
+
+def energy(QA, QB, R, L, full=False, shape=SQUARE):
+    """eq. (9) with square (l1, l2 <= L, default) or triangular (l1 + l2 <= L) truncation.
+    Returns Re U (and diagnostics if full)."""
     QA = np.asarray(QA, dtype=np.complex128)
     QB = np.asarray(QB, dtype=np.complex128)
     LA, LB = order_of(QA), order_of(QB)
@@ -122,8 +132,12 @@ def energy(QA, QB, R, L, full=False):
     R = _f64(R, (3,))
     ure, uim, asum = C.c_double(), C.c_double(), C.c_double()
     terms = np.zeros((L + 1) ** 2)
-    rc = load().oracle_energy(_p(qa), LA, _p(qb), LB, _p(R), int(L), C.byref(ure), C.byref(uim),
-                              _p(terms), C.byref(asum))
+    if shape == SQUARE:
+        rc = load().oracle_energy(_p(qa), LA, _p(qb), LB, _p(R), int(L), C.byref(ure), C.byref(uim),
+                                  _p(terms), C.byref(asum))
+    else:
+        rc = load().oracle_energy_shape(_p(qa), LA, _p(qb), LB, _p(R), int(L), int(shape), C.byref(ure),
+                                        C.byref(uim), _p(terms), C.byref(asum))
     if rc != 0:
         raise ValueError(f"oracle_energy failed ({rc})")
     if full:
@@ -149,8 +163,26 @@ def pose(xyz, c_old, quat, c_new):
     return out
 
 
-def trunc_bound(SA, SB, aA, aB, R, L):
-    return load().oracle_trunc_bound(float(SA), float(SB), float(aA), float(aB), float(R), int(L))
+def trunc_bound(SA, SB, aA, aB, R, L, shape=SQUARE):
+    f = load().oracle_trunc_bound if shape == SQUARE else load().oracle_trunc_bound_tri
+    return f(float(SA), float(SB), float(aA), float(aB), float(R), int(L))
+
+
+def energy_sensitivity(QA, AbarA, QB, AbarB, R, L, shape=SQUARE):
+    """sum over the kept terms of |factor| (Abar^A |Q^B| + |Q^A| Abar^B): a moment error of
+    at most e * Abar_lm per entry changes eq. (9) by at most e times this, to first order."""
+    QA = np.asarray(QA, dtype=np.complex128)
+    QB = np.asarray(QB, dtype=np.complex128)
+    AbarA = _f64(AbarA)
+    AbarB = _f64(AbarB)
+    assert len(AbarA) == len(QA) and len(AbarB) == len(QB)
+    qa, qb = _interleave(QA), _interleave(QB)
+    out = C.c_double()
+    rc = load().oracle_energy_sensitivity(_p(qa), _p(AbarA), order_of(QA), _p(qb), _p(AbarB), order_of(QB),
+                                          _p(_f64(R, (3,))), int(L), int(shape), C.byref(out))
+    if rc != 0:
+        raise ValueError(f"oracle_energy_sensitivity failed ({rc})")
+    return out.value
 
 
 def complex_to_packed(Q, L=None):

@@ -14,8 +14,12 @@
  *   - eq. (6)  3j symbols (general Racah formula)         -> oracle_threej
  *   - eq. (9)  truncated two-centre energy, square truncation l1,l2 <= Lmax
  *                                                          -> oracle_energy
- * plus two test helpers that are not in the paper: the rigid pose of a molecule
- * (oracle_pose) and a rigorous truncation-error bound (oracle_trunc_bound), and the
+ *              or triangular truncation l1+l2 <= Lmax      -> oracle_energy_shape
+ * plus test helpers that are not in the paper: the rigid pose of a molecule
+ * (oracle_pose), rigorous truncation-error bounds for both truncation shapes
+ * (oracle_trunc_bound, oracle_trunc_bound_tri), the first-order sensitivity of eq. (9) to
+ * perturbations of the moments (oracle_energy_sensitivity, the scale of the rounding error
+ * of a reduced-precision moment pass), and the
  * forces the paper names as the other use of its final expression (section I):
  *   - -grad_R0 of eq. (9), term by term                   -> oracle_energy_grad
  *   - the coefficients of eq. (9) as a linear function of one molecule's moments
@@ -260,13 +264,21 @@ int oracle_moments(const double *xyz, const double *q, int64_t n, const double *
  * with their orders LA, LB.  Outputs: U_re, U_im (the sum is real up to rounding),
  * optional terms[(L+1)^2] = Re of the partial sum for each (l1, l2) at index l1*(L+1)+l2,
  * optional abs_sum = sum of |term| (the scale against which rounding is judged).
+ *
+ * shape selects which (l1, l2) blocks the sum keeps.  The limits printed under eq. (9) are
+ * garbled ("l1, l2 = 0" and "l1 + l2 = L" under L_max); the text after it and eq. (11) loop
+ * l1 and l2 each to L_max (shape 0, square, the reading used everywhere by default); the
+ * other reading keeps the blocks of total order l1 + l2 <= L_max (shape 1, triangular), whose
+ * dropped blocks are exactly the (L'+1)-th and higher orders of the expansion of eq. (3).
+ * Blocks a shape drops are not summed and their terms[] entries are 0.
  * ------------------------------------------------------------------------------- */
-int oracle_energy(const double *QA, int LA, const double *QB, int LB, const double *R, int L,
-                  double *U_re, double *U_im, double *terms, double *abs_sum)
+int oracle_energy_shape(const double *QA, int LA, const double *QB, int LB, const double *R, int L,
+                        int shape, double *U_re, double *U_im, double *terms, double *abs_sum)
 {
     fact_init();
     if (!QA || !QB || !R || !U_re || L < 0 || L > LA || L > LB || 2 * L > 4 * ORACLE_LMAX)
         return -1;
+    if (shape != 0 && shape != 1) return -1;
     double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
     if (!(Rn > 0.0)) return -1;
     double ctr = R[2] / Rn;
@@ -281,6 +293,10 @@ int oracle_energy(const double *QA, int LA, const double *QB, int LB, const doub
     for (int l1 = 0; l1 <= L; ++l1) {
         for (int l2 = 0; l2 <= L; ++l2) {
             int Lp = l1 + l2;
+            if (shape == 1 && Lp > L) {
+                if (terms) terms[l1 * (L + 1) + l2] = 0.0;
+                continue;
+            }
             double coef = (double)sqrtl(4.0L * (long double)M_PI * fact(2 * Lp) /
                                         (fact(2 * l1) * fact(2 * l2)));
             double rpow = pow(Rn, -(double)(Lp + 1));
@@ -321,6 +337,71 @@ int oracle_energy(const double *QA, int LA, const double *QB, int LB, const doub
     *U_re = nsum_value(&sre);
     if (U_im) *U_im = nsum_value(&sim);
     if (abs_sum) *abs_sum = nsum_value(&sab);
+    free(P);
+    return 0;
+}
+
+/* eq. (9) with the square truncation l1, l2 <= L (the reading used by default). */
+int oracle_energy(const double *QA, int LA, const double *QB, int LB, const double *R, int L,
+                  double *U_re, double *U_im, double *terms, double *abs_sum)
+{
+    return oracle_energy_shape(QA, LA, QB, LB, R, L, 0, U_re, U_im, terms, abs_sum);
+}
+
+/* ---------------------------------------------------------------------------------
+ * First-order sensitivity of eq. (9) to errors in the moments.  Eq. (9) is bilinear in the
+ * two tables, U = sum_t f_t Q^A_{l1m1} Q^B_{l2m2} with f_t the factor of each term (sign,
+ * R0 power, square root, 3j symbol, conj Y).  If every moment is perturbed by at most a
+ * multiple e of its absolute sum, |dQ_lm| <= e Abar_lm with Abar_lm = sum_i |q_i|
+ * |r_i^l sqrt(4 pi/(2l+1)) Y_lm| (the Qabs output of oracle_moments), then to first order
+ *   |dU| <= e * sum_t |f_t| (Abar^A_{l1m1} |Q^B_{l2m2}| + |Q^A_{l1m1}| Abar^B_{l2m2}).
+ * This returns that sum (without e) over the terms the truncation shape keeps.  QA, QB:
+ * complex tables as for oracle_energy; AbarA, AbarB: real tables of the same orders.
+ * ------------------------------------------------------------------------------- */
+int oracle_energy_sensitivity(const double *QA, const double *AbarA, int LA, const double *QB,
+                              const double *AbarB, int LB, const double *R, int L, int shape,
+                              double *out)
+{
+    fact_init();
+    if (!QA || !QB || !AbarA || !AbarB || !R || !out || L < 0 || L > LA || L > LB ||
+        2 * L > 4 * ORACLE_LMAX || (shape != 0 && shape != 1))
+        return -1;
+    double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (!(Rn > 0.0)) return -1;
+    double ctr = R[2] / Rn;
+    if (ctr > 1.0) ctr = 1.0;
+    if (ctr < -1.0) ctr = -1.0;
+    double Theta = acos(ctr);
+    int L2 = 2 * L;
+    double *P = (double *)malloc(sizeof(double) * (size_t)(L2 + 1) * (L2 + 2) / 2);
+    if (!P) return -3;
+    legendre_normalised(L2, cos(Theta), sin(Theta), P);
+    nsum_t acc = {0, 0};
+    for (int l1 = 0; l1 <= L; ++l1) {
+        for (int l2 = 0; l2 <= L; ++l2) {
+            int Lp = l1 + l2;
+            if (shape == 1 && Lp > L) continue;
+            double coef = (double)sqrtl(4.0L * (long double)M_PI * fact(2 * Lp) /
+                                        (fact(2 * l1) * fact(2 * l2)));
+            double rpow = pow(Rn, -(double)(Lp + 1));
+            for (int m1 = -l1; m1 <= l1; ++m1) {
+                int ka = l1 * l1 + l1 + m1;
+                double qa = hypot(QA[2 * ka], QA[2 * ka + 1]);
+                for (int m2 = -l2; m2 <= l2; ++m2) {
+                    int kb = l2 * l2 + l2 + m2;
+                    int M = m1 + m2;
+                    double tj = oracle_threej(l1, l2, Lp, m1, m2, -M);
+                    if (tj == 0.0) continue;
+                    int aM = M < 0 ? -M : M;
+                    /* |conj Y_{L'M}| = |Pbar_{L'}^{|M|}| */
+                    double f = fabs(rpow * coef * tj * P[Lp * (Lp + 1) / 2 + aM]);
+                    double qb = hypot(QB[2 * kb], QB[2 * kb + 1]);
+                    nsum_add(&acc, f * (AbarA[ka] * qb + qa * AbarB[kb]));
+                }
+            }
+        }
+    }
+    *out = nsum_value(&acc);
     free(P);
     return 0;
 }
@@ -605,4 +686,18 @@ double oracle_trunc_bound(double SA, double SB, double aA, double aB, double R, 
     if (!(al + be < 1.0)) return INFINITY;
     double t1 = pow(al / (1.0 - be), L + 1), t2 = pow(be / (1.0 - al), L + 1);
     return SA * SB / (R * (1.0 - al - be)) * (t1 + t2);
+}
+
+/* ---------------------------------------------------------------------------------
+ * The same for the triangular truncation l1 + l2 <= L (oracle_energy_shape, shape 1): the
+ * dropped terms are the bidegree (l1, l2) Taylor terms with l1 + l2 = n > L, whose bounds
+ * sum to C(n, l1) alpha^l1 beta^l2 summed over l1 = (alpha + beta)^n, so with t = alpha + beta
+ *   |dU| <= SA SB / R * sum_{n > L} t^n = SA SB t^{L+1} / (R (1 - t)).
+ * Requires t < 1 (eq. (2)); returns +inf otherwise.
+ * ------------------------------------------------------------------------------- */
+double oracle_trunc_bound_tri(double SA, double SB, double aA, double aB, double R, int L)
+{
+    double t = aA / R + aB / R;
+    if (!(t < 1.0)) return INFINITY;
+    return SA * SB * pow(t, L + 1) / (R * (1.0 - t));
 }

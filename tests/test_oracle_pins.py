@@ -361,3 +361,216 @@ def test_packed_roundtrip(orc):
     P = orc.complex_to_packed(Q)
     assert len(P) == 49
     assert np.max(np.abs(orc.packed_to_complex(P) - Q)) < 1e-15
+
+
+# ---------------------------------------------------------------- truncation bounds, by value
+def _taylor_tail_sums(al, be, L, nmax=None):
+    """Brute-force sums of the per-term bounds C(l1+l2, l1) al^l1 be^l2 of the double Taylor
+    series of 1/|R + r_B - r_A| (R = 1): over the blocks outside the square l1, l2 <= L
+    (union), over those with both orders above L (intersection, which the closed form of the
+    square bound counts twice), and over those outside the triangle l1 + l2 <= L.  Summed by
+    total order n = l1 + l2 until the terms are below 1e-300 of the sum."""
+    from scipy.special import gammaln
+    t = al + be
+    if nmax is None:
+        nmax = int(np.ceil(np.log(1e-19) / np.log(t))) + L + 60
+    union, inter, tri = [], [], []
+    for n in range(nmax + 1):
+        l1 = np.arange(n + 1)
+        l2 = n - l1
+        lt = gammaln(n + 1) - gammaln(l1 + 1) - gammaln(l2 + 1)
+        with np.errstate(divide="ignore"):
+            lt = lt + l1 * np.log(al) + l2 * np.log(be)
+        v = np.exp(lt)
+        union.extend(v[(l1 > L) | (l2 > L)])
+        inter.extend(v[(l1 > L) & (l2 > L)])
+        if n > L:
+            tri.extend(v)
+    return math.fsum(union), math.fsum(inter), math.fsum(tri)
+
+
+@pytest.mark.parametrize("al,be", [(0.1, 0.2), (0.3, 0.3), (0.45, 0.15), (0.05, 0.6), (0.4, 0.45)])
+def test_trunc_bound_value_equals_tail_sum(orc, al, be):
+    """The closed forms of both bounds equal the brute-force sums of the term bounds they
+    claim to add up (square: the two one-sided tails, i.e. the union of the dropped blocks plus
+    their intersection once more; triangle: every block of total order > L), so a wrong
+    exponent, a dropped (1 - alpha - beta) or a swapped ratio fails.  SA, SB and R scale it."""
+    SA, SB, R = 2.5, 0.7, 3.0
+    for L in (0, 1, 2, 4, 7, 10, 16):
+        union, inter, tri = _taylor_tail_sums(al, be, L)
+        b = orc.trunc_bound(SA, SB, al * R, be * R, R, L)
+        assert b == pytest.approx(SA * SB / R * (union + inter), rel=1e-12), (al, be, L)
+        assert b >= SA * SB / R * union
+        bt = orc.trunc_bound(SA, SB, al * R, be * R, R, L, shape=orc.TRIANGULAR)
+        assert bt == pytest.approx(SA * SB / R * tri, rel=1e-12), (al, be, L)
+
+
+def _tight_collinear(al, be, R=5.0):
+    """One unit charge in each molecule on the line of centres, each at its molecule's radius
+    and facing the other: every term of the double Taylor series is positive, so the error of
+    a truncation equals the sum of the bounds of the terms it drops."""
+    u = np.array([0.36, -0.48, 0.8])
+    cA = np.array([0.5, 1.0, -2.0])
+    cB = cA + R * u
+    xA = (cA + al * R * u)[None, :]
+    xB = (cB - be * R * u)[None, :]
+    return xA, np.ones(1), cA, xB, np.ones(1), cB, R
+
+
+@pytest.mark.parametrize("al,be", [(0.3, 0.3), (0.2, 0.45), (0.5, 0.1)])
+def test_trunc_bound_tight_collinear(orc, al, be):
+    xA, qA, cA, xB, qB, cB, R = _tight_collinear(al, be)
+    Uc = orc.coulomb(xA, qA, xB, qB)
+    assert Uc == pytest.approx(1.0 / (R * (1.0 - al - be)), rel=1e-14)
+    QA, QB = orc.moments(xA, qA, cA, 12), orc.moments(xB, qB, cB, 12)
+    for L in range(1, 11):
+        union, inter, tri = _taylor_tail_sums(al, be, L)
+        err_sq = Uc - orc.energy(QA, QB, cB - cA, L)
+        err_tri = Uc - orc.energy(QA, QB, cB - cA, L, shape=orc.TRIANGULAR)
+        # the square truncation misses exactly the union of the dropped blocks
+        assert err_sq == pytest.approx(union / R, rel=1e-9, abs=1e-15 / R), (L, err_sq, union / R)
+        b = orc.trunc_bound(1.0, 1.0, al * R, be * R, R, L)
+        assert err_sq <= b and b == pytest.approx((union + inter) / R, rel=1e-12)
+        # the triangular truncation misses exactly its bound: the bound is attained
+        bt = orc.trunc_bound(1.0, 1.0, al * R, be * R, R, L, shape=orc.TRIANGULAR)
+        assert err_tri == pytest.approx(bt, rel=1e-9), (L, err_tri, bt)
+
+
+# ---------------------------------------------------------------- triangular truncation
+def test_triangular_collinear_closed_form(orc):
+    """Charges on the line of centres: the triangular sum keeps exactly the blocks
+    l1 + l2 <= L of the 1-D Taylor double series, and drops the others."""
+    rng = np.random.default_rng(19)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    zA, zB = rng.uniform(-1, 1, 6), rng.uniform(-1.1, 1.1, 5)
+    qA, qB = rng.uniform(-1, 1, 6), rng.uniform(-1, 1, 5)
+    R = 5.5
+    cA = np.array([-1.0, 0.5, 2.0])
+    cB = cA + R * u
+    xA, xB = cA + zA[:, None] * u, cB + zB[:, None] * u
+    QA, QB = orc.moments(xA, qA, cA, 9), orc.moments(xB, qB, cB, 9)
+    for L in (0, 1, 3, 6, 9):
+        d = orc.energy(QA, QB, cB - cA, L, full=True, shape=orc.TRIANGULAR)
+        tot = 0.0
+        for l1 in range(L + 1):
+            for l2 in range(L + 1):
+                ref = 0.0
+                if l1 + l2 <= L:
+                    ref = (-1) ** l2 * math.comb(l1 + l2, l1) * np.sum(qA * zA ** l1) * np.sum(qB * zB ** l2) \
+                        / R ** (l1 + l2 + 1)
+                tot += ref
+                scale = abs(ref) + 1e-3 * math.comb(l1 + l2, l1) / R ** (l1 + l2 + 1)
+                assert abs(d["terms"][l1, l2] - ref) < 1e-13 * scale, (L, l1, l2)
+        assert d["U"] == pytest.approx(tot, rel=1e-12, abs=1e-15)
+
+
+def test_triangular_equals_taylor_orders(orc):
+    """The triangular sum at L is the Taylor series of eq. (1) through total order L:
+    the sum of the Cartesian Taylor blocks with l1 + l2 <= L (sympy derivatives of 1/R)."""
+    xA, qA, cA, xB, qB, cB = _two_clouds(13, nA=5, nB=4, t=0.45)
+    ref = _cartesian_taylor_terms(xA, qA, cA, xB, qB, cB, 4)
+    QA, QB = orc.moments(xA, qA, cA, 4), orc.moments(xB, qB, cB, 4)
+    scale = max(abs(v) for v in ref.values())
+    for L in range(5):
+        U = orc.energy(QA, QB, cB - cA, L, shape=orc.TRIANGULAR)
+        want = sum(v for (l1, l2), v in ref.items() if l1 + l2 <= L)
+        assert abs(U - want) < 1e-12 * scale, (L, U, want)
+
+
+@pytest.mark.parametrize("t", [0.3, 0.6, 0.85])
+def test_triangular_vs_direct_sum_within_bound(orc, t):
+    """P1 for the triangular truncation: |U_tri(L) - eq. (1)| <= S_A S_B t^{L+1}/(R(1-t)),
+    and at equal L the square truncation (which keeps more blocks) is at least as close on
+    average over the seeds."""
+    e_sq, e_tri = 0.0, 0.0
+    for seed in range(3):
+        xA, qA, cA, xB, qB, cB = _two_clouds(40 + seed, t=t)
+        Uc = orc.coulomb(xA, qA, xB, qB)
+        aA, aB = orc.radius(xA, cA), orc.radius(xB, cB)
+        R = np.linalg.norm(cB - cA)
+        QA, QB = orc.moments(xA, qA, cA, 12), orc.moments(xB, qB, cB, 12)
+        for L in range(13):
+            U = orc.energy(QA, QB, cB - cA, L, shape=orc.TRIANGULAR)
+            b = orc.trunc_bound(np.abs(qA).sum(), np.abs(qB).sum(), aA, aB, R, L, shape=orc.TRIANGULAR)
+            assert abs(U - Uc) <= b * (1 + 1e-9) + 1e-14, (t, seed, L, U, Uc, b)
+        e_tri += abs(orc.energy(QA, QB, cB - cA, 8, shape=orc.TRIANGULAR) - Uc)
+        e_sq += abs(orc.energy(QA, QB, cB - cA, 8) - Uc)
+    assert e_sq <= e_tri
+
+
+def test_square_minus_triangular_is_the_high_blocks(orc):
+    xA, qA, cA, xB, qB, cB = _two_clouds(14, t=0.5)
+    L = 7
+    QA, QB = orc.moments(xA, qA, cA, L), orc.moments(xB, qB, cB, L)
+    sq = orc.energy(QA, QB, cB - cA, L, full=True)
+    tri = orc.energy(QA, QB, cB - cA, L, full=True, shape=orc.TRIANGULAR)
+    hi = sum(sq["terms"][l1, l2] for l1 in range(L + 1) for l2 in range(L + 1) if l1 + l2 > L)
+    assert sq["U"] - tri["U"] == pytest.approx(hi, rel=1e-10, abs=1e-14 * sq["abs_sum"])
+    for l1 in range(L + 1):
+        for l2 in range(L + 1 - l1):
+            assert tri["terms"][l1, l2] == sq["terms"][l1, l2]
+
+
+# ---------------------------------------------------------------- sensitivity of eq. (9)
+def test_sensitivity_single_charges_is_twice_abs_sum(orc):
+    """With one charge per molecule the absolute sums equal the moduli of the moments
+    (Abar_lm = |Q_lm|), so the sensitivity is 2 sum_t |f_t Q^A Q^B| = 2 abs_sum."""
+    xA, qA, cA, xB, qB, cB = _two_clouds(15, nA=1, nB=1, t=0.5)
+    for shape in (orc.SQUARE, orc.TRIANGULAR):
+        for L in (0, 3, 8):
+            QA, AA = orc.moments(xA, qA, cA, L, with_abs=True)
+            QB, AB = orc.moments(xB, qB, cB, L, with_abs=True)
+            assert np.allclose(AA, np.abs(QA), rtol=1e-13) and np.allclose(AB, np.abs(QB), rtol=1e-13)
+            d = orc.energy(QA, QB, cB - cA, L, full=True, shape=shape)
+            s = orc.energy_sensitivity(QA, AA, QB, AB, cB - cA, L, shape=shape)
+            assert s == pytest.approx(2.0 * d["abs_sum"], rel=1e-12), (shape, L)
+
+
+def test_sensitivity_brute_force_small_order(orc):
+    """Independent evaluation for L <= 2: each term's factor from sympy's 3j symbol and scipy's
+    Y_lm, summed in Python."""
+    from scipy.special import sph_harm_y
+    from sympy.physics.wigner import wigner_3j
+    xA, qA, cA, xB, qB, cB = _two_clouds(16, nA=4, nB=3, t=0.5)
+    Rv = cB - cA
+    R = np.linalg.norm(Rv)
+    th, ph = math.acos(Rv[2] / R), math.atan2(Rv[1], Rv[0])
+    for shape in (orc.SQUARE, orc.TRIANGULAR):
+        L = 2
+        QA, AA = orc.moments(xA, qA, cA, L, with_abs=True)
+        QB, AB = orc.moments(xB, qB, cB, L, with_abs=True)
+        ref = 0.0
+        for l1 in range(L + 1):
+            for l2 in range(L + 1):
+                if shape == orc.TRIANGULAR and l1 + l2 > L:
+                    continue
+                Lp = l1 + l2
+                coef = math.sqrt(4 * math.pi * math.factorial(2 * Lp) / (math.factorial(2 * l1) * math.factorial(2 * l2)))
+                for m1 in range(-l1, l1 + 1):
+                    for m2 in range(-l2, l2 + 1):
+                        M = m1 + m2
+                        f = abs(R ** -(Lp + 1) * coef * float(wigner_3j(l1, l2, Lp, m1, m2, -M))
+                                * complex(sph_harm_y(Lp, M, th, ph)))
+                        ka, kb = l1 * l1 + l1 + m1, l2 * l2 + l2 + m2
+                        ref += f * (AA[ka] * abs(QB[kb]) + abs(QA[ka]) * AB[kb])
+        s = orc.energy_sensitivity(QA, AA, QB, AB, Rv, L, shape=shape)
+        assert s == pytest.approx(ref, rel=1e-12), shape
+
+
+def test_sensitivity_bounds_moment_perturbations(orc):
+    """Moments perturbed by e * Abar with random phases change eq. (9) by at most
+    e * sensitivity + e^2 * (the bilinear remainder)."""
+    xA, qA, cA, xB, qB, cB = _two_clouds(17, t=0.6)
+    L = 8
+    QA, AA = orc.moments(xA, qA, cA, L, with_abs=True)
+    QB, AB = orc.moments(xB, qB, cB, L, with_abs=True)
+    U0 = orc.energy(QA, QB, cB - cA, L)
+    s = orc.energy_sensitivity(QA, AA, QB, AB, cB - cA, L)
+    rng = np.random.default_rng(3)
+    e = 1e-7
+    for _ in range(5):
+        dA = e * AA * np.exp(2j * np.pi * rng.uniform(size=len(AA)))
+        dB = e * AB * np.exp(2j * np.pi * rng.uniform(size=len(AB)))
+        dU = orc.energy(QA + dA, QB + dB, cB - cA, L) - U0
+        assert abs(dU) <= e * s * (1 + 1e-6)
