@@ -64,6 +64,10 @@ extern "C" {
 #define TCM_REUSE      2    /* use the molecule's resident moments if their order is >= L    */
 #define TCM_DEVICE_IO  16   /* tcm_scan_translations: R, U_out, status_out are device         */
                             /* pointers and the call is asynchronous on the context's stream  */
+#define TCM_TRIANGULAR 32   /* truncate eq. 9 to the blocks l1 + l2 <= L (the other reading   */
+                            /* of its garbled limits) instead of the square l1, l2 <= L:      */
+                            /* energies, batches, scans, all pairs, adaptive truncation and   */
+                            /* serving; the force entry points reject it (TCM_EINVAL)         */
 
 typedef struct tcm_ctx tcm_ctx;
 typedef struct tcm_plan tcm_plan;
@@ -101,11 +105,13 @@ int tcm_moments(tcm_ctx *ctx, const double *coords, const double *charges, int64
                 const double *centre, int L, int precision, double *Q_out, double *radius_out,
                 double *centre_out);
 
-/* eq. 9 with square truncation l1, l2 <= L for one pair, from host moment tables.
+/* eq. 9 with square truncation l1, l2 <= L (or l1 + l2 <= L with TCM_TRIANGULAR) for one
+ * pair, from host moment tables.
  * QA, QB: packed FP64 tables of order >= L.  aA, aB: the molecules' radii (eq. 2 test).
  * R: FP64[3], c_B - c_A.  quat_b: FP64[4] unit quaternion (w, x, y, z) rotating B actively
  * about its centre before the contraction, or NULL for none; QB are B's moments in its
- * unrotated frame.  flags: TCM_UNCHECKED or 0.  U_out: the energy.  Synchronous. */
+ * unrotated frame.  flags: TCM_UNCHECKED, TCM_TRIANGULAR or 0.  U_out: the energy.
+ * Synchronous. */
 int tcm_pair_energy(tcm_ctx *ctx, const double *QA, double aA, const double *QB, double aB,
                     const double *R, const double *quat_b, int L, int flags, double *U_out);
 
@@ -125,7 +131,9 @@ int tcm_mol_register_device(tcm_ctx *ctx, const double *d_x, const double *d_y,
                             const double *d_z, const double *d_q, int64_t n,
                             const double *centre, int precision, tcm_mol_id *id_out);
 
-/* Free the molecule's atoms (if uploaded) and resident moments. */
+/* Free the molecule's atoms (if uploaded) and resident moments.  TCM_EAGAIN while a live plan
+ * (tcm_plan_create) names the molecule: its launches address these buffers, so release it
+ * after tcm_plan_destroy. */
 int tcm_mol_release(tcm_ctx *ctx, tcm_mol_id id);
 
 /* Compute (or, with TCM_REUSE in flags, reuse) the molecule's order-L moments on the device
@@ -161,7 +169,10 @@ int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, dou
  * the context's stream and one forked stream (balanced by work) so that their workgroups
  * interleave.  Either way the run is asynchronous on the context's stream (outputs stay on
  * the device until tcm_plan_results), every moment the batch needs is recomputed (no
- * TCM_REUSE), and the results are identical bit for bit.  Destroy plans before their
+ * TCM_REUSE), and the results are identical bit for bit.  The moments a plan computes count as
+ * resident (for later TCM_REUSE calls on the same stream) once a run has been issued, at the
+ * plan's order; until then a reuse recomputes them.  A live plan pins the molecules it names
+ * (tcm_mol_release returns TCM_EAGAIN).  Destroy plans before their
  * context: their device memory is returned to its budget. */
 int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
                     tcm_plan **plan_out);
@@ -187,8 +198,9 @@ void tcm_plan_destroy(tcm_plan *plan);
 
 /* Energies of molecule B at nR positions relative to A (the scan of the paper's section IV,
  * in any directions), B keeping one orientation: quat_b (w, x, y, z), NULL = identity, as in
- * tcm_pair_req.  R: FP64 [nR][3], each c_B - c_A.  Eq. (9) with l1, l2 <= L regrouped by
- * L' = l1 + l2: the pair tensor G_{L'M} = sum over l1 + l2 = L', m1 + m2 = M of
+ * tcm_pair_req.  R: FP64 [nR][3], each c_B - c_A.  Eq. (9) with l1, l2 <= L (l1 + l2 <= L with
+ * TCM_TRIANGULAR in flags) regrouped by L' = l1 + l2: the pair tensor G_{L'M} = sum over
+ * l1 + l2 = L', m1 + m2 = M of
  * (-1)^{l2} Q^A_{l1 m1} Q^B_{l2 m2} (with the factorial normalisation) is built once from the
  * moments (computed, or reused with TCM_REUSE in flags), and each position then costs
  * O(L^2) instead of the O(L^4) of a full contraction.  U_out[nR], status_out[nR]:
@@ -205,7 +217,9 @@ int tcm_scan_translations(tcm_ctx *ctx, tcm_mol_id a, tcm_mol_id b, int L, const
 /* Adaptive truncation: each request's L is its maximum order; the pair is contracted at the
  * smallest order L' <= L whose rigorous truncation bound
  *   S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L'+1} + (beta/(1-alpha))^{L'+1}]
- * (alpha = a_A/R, beta = a_B/R, S = sum |q|; it bounds |eq. (1) - eq. (9) at L'|) is <= tol,
+ * (alpha = a_A/R, beta = a_B/R, S = sum |q|; it bounds |eq. (1) - eq. (9) at L'|; with
+ * TCM_TRIANGULAR in the request's flags the bound of that truncation,
+ * S_A S_B t^{L'+1} / (R (1 - t)), t = alpha + beta) is <= tol,
  * or at L when none is.  The moments are computed (or reused with TCM_REUSE) at L and stay
  * resident; sum |q| is computed once per molecule and cached with its moments.  U_out,
  * status_out: as tcm_batch_energy; L_out (may be NULL): the order used (-1 on error);
@@ -254,10 +268,21 @@ int tcm_all_pairs(tcm_ctx *ctx, const tcm_mol_id *ids, int64_t K, int L, int fla
  * assumes packed FP32, which this library does not use). */
 int tcm_alu_calibrate(tcm_ctx *ctx, int precision, double *tflops_out);
 
-/* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms. */
+/* Atoms per thread per tile used for (precision, L, n); the tile is 256 * kper atoms.  For
+ * TCM_F32C the value used is min(kper, the context's FP32 run cap, tcm_set_fp32_run).
+ * tcm_tune_set returns TCM_EAGAIN while a server runs (a fragment's tiling, and so every
+ * rounding of its moments, stays fixed while it is served). */
 int tcm_tune_get(tcm_ctx *ctx, int precision, int L, int64_t n, int *kper_out);
 int tcm_tune_set(tcm_ctx *ctx, int precision, int L, int64_t n, int kper);
-/* Autotuner: time the moment-tile kernels for every candidate kper (8..256, powers of two)
+/* Cap on the run of atoms one thread sums in plain FP32 in the TCM_F32C moment pass (its kper;
+ * every sum above that is compensated).  The cap is part of that path's error bound: each
+ * moment is within (8 (l+1) + 2 kmax + 64) 2^-24 of its absolute sum
+ * sum_i |q_i| |r_i^l sqrt(4 pi/(2l+1)) Y_lm| (eq. 8), and a shorter run lowers the typical error
+ * at the cost of more compensated merges.  1 <= kmax <= 1024; default 64.  The autotuners
+ * only try FP32 tilings within the cap.  TCM_EAGAIN while a server runs. */
+int tcm_set_fp32_run(tcm_ctx *ctx, int kmax);
+/* Autotuner: time the moment-tile kernels for every candidate kper (8..256, powers of two,
+ * FP32 within the run cap)
  * on a synthetic batch of copies of an n-atom molecule (at least 64M atoms, or 4096 copies)
  * so that every candidate runs many waves of items, and keep the fastest for (precision, L,
  * n's power-of-two size bucket).  best_ms_out (may be NULL): the winner's tile time per
@@ -280,13 +305,16 @@ int tcm_tune_load(tcm_ctx *ctx, const char *path);
 /* ---- serving ----------------------------------------------------------------------- */
 
 /* A served pair-energy request.  Fragments are named by caller-chosen keys.  A fragment the
- * server already holds (atoms and moments resident in its cache) is reused: its moments are
- * computed once per order and kept for later poses and partners.  A fragment that is not
- * resident must come with its atoms (FP64 structure of arrays x, y, z, q; device pointers,
- * or host pointers with TCM_HOST_ATOMS), which the server copies into memory it owns, so the
- * caller may reuse the arrays once the request completes (or, with TCM_BORROW_ATOMS,
- * references in place).  New fragments become resident under an LRU policy bounded by the
- * context's HBM budget; their moment tables live in fixed-size slots of a device arena. */
+ * server already holds (moments resident in its cache) is reused: its moments are computed
+ * once per order and kept for later poses and partners.  A fragment that is not resident must
+ * come with its atoms (FP64 structure of arrays x, y, z, q; device pointers, or host pointers
+ * with TCM_HOST_ATOMS), which the server copies into memory it owns, so the caller may reuse
+ * the arrays once the request completes (or, with TCM_BORROW_ATOMS, references in place).
+ * New fragments become resident under an LRU policy bounded by the context's HBM budget:
+ * under pressure the atoms of idle fragments are evicted first while their moment tables
+ * (fixed-size slots of a device arena, 8.7 KB each) stay, so a fragment is served at any order
+ * it already holds after its atoms are gone; a higher order then needs its atoms again (a
+ * request that names them; else TCM_ENOTFOUND). */
 #define TCM_HOST_ATOMS   4  /* request flag: atoms_a / atoms_b are host pointers (copied)    */
 #define TCM_BORROW_ATOMS 8  /* request flag: device atoms are referenced, not copied; they   */
                             /* must stay valid while the fragment is resident (until it is  */
@@ -331,12 +359,16 @@ int tcm_poll(tcm_ctx *ctx, uint64_t ticket, double *U_out, int32_t *status_out,
  * free the server's cache. */
 int tcm_server_stop(tcm_ctx *ctx);
 /* Counters since start: completed requests, launches, fragment cache hits / misses,
- * requests that had to wait at least once (memory, or a fragment still in flight), fragments
- * evicted.  A request is admitted with both of its fragments or waits without fetching
- * either, so every evicted fragment had been fetched by an admitted request
- * (evictions <= cache_misses). */
+ * requests that had to wait at least once (memory, or a fragment still in flight), atom
+ * evictions (a fragment's atoms freed to make room; its moment table stays resident, so the
+ * fragment is still served at any order up to the one it holds), fragments dropped whole
+ * (moment table included: the moment arena could not grow), and requests that failed with
+ * TCM_ENOTFOUND because they needed an order above the resident one of a fragment whose atoms
+ * had been evicted and did not bring them again.  A request is admitted with both of its
+ * fragments or waits without fetching either.  Any pointer may be NULL. */
 int tcm_server_stats(tcm_ctx *ctx, int64_t *completed, int64_t *launches, int64_t *cache_hits,
-                     int64_t *cache_misses, int64_t *deferred, int64_t *evictions);
+                     int64_t *cache_misses, int64_t *deferred, int64_t *evictions, int64_t *dropped,
+                     int64_t *evicted_misses);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,8 @@ struct DevPlan {
     double* part_d;                // FP64 path tile partials
     double* stats_part;            // STATS partials, 10 doubles per item
     double* r2_part;               // per-tile max |r|^2 (FP64)
+    double* prot;                  // pair launches: rotated moments [2][nh(pair_lmax)][npairs]
+    double* pum;                   // pair launches: per-m partial energies [pair_lmax+1][npairs]
     // outputs
     double* U;
     int32_t* status;
@@ -87,6 +89,7 @@ struct DevPlan {
     const double* invk;            // 1/k_lm of the normalised recurrence, per packed index
     const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
     const double* rot;             // rotation tables (D and D^{-1} per l, compressed by sparsity)
+    const double* fact;            // k!, k <= 2 LMAX + 1
 };
 
 // Packed index helpers (layout of every moment table at the boundary):

@@ -180,17 +180,10 @@ __device__ __forceinline__ void stats_finalize(const DevPlan& P, int mol, char* 
 }
 
 // ------------------------------------------------------------------ PAIR items
-// One pair per workgroup of PAIR_WG threads; the LDS layout is sized for the largest order Lm
-// of the launch's pairs.  The size is the same for every launch, so a pair's summation order --
-// and its energy, bit for bit -- does not depend on how many pairs share the launch.
-constexpr int PAIR_WG = 256;
-__host__ __device__ constexpr int ni(int Lm) { return (2 * Lm + 1) * (2 * Lm + 2) / 2; }
-
-__host__ __device__ constexpr size_t pair_smem_bytes(int Lm)
-{
-    // sA, sB, tA, tB [nh], spow [Lm+1], fac [2Lm+1], scsA, scsB [6(Lm+1)], qq [8], red [waves]
-    return sizeof(double) * (4 * (size_t)nh(Lm) + (Lm + 1) + (2 * Lm + 1) + 12 * (Lm + 1) + 8 + PAIR_WG / 64);
-}
+// The LDS layout of the pair kernels is sized for the largest order Lm of the launch's pairs;
+// a pair's summation order -- and its energy, bit for bit -- depends only on its own order, not
+// on Lm or on how many pairs share the launch.
+constexpr int PAIR_WG = 256;             // the force kernel and the scan tensor kernel
 
 __device__ void rot_phase(double* v, int L, const double* cs /*[Lm+1][2]*/)
 {
@@ -302,11 +295,13 @@ __device__ inline void rotate_moments(const double* rot, double* v, double* t, i
 }
 
 // rotate_moments on two tables at once (each with its own angles): every table row is loaded
-// once for both, and each table's arithmetic is exactly that of rotate_moments.
+// once for both, and each table's arithmetic is exactly that of rotate_moments.  NT threads
+// take part (a whole workgroup of NT threads).
+template <int NT>
 __device__ void rot_phase2(double* va, double* vb, int L, const double* ca, const double* cb)
 {
     const int NHl = nh(L);
-    for (int e = threadIdx.x; e < 2 * NHl; e += PAIR_WG) {
+    for (int e = threadIdx.x; e < 2 * NHl; e += NT) {
         const bool b = e >= NHl;
         const int h = b ? e - NHl : e;
         const int l = l_of(h), off = h - l * l;
@@ -322,11 +317,12 @@ __device__ void rot_phase2(double* va, double* vb, int L, const double* ca, cons
     }
 }
 
+template <int NT>
 __device__ void rot_matvec2(const double* tab, const double* ina, const double* inb, double* outa, double* outb,
                             int L, bool inverse)
 {
     const int NHl = nh(L);
-    for (int h = threadIdx.x; h < NHl; h += PAIR_WG) {
+    for (int h = threadIdx.x; h < NHl; h += NT) {
         const int l = l_of(h), i = h - l * l, n = 2 * l + 1, K = l / 2 + 1;
         int jb;
         const double* val;
@@ -355,18 +351,19 @@ __device__ void rot_matvec2(const double* tab, const double* ina, const double* 
     }
 }
 
+template <int NT>
 __device__ inline void rotate_moments2(const double* rot, double* va, double* vb, double* ta, double* tb, int L,
                                        int Lm, const double* ca, const double* cb)
 {
-    rot_phase2(va, vb, L, ca, cb);
+    rot_phase2<NT>(va, vb, L, ca, cb);
     __syncthreads();
-    rot_matvec2(rot, va, vb, ta, tb, L, false);
+    rot_matvec2<NT>(rot, va, vb, ta, tb, L, false);
     __syncthreads();
-    rot_phase2(ta, tb, L, ca + 2 * (Lm + 1), cb + 2 * (Lm + 1));
+    rot_phase2<NT>(ta, tb, L, ca + 2 * (Lm + 1), cb + 2 * (Lm + 1));
     __syncthreads();
-    rot_matvec2(rot, ta, tb, va, vb, L, true);
+    rot_matvec2<NT>(rot, ta, tb, va, vb, L, true);
     __syncthreads();
-    rot_phase2(va, vb, L, ca + 4 * (Lm + 1), cb + 4 * (Lm + 1));
+    rot_phase2<NT>(va, vb, L, ca + 4 * (Lm + 1), cb + 4 * (Lm + 1));
     __syncthreads();
 }
 
@@ -376,104 +373,299 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 // divided by f R^l,
 //     U = (1/R) sum_{l1, l2} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! sum_{m >= 0} w_m (-1)^m Re(a_{l1 m} conj(b_{l2 m}))
 // (w_0 = 1, w_m = 2; b_{l,-m} = (-1)^m conj(b_lm) folds m < 0 in): O(L^3) after two O(L^3)
-// rotations, the pose of B folded into its rotation.  The frame rotation is the quaternion
+// rotations, the pose of B folded into its rotation.  The square truncation keeps l1, l2 <= L;
+// the triangular one (TCM_TRIANGULAR) only l1 + l2 <= L.  The frame rotation is the quaternion
 // taking n = R/|R| to t = sign(n_z) z, (1 + n.t, n x t) normalised (1 + |n_z| >= 1, so it is
 // well conditioned for every direction).
-__device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* smem)
+//
+// The pair launches take the pairs G at a time (G = 64, one wavefront; 32 when the order
+// exceeds 24, to keep the LDS of a workgroup within 64 KB), one pair per lane: every loop index (order,
+// row, slot, m) is then the same in all lanes of a wavefront, the rotation tables are read once
+// per group into LDS and shared by its pairs, and the vector units do the arithmetic of G pairs
+// per instruction.  A group runs to the largest order of its pairs (the launch lists pairs by
+// decreasing order, so groups are nearly uniform); a lane whose pair has a lower order skips
+// what it does not need.
+//   tcm_pairs_rot    (group, l, side): the order-l block of one side's table rotated into the
+//                    frame where R lies along z (B's pose folded in), scaled by R^-l / f_lm,
+//                    written to the plan's scratch [side][h][pair];
+//   tcm_pairs_sum_m  (group, m): for each pair the m-term of the axial contraction;
+//   tcm_pairs_final  (pair): U = (sum over m in order) / R and the status (eq. 2 checked here).
+// Each pair's arithmetic is its own lane's, in a fixed order: a result does not depend on the
+// other pairs of the launch.
+constexpr int PAIR_LANES = 64;
+using cdptr = const __attribute__((address_space(4))) double*;
+
+// Largest order of the group's pairs (the launch lists pairs by decreasing order, but the
+// adaptive path lowers orders on the device after the listing).
+__device__ __forceinline__ int group_order(const DevPlan& P, int g0, int end)
 {
-    const PairWork& pw = P.pairs[p];
-    const int tid = threadIdx.x;
-    const int L = pw.L, NHl = nh(L);
+    const int G = blockDim.x;
+    int v = g0 + (int)threadIdx.x < end ? P.pairs[g0 + threadIdx.x].L : -1;
+    for (int off = G / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, G));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Per-lane geometry of a pair: 1/R, the sign of R_z, and the unit quaternion of the side's
+// rotation (side 0: the frame rotation taking R/|R| to +-z; side 1: the frame after B's pose).
+__device__ __forceinline__ void pair_frame(const PairWork& pw, int side, double& ir, double& sg, double q[4])
+{
     const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
     const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    ir = Rn > 0.0 ? 1.0 / Rn : 0.0;
+    const double nx = Rx * ir, ny = Ry * ir, nz = Rz * ir;
+    sg = nz < 0.0 ? -1.0 : 1.0;
+    double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx;
+    const double qn = sqrt(w * w + x * x + y * y);
+    w /= qn; x /= qn; y /= qn;
+    if (side == 1 && pw.has_rot) {           // frame (x) pose: the pose applied first
+        const double* p = pw.quat;
+        q[0] = w * p[0] - x * p[1] - y * p[2];
+        q[1] = w * p[1] + x * p[0] + y * p[3];
+        q[2] = w * p[2] - x * p[3] + y * p[0];
+        q[3] = w * p[3] + x * p[2] - y * p[1];
+    } else {
+        q[0] = w; q[1] = x; q[2] = y; q[3] = 0.0;
+    }
+}
+
+// e^{i gamma}, e^{i beta}, e^{i alpha} of the ZYZ Euler angles of the unit quaternion q
+// (R = Rz(alpha) Ry(beta) Rz(gamma)), without angles: with r1 = |(w, z)| and r2 = |(x, y)|,
+// e^{i a+} = (w + i z)/r1 and e^{i a-} = (y - i x)/r2 (either free, taken as 0, when its modulus
+// vanishes), gamma = a+ - a-, alpha = a+ + a-, e^{i beta} = (r1 + i r2)^2 / (r1^2 + r2^2).
+__device__ __forceinline__ void euler_bases(const double q[4], double e[3][2])
+{
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    const double r1 = sqrt(w * w + z * z), r2 = sqrt(x * x + y * y);
+    double pc = 1.0, ps = 0.0, mc = 1.0, ms = 0.0;
+    if (r1 > 0.0) { pc = w / r1; ps = z / r1; }
+    if (r2 > 0.0) { mc = y / r2; ms = -x / r2; }
+    const double rr = r1 * r1 + r2 * r2;
+    e[0][0] = pc * mc + ps * ms; e[0][1] = ps * mc - pc * ms;        // gamma
+    e[1][0] = (r1 * r1 - r2 * r2) / rr; e[1][1] = 2.0 * r1 * r2 / rr;  // beta
+    e[2][0] = pc * mc - ps * ms; e[2][1] = ps * mc + pc * ms;        // alpha
+}
+
+// One row of the order-l block of D (inverse: D^-1) applied to the LDS vectors v[j][lane]:
+// the row's code and values are wave-uniform (read from the block staged in LDS); the sum over
+// the K slots in the order of the tables (even and odd slots in two partial sums).
+__device__ __forceinline__ double rot_row_lanes(const double* blk, int n, int K, int i, bool inverse, const double* v,
+                                                int G)
+{
+    const int code = (int)blk[(inverse ? n : 0) + i];
+    const int jb = (code & 0xffff) - 1;
+    const double* val = blk + 2 * n + (inverse ? K * n : 0) + i;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+        const int j = min(n - 1, max(0, jb + 4 * k));
+        const double x = val[k * n] * v[j * G];
+        if (k & 1) s1 += x; else s0 += x;
+    }
+    return s0 + s1;
+}
+
+// LDS of the rotation launch: the two vectors of the group ([2l+1][G] each) and the order's
+// table block (2n codes and 2Kn values); the group size keeps it within 64 KB.
+__host__ __device__ constexpr int rot_block_len(int l) { return 2 * (2 * l + 1) * (l / 2 + 2); }
+__host__ __device__ constexpr int pair_group(int Lm) { return Lm <= 24 ? 64 : 32; }
+
+__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_rot(DevPlan P, int begin, int end)
+{
+    extern __shared__ __align__(16) double sv[];       // [2][2 pair_lmax + 1][G], table block
+    const int lane = threadIdx.x, G = blockDim.x;
+    const int g0 = begin + (int)blockIdx.x * G;
+    const int l = blockIdx.y, side = blockIdx.z;
+    if (l > group_order(P, g0, end)) return;             // beyond the group's largest order
+    const int p = min(g0 + lane, end - 1);
+    const PairWork& pw = P.pairs[p];
+    const bool act = g0 + lane < end && pw.L >= l;
+    const int n = 2 * l + 1, K = l / 2 + 1;
+    double* v0 = sv + lane;
+    double* v1 = sv + (size_t)(2 * P.pair_lmax + 1) * G + lane;
+    double* tb = sv + (size_t)2 * (2 * P.pair_lmax + 1) * G;
+    {   // the order's table block, and the order-l block of the side's moments scaled by R^-l
+        const double* src = P.rot + rot_block_offset(l);
+        const int nb = rot_block_len(l);
+        for (int k = lane; k < nb; k += G) tb[k] = src[k];
+    }
+    double ir, sg, q[4], e[3][2];
+    pair_frame(pw, side, ir, sg, q);
+    double sc = 1.0;
+    for (int k = 0; k < l; ++k) sc *= ir;                // R^-l by a chain of l products
+    {
+        const double* Q = (side ? pw.QB : pw.QA) + l * l;
+#pragma unroll 4
+        for (int j = 0; j < n; ++j) v0[j * G] = act ? Q[j] * sc : 0.0;
+    }
+    euler_bases(q, e);
+    // Z(gamma), in place: each lane its own entries, e^{i m gamma} by successive products
+    {
+        double c = 1.0, sn = 0.0;
+        for (int m = 1; m <= l; ++m) {
+            const double t = c * e[0][0] - sn * e[0][1];
+            sn = c * e[0][1] + sn * e[0][0];
+            c = t;
+            const double re = v0[(2 * m - 1) * G], im = v0[2 * m * G];
+            v0[(2 * m - 1) * G] = c * re - sn * im;
+            v0[2 * m * G] = sn * re + c * im;
+        }
+    }
+    __syncthreads();
+    // Z(beta) D
+    {
+        double c = 1.0, sn = 0.0;
+        v1[0] = rot_row_lanes(tb, n, K, 0, false, v0, G);
+        for (int m = 1; m <= l; ++m) {
+            const double t = c * e[1][0] - sn * e[1][1];
+            sn = c * e[1][1] + sn * e[1][0];
+            c = t;
+            const double re = rot_row_lanes(tb, n, K, 2 * m - 1, false, v0, G);
+            const double im = rot_row_lanes(tb, n, K, 2 * m, false, v0, G);
+            v1[(2 * m - 1) * G] = c * re - sn * im;
+            v1[2 * m * G] = sn * re + c * im;
+        }
+    }
+    __syncthreads();
+    // Z(alpha) D^-1, then 1/f_lm; out to the scratch [side][h][pair]
+    {
+        cdptr invf = (cdptr)P.invf + l * l;
+        double* out = P.prot + ((size_t)side * nh(P.pair_lmax) + l * l) * P.npairs + p;
+        const size_t st = P.npairs;
+        double c = 1.0, sn = 0.0;
+        const double r0 = rot_row_lanes(tb, n, K, 0, true, v1, G) * invf[0];
+        if (act) out[0] = r0;
+        for (int m = 1; m <= l; ++m) {
+            const double t = c * e[2][0] - sn * e[2][1];
+            sn = c * e[2][1] + sn * e[2][0];
+            c = t;
+            const double re = rot_row_lanes(tb, n, K, 2 * m - 1, true, v1, G);
+            const double im = rot_row_lanes(tb, n, K, 2 * m, true, v1, G);
+            const double f = invf[2 * m - 1];
+            if (act) {
+                out[(2 * m - 1) * st] = (c * re - sn * im) * f;
+                out[2 * m * st] = (sn * re + c * im) * f;
+            }
+        }
+    }
+}
+
+// In the frame where R lies along t = +-z (I_{L'0}(t) = (+-1)^{L'} L'!, every other M zero) and
+// with a, b the rotated moments divided by f R^l,
+//     U = (1/R) sum_m w_m (-1)^m sum_{l1, l2 >= m} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! Re(a_{l1 m} conj(b_{l2 m}))
+// (w_0 = 1, w_m = 2; square truncation l1, l2 <= L, triangular l1 + l2 <= L).  One workgroup
+// per (group, m): the columns a_{. m}, b_{. m} of the group's pairs and the factorials staged in
+// LDS first (all loads in flight together), then the double sum from LDS.
+__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_sum_m(DevPlan P, int begin, int end)
+{
+    extern __shared__ __align__(16) double sb[];       // fact [2 LMAX + 2], then A, B [pair_lmax + 1][2][G]
+    const int lane = threadIdx.x, G = blockDim.x;
+    const int g0 = begin + (int)blockIdx.x * G;
+    const int m = blockIdx.y;
+    const int gL = group_order(P, g0, end);
+    if (m > gL) return;
+    const int p = min(g0 + lane, end - 1);
+    const PairWork& pw = P.pairs[p];
+    const int Lp = pw.L;
+    const bool act = g0 + lane < end && Lp >= m;
+    const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
+    const double sg = pw.R[2] < 0.0 ? -1.0 : 1.0;
+    const size_t st = P.npairs;
+    double* fs = sb;
+    double* sa = sb + 2 * LMAX + 2;
+    double* sbb = sa + (size_t)2 * (P.pair_lmax + 1) * G;
+    for (int k = lane; k < 2 * LMAX + 2; k += G) fs[k] = P.fact[k];
+    // (-1)^{l2} (+-1)^{l1+l2} = (+-1)^{l1} (-+1)^{l2}: each column is staged with the sign of its
+    // order (sign changes only, no rounding)
+    {
+        const double* A = P.prot + p;
+        const double* B = P.prot + (size_t)nh(P.pair_lmax) * st + p;
+#pragma unroll 4
+        for (int l = m; l <= gL; ++l) {
+            const int h = m == 0 ? l * l : l * l + 2 * m - 1;
+            const bool ok = act && l <= Lp;
+            const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
+            const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
+            sa[(2 * l) * G + lane] = ok ? s1 * A[h * st] : 0.0;
+            sa[(2 * l + 1) * G + lane] = (ok && m > 0) ? s1 * A[(h + 1) * st] : 0.0;
+            sbb[(2 * l) * G + lane] = ok ? s2 * B[h * st] : 0.0;
+            sbb[(2 * l + 1) * G + lane] = (ok && m > 0) ? s2 * B[(h + 1) * st] : 0.0;
+        }
+    }
+    __syncthreads();
+    double Um = 0.0;
+    for (int l1 = m; l1 <= gL; ++l1) {
+        if (!(act && l1 <= Lp)) continue;
+        const double ar = sa[(2 * l1) * G + lane], ai = sa[(2 * l1 + 1) * G + lane];
+        const int l2hi = tri ? Lp - l1 : Lp;
+        double cr = 0.0, ci = 0.0;                        // sum_l2 (l1+l2)! conj(signed b_{l2 m})
+#pragma unroll 4
+        for (int l2 = m; l2 <= l2hi; ++l2) {
+            const double f = fs[l1 + l2];
+            cr += f * sbb[(2 * l2) * G + lane];
+            ci -= f * sbb[(2 * l2 + 1) * G + lane];
+        }
+        Um += ar * cr - ai * ci;
+    }
+    if (act) {
+        const double wt = m == 0 ? 1.0 : 2.0;
+        P.pum[(size_t)m * st + p] = (m & 1) ? -wt * Um : wt * Um;
+    }
+}
+
+// Adaptive truncation: per pair, the smallest order L' <= L whose rigorous bound of the
+// truncation error meets tol -- square S_A S_B / (R (1-a-b)) [(a/(1-b))^{L'+1} + (b/(1-a))^{L'+1}],
+// triangular S_A S_B t^{L'+1} / (R (1-t)), t = a + b, with a = a_A/R, b = a_B/R and S = sum |q|
+// (meta[5] of each molecule) -- by running products of the ratios (no power per order), L when
+// none does.  The pair's order in the plan is lowered to it; Lout[out] and bout[out] receive the
+// order and its bound (infinite outside the domain of eq. 2, where the pair keeps L).
+__global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int end, double tol, int32_t* Lout,
+                                                       double* bout)
+{
+    const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
+    if (p >= end) return;
+    PairWork& pw = const_cast<PairWork&>(P.pairs[p]);
+    const double R = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
+    const double al = pw.metaA[3] / R, be = pw.metaB[3] / R;
+    int L = pw.L;
+    double b = __builtin_inf();
+    if (al + be < 1.0) {
+        const double pre = pw.metaA[5] * pw.metaB[5] / (R * (1.0 - al - be));
+        const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
+        const double r1 = tri ? al + be : al / (1.0 - be), r2 = tri ? 0.0 : be / (1.0 - al);
+        double p1 = r1, p2 = r2;
+        for (int l = 0;; ++l, p1 *= r1, p2 *= r2) {
+            b = pre * (p1 + p2);
+            if (b <= tol || l == pw.L) {
+                L = l;
+                break;
+            }
+        }
+    }
+    pw.L = L;
+    Lout[pw.out] = L;
+    bout[pw.out] = b;
+}
+
+// U = (1/R) sum_{m = 0..L} (the m-terms, in order) and the status: eq. 2 (|R| > a_A + a_B,
+// strict) unless TCM_UNCHECKED; a zero R is invalid.
+__global__ __launch_bounds__(WG) void tcm_pairs_final(DevPlan P, int begin, int end)
+{
+    const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
+    if (p >= end) return;
+    const PairWork& pw = P.pairs[p];
+    const double Rn = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
     const double aA = pw.metaA[3], aB = pw.metaB[3];
     if (!(Rn > 0.0) || (!(pw.flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
-        if (tid == 0) {
-            P.status[pw.out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
-            P.U[pw.out] = __builtin_nan("");
-        }
+        P.status[pw.out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
+        P.U[pw.out] = __builtin_nan("");
         return;
     }
-    const int Lm = P.pair_lmax;
-    double* sA = reinterpret_cast<double*>(smem);
-    double* sB = sA + nh(Lm);
-    double* tA = sB + nh(Lm);                // rotation temporaries
-    double* tB = tA + nh(Lm);
-    double* spow = tB + nh(Lm);              // R^-l, l <= Lm
-    double* fac = spow + (Lm + 1);           // (+-1)^k k!, k <= 2Lm
-    double* scsA = fac + (2 * Lm + 1);       // [3][Lm+1][2] each
-    double* scsB = scsA + 6 * (Lm + 1);
-    double* qq = scsB + 6 * (Lm + 1);        // frame quaternion, then B's
-    double* red = qq + 8;
-    if (tid == 0) {
-        const double ir = 1.0 / Rn;
-        spow[0] = 1.0;
-        for (int l = 1; l <= L; ++l) spow[l] = spow[l - 1] * ir;
-        const double nx = Rx * ir, ny = Ry * ir, nz = Rz * ir, sg = nz < 0.0 ? -1.0 : 1.0;
-        double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx;
-        const double qn = sqrt(w * w + x * x + y * y);
-        w /= qn; x /= qn; y /= qn;
-        qq[0] = w; qq[1] = x; qq[2] = y; qq[3] = 0.0;
-        if (pw.has_rot) {                    // frame (x) pose: the pose applied first
-            const double* q = pw.quat;
-            qq[4] = w * q[0] - x * q[1] - y * q[2];
-            qq[5] = w * q[1] + x * q[0] + y * q[3];
-            qq[6] = w * q[2] - x * q[3] + y * q[0];
-            qq[7] = w * q[3] + x * q[2] - y * q[1];
-        } else {
-            qq[4] = w; qq[5] = x; qq[6] = y; qq[7] = 0.0;
-        }
-        fac[0] = 1.0;
-        for (int k = 1; k <= 2 * L; ++k) fac[k] = fac[k - 1] * (sg * k);
-    }
-    __syncthreads();
-    if (tid <= L) {
-        euler_phases(qq, tid, Lm, scsA);
-        euler_phases(qq + 4, tid, Lm, scsB);
-    }
-    for (int h = tid; h < NHl; h += PAIR_WG) {
-        const double sc = spow[l_of(h)];
-        sA[h] = pw.QA[h] * sc;
-        sB[h] = pw.QB[h] * sc;
-    }
-    __syncthreads();
-    rotate_moments2(P.rot, sA, sB, tA, tB, L, Lm, scsA, scsB);
-    for (int h = tid; h < NHl; h += PAIR_WG) {
-        sA[h] *= P.invf[h];
-        sB[h] *= P.invf[h];
-    }
-    __syncthreads();
-    // rows (m, l1 >= m), m-major
-    double Upart = 0.0;
-    const int nr = (L + 1) * (L + 2) / 2;
-    for (int r = tid; r < nr; r += PAIR_WG) {
-        int m = 0, k = r;
-        while (k >= L - m + 1) { k -= L - m + 1; ++m; }
-        const int l1 = m + k;
-        const double ar = m == 0 ? sA[l1 * l1] : sA[l1 * l1 + 2 * m - 1];
-        const double ai = m == 0 ? 0.0 : sA[l1 * l1 + 2 * m];
-        double cr = 0.0, ci = 0.0;           // sum_l2 (-1)^{l2} fac[l1+l2] conj(b_{l2 m})
-        for (int l2 = m; l2 <= L; ++l2) {
-            const double br = m == 0 ? sB[l2 * l2] : sB[l2 * l2 + 2 * m - 1];
-            const double bi = m == 0 ? 0.0 : sB[l2 * l2 + 2 * m];
-            const double f = (l2 & 1) ? -fac[l1 + l2] : fac[l1 + l2];
-            cr += f * br;
-            ci -= f * bi;
-        }
-        const double t = ar * cr - ai * ci;
-        const double wt = m == 0 ? 1.0 : 2.0;
-        Upart += (m & 1) ? -wt * t : wt * t;
-    }
-    Upart = wave_sum(Upart);                 // then the waves' sums in wave order
-    if ((tid & 63) == 0) red[tid >> 6] = Upart;
-    __syncthreads();
-    if (tid == 0) {
-        double u = 0.0;
-        for (int wv = 0; wv < PAIR_WG / 64; ++wv) u += red[wv];
-        P.U[pw.out] = u / Rn;
-        P.status[pw.out] = TCM_OK;
-    }
-    __syncthreads();
+    double u = 0.0;
+#pragma unroll 4
+    for (int m = 0; m <= pw.L; ++m) u += P.pum[(size_t)m * P.npairs + p];
+    P.U[pw.out] = u / Rn;
+    P.status[pw.out] = TCM_OK;
 }
 
 // ------------------------------------------------------------------ translation scan
@@ -491,14 +683,18 @@ __device__ __forceinline__ void pair_item_axial(const DevPlan& P, int p, char* s
 //     gamma_{L'M} = ((L'-1)^2 - M^2) / ((2L'-1)(2L'-3)),
 // so that U R = sum_M Re(conj(u^M) sum_{L'} p_{L'M} Gt_{L'M}) with Gt = w_M (2L'-1)!! G
 // (w_0 = 1, w_M = 2).  The table holds one row {Re Gt, Im Gt, gamma, 0} per (L', M),
-// column by column (M = 0 .. 2L, L' = M .. 2L): each position then costs five FP64
-// operations per row, the rows read with wave-uniform loads.  G costs O(L^4) once.
+// column by column (M = 0 .. Lt, L' = M .. Lt; Lt = 2L for the square truncation l1, l2 <= L,
+// Lt = L for the triangular one l1 + l2 <= L, whose terms are exactly those with L' <= L): each
+// position then costs five FP64 operations per row, the rows read with wave-uniform loads.
+// G costs O(L^4) once.
 
-__host__ __device__ constexpr int scan_col_start(int L, int M) { return M * (2 * L + 1) - M * (M - 1) / 2; }
+// first row of column M in a table over L' <= Lt
+__host__ __device__ constexpr int scan_col_start(int Lt, int M) { return M * (Lt + 1) - M * (M - 1) / 2; }
+__host__ __device__ constexpr int scan_rows(int Lt) { return (Lt + 1) * (Lt + 2) / 2; }
 
 // One wave per table row: lanes take the (l1, m1) terms of G_{L'M}, a butterfly sums them.
 // Every workgroup rotates and scales its own copy of the moment tables in LDS.
-__global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, const double* QB, int L, double rho,
+__global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, const double* QB, int L, int Lt, double rho,
                                                            const double* invf, const double* rot, int has_rot,
                                                            double q0, double q1, double q2, double q3, double* T)
 {
@@ -523,10 +719,10 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, con
     }
     __syncthreads();
     const int e = __builtin_amdgcn_readfirstlane(blockIdx.x * (PAIR_WG / 64) + tid / 64);
-    if (e >= ni(L)) return;
+    if (e >= scan_rows(Lt)) return;
     int M = 0;
-    while (scan_col_start(L, M + 1) <= e) ++M;
-    const int Lp = M + (e - scan_col_start(L, M));
+    while (M < Lt && scan_col_start(Lt, M + 1) <= e) ++M;
+    const int Lp = M + (e - scan_col_start(Lt, M));
     // a_{l m} for any m: m < 0 through a_{l,-m} = (-1)^m conj(a_lm)
     auto get = [&](const double* v, int l, int m, double& re, double& im) {
         const int am = m < 0 ? -m : m;
@@ -571,7 +767,7 @@ __global__ __launch_bounds__(PAIR_WG) void tcm_scan_tensor(const double* QA, con
 // that every table row loaded into SGPRs feeds SCAN_NP positions' arithmetic.
 constexpr int SCAN_NP = 2;
 
-__global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T, int L, double rho, double aA,
+__global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T, int Lt, double rho, double aA,
                                                     double aB, int unchecked, const double* __restrict__ R,
                                                     int64_t nR, double* __restrict__ U, int32_t* __restrict__ status)
 {
@@ -602,7 +798,7 @@ __global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T
         wr[j] = 1.0;                                     // u^M
         wi[j] = 0.0;
     }
-    const int L2 = 2 * L;
+    const int L2 = Lt;
     // the table is read-only here and the same for every lane: constant address space, so
     // that its loads are scalar loads into SGPRs
     using crow = const __attribute__((address_space(4))) double*;
@@ -660,21 +856,22 @@ __global__ __launch_bounds__(WG) void tcm_scan_eval(const double* __restrict__ T
     }
 }
 
-hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
-                       const double* invf, const double* rot, const double* quat, double* T, const double* R,
-                       int64_t nR, double* U, int32_t* status, hipStream_t s)
+hipError_t launch_scan(const double* QA, const double* QB, int L, int triangular, double rho, double aA, double aB,
+                       int unchecked, const double* invf, const double* rot, const double* quat, double* T,
+                       const double* R, int64_t nR, double* U, int32_t* status, hipStream_t s)
 {
     const int has_rot = quat && !(quat[0] > 0 && quat[1] == 0 && quat[2] == 0 && quat[3] == 0);
     const double q[4] = {quat ? quat[0] : 1.0, quat ? quat[1] : 0.0, quat ? quat[2] : 0.0, quat ? quat[3] : 0.0};
     const size_t tb = sizeof(double) * (3 * (size_t)nh(L) + 6 * (L + 1));
     const int waves = PAIR_WG / 64;
-    hipLaunchKernelGGL(tcm_scan_tensor, dim3((unsigned)((ni(L) + waves - 1) / waves)), dim3(PAIR_WG), tb, s, QA, QB,
-                       L, rho, invf, rot, has_rot, q[0], q[1], q[2], q[3], T);
+    const int Lt = triangular ? L : 2 * L;
+    hipLaunchKernelGGL(tcm_scan_tensor, dim3((unsigned)((scan_rows(Lt) + waves - 1) / waves)), dim3(PAIR_WG), tb, s,
+                       QA, QB, L, Lt, rho, invf, rot, has_rot, q[0], q[1], q[2], q[3], T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nR <= 0) return e;
     const int64_t blocks = (nR + WG * SCAN_NP - 1) / (WG * SCAN_NP);
-    hipLaunchKernelGGL(tcm_scan_eval, dim3((unsigned)blocks), dim3(WG), 0, s, T, L, rho, aA, aB, unchecked, R, nR, U,
-                       status);
+    hipLaunchKernelGGL(tcm_scan_eval, dim3((unsigned)blocks), dim3(WG), 0, s, T, Lt, rho, aA, aB, unchecked, R, nR,
+                       U, status);
     return hipGetLastError();
 }
 
@@ -829,7 +1026,7 @@ __device__ __forceinline__ void pair_ft_item(const DevPlan& P, int p, char* smem
         sB[h] = pw.QB[h] * sc;
     }
     __syncthreads();
-    rotate_moments2(P.rot, sA, sB, tA, tB, L, Lm, scsA, scsB);
+    rotate_moments2<PAIR_WG>(P.rot, sA, sB, tA, tB, L, Lm, scsA, scsB);
     for (int h = tid; h < NHl; h += PAIR_WG) {
         sA[h] *= P.invf[h];
         sB[h] *= P.invf[h];
@@ -1079,12 +1276,6 @@ __global__ __launch_bounds__(WG) void tcm_moments_finalize(DevPlan P)
     if ((int)blockIdx.x < P.nmol) finalize_moments(P, blockIdx.x, reinterpret_cast<char*>(smem));
 }
 
-__global__ __launch_bounds__(PAIR_WG) void tcm_pairs(DevPlan P, int begin, int end)
-{
-    extern __shared__ __align__(16) char smem[];         // pair_smem_bytes(P.pair_lmax)
-    const int item = begin + (int)blockIdx.x;
-    if (item < end) pair_item_axial(P, item, smem);
-}
 
 // Calibration of the vector ALU: 16 independent FMA chains per thread (a = a * b + c), so the
 // sustained rate of plain (non-packed) FMA instructions is measured without latency limits.
@@ -1234,10 +1425,31 @@ hipError_t launch_atom_forces(const double* atab, int side, int L, const double*
     return hipGetLastError();
 }
 
+// The pairs [begin, end) of the plan (listed by decreasing order): rotation, per-m terms,
+// final sums (three launches, ordered on s).
 hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
-    hipLaunchKernelGGL(tcm_pairs, dim3(end - begin), dim3(PAIR_WG), pair_smem_bytes(P.pair_lmax), s, P, begin, end);
+    const int Lm = P.pair_lmax;
+    const int G = pair_group(Lm);
+    const unsigned groups = (unsigned)((end - begin + G - 1) / G);
+    const size_t rot_lds = sizeof(double) * (2 * (2 * (size_t)Lm + 1) * G + rot_block_len(Lm));
+    const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + 4 * ((size_t)Lm + 1) * G);
+    hipLaunchKernelGGL(tcm_pairs_rot, dim3(groups, Lm + 1, 2), dim3(G), rot_lds, s, P, begin, end);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(G), sum_lds, s, P, begin, end);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol, int32_t* Lout, double* bout,
+                               hipStream_t s)
+{
+    if (end <= begin) return hipSuccess;
+    hipLaunchKernelGGL(tcm_pairs_choose, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end,
+                       tol, Lout, bout);
     return hipGetLastError();
 }
 

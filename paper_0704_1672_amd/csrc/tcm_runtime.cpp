@@ -99,14 +99,22 @@ int64_t tune_key(int prec, int L, int64_t n) { return (int64_t)prec * 100000 + L
 
 // Atoms per thread per tile.  A function of (precision, L, n) only, so a molecule's tiling --
 // and therefore every rounding of its moments -- is the same whatever else shares a launch.
+// In the FP32 path a thread sums its kper atoms in plain FP32 (everything above is merged with
+// TwoSum), so kper is part of that path's error bound, (8(l+1) + 2 kper + 64) 2^-24 times the
+// absolute sum of a moment: it never exceeds the context's cap f32_run_max.
 int Ctx::kper_for(int prec, int L, int64_t n)
 {
+    int k;
     auto it = tune.find(tune_key(prec, L, n));
-    if (it != tune.end()) return it->second;
-    // default: aim at ~16 tiles per molecule, 4 <= kper <= 64, powers of two
-    int64_t want = n / (WG * 16);
-    int k = 4;
-    while (k < 64 && k < want) k <<= 1;
+    if (it != tune.end()) {
+        k = it->second;
+    } else {
+        // default: aim at ~16 tiles per molecule, 4 <= kper <= 64, powers of two
+        int64_t want = n / (WG * 16);
+        k = 4;
+        while (k < 64 && k < want) k <<= 1;
+    }
+    if (prec == TCM_F32C && k > f32_run_max) k = f32_run_max;
     return k;
 }
 
@@ -334,15 +342,20 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
         off_r2 += nt;
     }
     const size_t nmol = mols.size(), np = pairs.size();
+    int plmax = 0;
+    for (const PairJob& j : pairs) plmax = std::max(plmax, j.L);
     const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (size_t)off_s +
                         2 * sizeof(int32_t) * (size_t)nitems + 1024;
-    const size_t need[8] = {blob, sizeof(int32_t),
-                            sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
-                            sizeof(double) * 10 * (size_t)(off_s > 0 ? off_s : 1), sizeof(double) * (size_t)(off_r2 > 0 ? off_r2 : 1),
-                            sizeof(double) * (np > 0 ? np : 1), sizeof(int32_t) * (np > 0 ? np : 1)};
-    const DevBuf* have[8] = {&ws.blob, &ws.sync, &ws.part_f, &ws.part_d, &ws.stats, &ws.r2, &ws.outU, &ws.outS};
+    const size_t np1 = np > 0 ? np : 1;
+    const size_t need[10] = {blob, sizeof(int32_t),
+                             sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
+                             sizeof(double) * 10 * (size_t)(off_s > 0 ? off_s : 1), sizeof(double) * (size_t)(off_r2 > 0 ? off_r2 : 1),
+                             sizeof(double) * np1, sizeof(int32_t) * np1,
+                             sizeof(double) * 2 * (size_t)nh(plmax) * np1, sizeof(double) * (size_t)(plmax + 1) * np1};
+    const DevBuf* have[10] = {&ws.blob, &ws.sync, &ws.part_f, &ws.part_d, &ws.stats, &ws.r2, &ws.outU, &ws.outS,
+                              &ws.prot, &ws.pum};
     size_t grow = 0;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 10; ++i) {
         const size_t want = need[i] < 256 ? 256 : need[i];
         if (want > have[i]->cap) grow += want;
     }
@@ -531,6 +544,9 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     if ((rc = c->alloc(ws.r2, sizeof(double) * (off_r2 > 0 ? off_r2 : 1))) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.outU, sizeof(double) * (npairs > 0 ? npairs : 1))) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.outS, sizeof(int32_t) * (npairs > 0 ? npairs : 1))) != TCM_OK) return rc;
+    const size_t np1 = npairs > 0 ? (size_t)npairs : 1;
+    if ((rc = c->alloc(ws.prot, sizeof(double) * 2 * (size_t)nh(pair_lmax) * np1)) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.pum, sizeof(double) * (size_t)(pair_lmax + 1) * np1)) != TCM_OK) return rc;
     if (hipMemcpyAsync(ws.blob.p, ws.hstage, blob, hipMemcpyHostToDevice, s) != hipSuccess) return TCM_EDEVICE;
     char* d = (char*)ws.blob.p;
     DevPlan& P = bp.P;
@@ -553,6 +569,9 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.invk = (const double*)c->t_invk.p;
     P.invf = (const double*)c->t_invf.p;
     P.rot = (const double*)c->t_rot.p;
+    P.fact = (const double*)c->t_fact.p;
+    P.prot = (double*)ws.prot.p;
+    P.pum = (double*)ws.pum.p;
     bp.n_stats = P.n_stats;
     bp.n_tiles = P.n_tiles;
     bp.npairs = npairs;
@@ -563,9 +582,9 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     return TCM_OK;
 }
 
-static int ensure_aux(Workspace& ws)
+static int ensure_aux(Workspace& ws, size_t ngroups)
 {
-    for (int k = 0; k < NLANES - 1; ++k) {
+    for (int k = 0; k < NLANES; ++k) {
         if (!ws.aux[k] && hipStreamCreateWithFlags(&ws.aux[k], hipStreamNonBlocking) != hipSuccess) {
             ws.aux[k] = nullptr;
             return TCM_EDEVICE;
@@ -579,12 +598,17 @@ static int ensure_aux(Workspace& ws)
         ws.fork = nullptr;
         return TCM_EDEVICE;
     }
+    while (ws.gev.size() < ngroups) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TCM_EDEVICE;
+        ws.gev.push_back(e);
+    }
     return TCM_OK;
 }
 
 static void destroy_streams(Workspace& ws)
 {
-    for (int k = 0; k < NLANES - 1; ++k) {
+    for (int k = 0; k < NLANES; ++k) {
         if (ws.aux[k]) (void)hipStreamDestroy(ws.aux[k]);
         ws.aux[k] = nullptr;
         if (ws.join[k]) (void)hipEventDestroy(ws.join[k]);
@@ -592,21 +616,24 @@ static void destroy_streams(Workspace& ws)
     }
     if (ws.fork) (void)hipEventDestroy(ws.fork);
     ws.fork = nullptr;
+    for (hipEvent_t e : ws.gev) (void)hipEventDestroy(e);
+    ws.gev.clear();
 }
 
-// Issue the launches of one run (every kernel has one workgroup per item).  Both orders start
-// with one statistics launch over every molecule of the batch and one centre/scale launch,
-// and end with the moment finalisation and the pair launch on s.
-//   serial (serial = true): the tile launch of each (precision, L) group in turn on s (the
+// Issue the launches of one run (every kernel has one workgroup per item); the moment
+// finalisation and the pair launch end it on s.
+//   serial (serial = true): one statistics launch over every molecule of the batch, one
+//     centre/scale launch, the tile launch of each (precision, L) group in turn on s (the
 //     order a captured graph replays); with ev (5 events) the elapsed time of each step is
 //     measured on the launch stream.
-//   lanes (serial = false): the groups' tile launches are spread over s and NLANES - 1 more
-//     streams, balanced by work (largest first, each to the lightest lane), each lane issuing
-//     its smallest launch first.  The workgroups of
-//     the two lanes' launches interleave as slots free up, so a small group's items fill the
-//     tail of a large one instead of running alone on a half-empty device.  Two streams, not
-//     one per group: the process's streams share four hardware queues, and with one stream
-//     per group some groups queued behind others.
+//   lanes (serial = false): the groups' tile launches are spread over NLANES streams forked
+//     from s, balanced by work (largest first, each to the lightest lane), each lane issuing
+//     its smallest launch first, so that the two lanes' workgroups interleave as slots free up
+//     and a small group's items fill the tail of a large one.  The statistics (HBM bound) and
+//     centre/scale of each group run on s, group by group in the order the lanes start them,
+//     and a tile launch waits only for its own group's: the statistics of later groups run
+//     beside the ALU-bound tiles of earlier ones.  (The process's streams share four hardware
+//     queues: s and two lanes, not one stream per group.)
 int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t* ev, bool energy)
 {
     (void)c;
@@ -617,20 +644,13 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
         const BuiltPlan::Group& G = bp.groups[g];
         return launch_tiles(G.prec, G.L, bp.P, S + G.begin, S + G.end, st) == hipSuccess;
     };
-    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_stats(bp.P, 0, S, s) != hipSuccess) return TCM_EDEVICE;
-    if (launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) return TCM_EDEVICE;
-    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
-    if (!serial && ng > 1 && bp.ws && ensure_aux(*bp.ws) == TCM_OK) {
+    if (!serial && ng > 1 && bp.ws && ensure_aux(*bp.ws, (size_t)ng) == TCM_OK) {
         Workspace& ws = *bp.ws;
         std::vector<int> order(ng);
         for (int g = 0; g < ng; ++g) order[g] = g;
         std::stable_sort(order.begin(), order.end(),
                          [&](int u, int v) { return bp.groups[u].work > bp.groups[v].work; });
         const int nl = ng < NLANES ? ng : NLANES;
-        if (hipEventRecord(ws.fork, s) != hipSuccess) return TCM_EDEVICE;
-        for (int k = 0; k < nl - 1; ++k)
-            if (hipStreamWaitEvent(ws.aux[k], ws.fork, 0) != hipSuccess) return TCM_EDEVICE;
         double load[NLANES] = {};
         std::vector<int> lanes[NLANES];
         for (int g : order) {
@@ -640,17 +660,41 @@ int run_plan(Ctx* c, const BuiltPlan& bp, hipStream_t s, bool serial, hipEvent_t
             load[lane] += bp.groups[g].work;
             lanes[lane].push_back(g);
         }
-        // within a lane the smallest launch first: the small groups run beside the start of
-        // the large ones, and every lane ends in a large launch whose own cheapest items fill
-        // the tail
+        // each lane's launches smallest first; the statistics in the order the lanes start them
+        std::vector<int> stats_order;
+        for (size_t r = 0;; ++r) {
+            bool any = false;
+            for (int k = 0; k < nl; ++k)
+                if (r < lanes[k].size()) {
+                    stats_order.push_back(lanes[k][lanes[k].size() - 1 - r]);
+                    any = true;
+                }
+            if (!any) break;
+        }
+        if (hipEventRecord(ws.fork, s) != hipSuccess) return TCM_EDEVICE;
         for (int k = 0; k < nl; ++k)
-            for (auto it = lanes[k].rbegin(); it != lanes[k].rend(); ++it)
-                if (!group_tiles(*it, k ? ws.aux[k - 1] : s)) return TCM_EDEVICE;
-        for (int k = 0; k < nl - 1; ++k) {
+            if (hipStreamWaitEvent(ws.aux[k], ws.fork, 0) != hipSuccess) return TCM_EDEVICE;
+        for (int g : stats_order) {
+            const BuiltPlan::Group& G = bp.groups[g];
+            if (launch_stats(bp.P, G.stats_begin, G.stats_end, s) != hipSuccess ||
+                launch_stats_finalize(bp.P, G.mol_begin, G.mol_end, s) != hipSuccess ||
+                hipEventRecord(ws.gev[g], s) != hipSuccess)
+                return TCM_EDEVICE;
+        }
+        for (int k = 0; k < nl; ++k)
+            for (auto it = lanes[k].rbegin(); it != lanes[k].rend(); ++it) {
+                if (hipStreamWaitEvent(ws.aux[k], ws.gev[*it], 0) != hipSuccess) return TCM_EDEVICE;
+                if (!group_tiles(*it, ws.aux[k])) return TCM_EDEVICE;
+            }
+        for (int k = 0; k < nl; ++k) {
             if (hipEventRecord(ws.join[k], ws.aux[k]) != hipSuccess) return TCM_EDEVICE;
             if (hipStreamWaitEvent(s, ws.join[k], 0) != hipSuccess) return TCM_EDEVICE;
         }
     } else {
+        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return TCM_EDEVICE;
+        if (launch_stats(bp.P, 0, S, s) != hipSuccess) return TCM_EDEVICE;
+        if (launch_stats_finalize(bp.P, 0, bp.P.nmol, s) != hipSuccess) return TCM_EDEVICE;
+        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return TCM_EDEVICE;
         for (int g = 0; g < ng; ++g)
             if (!group_tiles(g, s)) return TCM_EDEVICE;
     }
@@ -676,6 +720,7 @@ void free_workspace(Ctx* c, Workspace& ws)
     destroy_streams(ws);
     c->release(ws.blob); c->release(ws.sync); c->release(ws.part_f); c->release(ws.part_d);
     c->release(ws.stats); c->release(ws.r2); c->release(ws.outU); c->release(ws.outS);
+    c->release(ws.prot); c->release(ws.pum);
     if (ws.hstage) (void)hipHostFree(ws.hstage);
     ws.hstage = nullptr;
     ws.hstage_cap = 0;
@@ -741,15 +786,25 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
         tcm_destroy(t);
         return TCM_EDEVICE;
     }
+    std::vector<double> fact(2 * LMAX + 2);  // k! (long double products, rounded once)
+    {
+        long double f = 1.0L;
+        for (int k = 0; k < (int)fact.size(); ++k) {
+            if (k > 0) f *= (long double)k;
+            fact[k] = (double)f;
+        }
+    }
     int rc;
     if ((rc = c.alloc(c.t_invk, invk.size() * sizeof(double))) != TCM_OK ||
         (rc = c.alloc(c.t_invf, invf.size() * sizeof(double))) != TCM_OK ||
-        (rc = c.alloc(c.t_rot, rot.size() * sizeof(double))) != TCM_OK) {
+        (rc = c.alloc(c.t_rot, rot.size() * sizeof(double))) != TCM_OK ||
+        (rc = c.alloc(c.t_fact, fact.size() * sizeof(double))) != TCM_OK) {
         tcm_destroy(t);
         return rc;
     }
     if (hipMemcpy(c.t_invk.p, invk.data(), invk.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.t_invf.p, invf.data(), invf.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.t_fact.p, fact.data(), fact.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.t_rot.p, rot.data(), rot.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         tcm_destroy(t);
         return TCM_EDEVICE;
@@ -778,11 +833,12 @@ extern "C" void tcm_destroy(tcm_ctx* t)
     c.release(c.tmp_q);
     c.release(c.scan_g); c.release(c.scan_r); c.release(c.scan_u); c.release(c.scan_s);
     c.release(c.force_ft); c.release(c.force_w); c.release(c.force_t); c.release(c.force_a); c.release(c.force_b);
-    c.release(c.absq);
+    c.release(c.adapt);
     c.release(c.gather);
     c.release(c.t_invk);
     c.release(c.t_invf);
     c.release(c.t_rot);
+    c.release(c.t_fact);
     if (c.hpin) (void)hipHostFree(c.hpin);
     if (c.own_stream) (void)hipStreamDestroy(c.own_stream);
     delete t;
@@ -1005,6 +1061,7 @@ extern "C" int tcm_mol_release(tcm_ctx* t, tcm_mol_id id)
     std::lock_guard<std::mutex> g(c.mu);
     auto it = c.mols.find(id);
     if (it == c.mols.end()) return TCM_ENOTFOUND;
+    if (it->second->plan_refs > 0) return TCM_EAGAIN;      // a live plan still reads or writes it
     (void)hipStreamSynchronize(c.stream);
     c.release(it->second->atoms);
     c.release(it->second->moments);
@@ -1083,7 +1140,6 @@ int plan_requests(Ctx& c, const tcm_pair_req* reqs, int64_t np, bool allow_reuse
         rp.computed.push_back({m, L});
         m->Lcached = -1;                      // invalid until this run completes
         m->radius_host = -1.0;
-        m->absq_host = -1.0;
     }
     if (rc == TCM_OK) {
         rp.pj.reserve(np);
@@ -1122,7 +1178,6 @@ void mark_computed(ReqPlan& rp)
     for (auto& pr : rp.computed) {
         pr.first->Lcached = pr.second;
         pr.first->radius_host = -1.0;
-        pr.first->absq_host = -1.0;
     }
 }
 }  // namespace tcm
@@ -1154,7 +1209,6 @@ extern "C" int tcm_mol_moments(tcm_ctx* t, tcm_mol_id id, int L, int flags, doub
         j.meta = (double*)m->meta.p;
         m->Lcached = -1;
         m->radius_host = -1.0;
-        m->absq_host = -1.0;
         BuiltPlan bp;
         if ((rc = build_plan(&c, c.ws, {j}, {}, bp, s)) != TCM_OK) return rc;
         if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
@@ -1286,7 +1340,7 @@ extern "C" int tcm_all_pairs(tcm_ctx* t, const tcm_mol_id* ids, int64_t K, int L
             for (int d = 0; d < 3; ++d) r.R[d] = meta[(size_t)j * 8 + d] - meta[(size_t)i * 8 + d];
             r.quat_b[0] = 1.0;
             r.L = L;
-            r.flags = (flags & TCM_UNCHECKED) | TCM_REUSE;
+            r.flags = (flags & (TCM_UNCHECKED | TCM_TRIANGULAR)) | TCM_REUSE;
         }
     return batch_energy_locked(c, reqs.data(), np, U_out, status_out);
 }
@@ -1317,8 +1371,14 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
         delete pl;
         return TCM_EDEVICE;
     }
-    // moments become valid after the first run; mark now so later batches may reuse them
-    mark_computed(rp);
+    // the moments become valid when a run is issued (tcm_plan_run marks them then); until the
+    // plan is destroyed its molecules are pinned, so the buffers its launches address stay
+    pl->computed = rp.computed;
+    for (size_t k = 0; k < rp.side.size(); ++k) {
+        Mol* m = rp.side[k];
+        if (m && std::find(pl->refs.begin(), pl->refs.end(), m) == pl->refs.end()) pl->refs.push_back(m);
+    }
+    for (Mol* m : pl->refs) ++m->plan_refs;
     pl->npairs = (int)np;
     if (use_graph) {
         hipStream_t cs = nullptr;
@@ -1340,7 +1400,13 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
         if (cs) (void)hipStreamDestroy(cs);
         if (!ok) {
             (void)hipGetLastError();
-            tcm_plan_destroy(pl);
+            for (Mol* m : pl->refs) --m->plan_refs;      // the context lock is held here
+            pl->refs.clear();
+            pl->ctx = nullptr;
+            if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+            if (pl->graph) (void)hipGraphDestroy(pl->graph);
+            free_workspace(&c, pl->ws);
+            delete pl;
             return TCM_EDEVICE;
         }
     }
@@ -1348,25 +1414,41 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
     return TCM_OK;
 }
 
+// A run issued on the context's stream: the moments it writes count as resident from here on
+// (later work on that stream is ordered behind it), at exactly the plan's order.
+static void plan_issued(Ctx& c, tcm_plan* pl)
+{
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto& pr : pl->computed) {
+        pr.first->Lcached = pr.second;
+        pr.first->radius_host = -1.0;
+    }
+}
+
 extern "C" int tcm_plan_run(tcm_ctx* t, tcm_plan* pl)
 {
-    if (!t || !pl) return TCM_EINVAL;
+    if (!t || !pl || pl->ctx != &t->c) return TCM_EINVAL;
     Ctx& c = t->c;
     (void)hipSetDevice(c.device);
-    if (pl->exec) return hipGraphLaunch(pl->exec, c.stream) == hipSuccess ? TCM_OK : TCM_EDEVICE;
-    return run_plan(&c, pl->bp, c.stream, false, nullptr);
+    int rc;
+    if (pl->exec) rc = hipGraphLaunch(pl->exec, c.stream) == hipSuccess ? TCM_OK : TCM_EDEVICE;
+    else rc = run_plan(&c, pl->bp, c.stream, false, nullptr);
+    if (rc == TCM_OK) plan_issued(c, pl);
+    return rc;
 }
 
 extern "C" int tcm_plan_run_phased(tcm_ctx* t, tcm_plan* pl)
 {
-    if (!t || !pl) return TCM_EINVAL;
+    if (!t || !pl || pl->ctx != &t->c) return TCM_EINVAL;
     (void)hipSetDevice(t->c.device);
-    return run_plan(&t->c, pl->bp, t->c.stream, true, nullptr);
+    const int rc = run_plan(&t->c, pl->bp, t->c.stream, true, nullptr);
+    if (rc == TCM_OK) plan_issued(t->c, pl);
+    return rc;
 }
 
 extern "C" int tcm_plan_run_timed(tcm_ctx* t, tcm_plan* pl, double* ms_out)
 {
-    if (!t || !pl || !ms_out) return TCM_EINVAL;
+    if (!t || !pl || !ms_out || pl->ctx != &t->c) return TCM_EINVAL;
     Ctx& c = t->c;
     (void)hipSetDevice(c.device);
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -1374,6 +1456,7 @@ extern "C" int tcm_plan_run_timed(tcm_ctx* t, tcm_plan* pl, double* ms_out)
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
     if (rc == TCM_OK) rc = run_plan(&c, pl->bp, c.stream, true, ev);
+    if (rc == TCM_OK) plan_issued(c, pl);
     if (rc == TCM_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = TCM_EDEVICE;
     for (int k = 0; rc == TCM_OK && k < 4; ++k) {
         float ms = 0;
@@ -1420,6 +1503,11 @@ extern "C" int tcm_plan_info(tcm_plan* pl, int64_t* atoms, double* flops, int64_
 extern "C" void tcm_plan_destroy(tcm_plan* pl)
 {
     if (!pl) return;
+    if (pl->ctx) {                           // its launches may still run: let them finish
+        std::lock_guard<std::mutex> g(pl->ctx->mu);
+        (void)hipStreamSynchronize(pl->ctx->stream);
+        for (Mol* m : pl->refs) --m->plan_refs;
+    }
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     // the plan's buffers were charged to the context that created it (plans are destroyed
@@ -1441,7 +1529,17 @@ extern "C" int tcm_tune_set(tcm_ctx* t, int prec, int L, int64_t n, int k)
 {
     if (!t || L < 0 || L > LMAX || n < 0 || k < 1 || k > 1024) return TCM_EINVAL;
     std::lock_guard<std::mutex> g(t->c.mu);
+    if (t->c.server) return TCM_EAGAIN;      // tilings are fixed while a server runs
     t->c.tune[tune_key(prec, L, n)] = k;
+    return TCM_OK;
+}
+
+extern "C" int tcm_set_fp32_run(tcm_ctx* t, int kmax)
+{
+    if (!t || kmax < 1 || kmax > 1024) return TCM_EINVAL;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    if (t->c.server) return TCM_EAGAIN;
+    t->c.f32_run_max = kmax;
     return TCM_OK;
 }
 
@@ -1462,6 +1560,11 @@ extern "C" int tcm_tune_load(tcm_ctx* t, const char* path)
     if (!t || !path) return TCM_EINVAL;
     FILE* f = std::fopen(path, "r");
     if (!f) return TCM_ENOTFOUND;
+    std::lock_guard<std::mutex> g(t->c.mu);
+    if (t->c.server) {
+        std::fclose(f);
+        return TCM_EAGAIN;                   // tilings are fixed while a server runs
+    }
     char line[256];
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
@@ -1524,7 +1627,9 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
     }
     const double aA = ma->radius_host, aB = mb->radius_host;
     const double rho = aA + aB > 0.0 ? aA + aB : 1.0;
-    const int64_t NG = (2 * (int64_t)L + 1) * (2 * L + 2) / 2;
+    const bool tri = (flags & TCM_TRIANGULAR) != 0;
+    const int64_t Lt = tri ? L : 2 * (int64_t)L;                 // largest total order L' = l1 + l2
+    const int64_t NG = (Lt + 1) * (Lt + 2) / 2;
     if ((rc = c.alloc(c.scan_g, sizeof(double) * 4 * NG)) != TCM_OK) return rc;   // table rows of 4 doubles
     const double* dR = R;
     double* dU = U_out;
@@ -1540,7 +1645,7 @@ extern "C" int tcm_scan_translations(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, int
         dU = (double*)c.scan_u.p;
         dS = (int32_t*)c.scan_s.p;
     }
-    if (launch_scan((const double*)ma->moments.p, (const double*)mb->moments.p, L, rho, aA, aB,
+    if (launch_scan((const double*)ma->moments.p, (const double*)mb->moments.p, L, tri ? 1 : 0, rho, aA, aB,
                     (flags & TCM_UNCHECKED) ? 1 : 0, (const double*)c.t_invf.p, (const double*)c.t_rot.p, quat_b,
                     (double*)c.scan_g.p, dR, nR, dU, dS, s) != hipSuccess)
         return TCM_EDEVICE;
@@ -1600,81 +1705,61 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
     std::lock_guard<std::mutex> g(c.mu);
     (void)hipSetDevice(c.device);
     hipStream_t s = c.stream;
-    // 1. moments at each request's maximum order
+    // one plan at each request's maximum order; every step on the device, one read-back:
+    // moments (computed or reused), sum |q| of molecules that lack it (meta[5], once per
+    // molecule), the order choice lowering each pair's order in the plan, the contractions
     ReqPlan rp;
     int rc = plan_requests(c, reqs, np, true, rp);
     if (rc != TCM_OK) return rc;
-    if (!rp.mj.empty()) {
-        BuiltPlan bp;
-        if ((rc = build_plan(&c, c.ws, rp.mj, {}, bp, s)) != TCM_OK) return rc;
-        if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
-        if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
-        mark_computed(rp);
-        rp.mj.clear();                       // resident from here on: the pair jobs depend on none
-        rp.computed.clear();
-        for (PairJob& j : rp.pj) j.depA = j.depB = -1;
-    }
-    // 2. radius and sum |q| of every molecule involved (read once per computation)
+    BuiltPlan bp;
+    if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
+    const int npj = (int)rp.pj.size();
+    if ((rc = c.alloc(c.adapt, (sizeof(double) + sizeof(int32_t)) * (size_t)(npj > 0 ? npj : 1))) != TCM_OK) return rc;
+    double* dB = (double*)c.adapt.p;
+    int32_t* dL = (int32_t*)(dB + (npj > 0 ? npj : 1));
+    if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;
     std::vector<Mol*> need;
     for (int64_t i = 0; i < np; ++i) {
         if (rp.pre_status[i] != TCM_OK) continue;
         for (Mol* m : {rp.side[2 * i], rp.side[2 * i + 1]})
-            if (m->radius_host < 0.0 || m->absq_host < 0.0) need.push_back(m);
-    }
-    std::sort(need.begin(), need.end(), [](const Mol* u, const Mol* v) { return u->id < v->id; });
-    need.erase(std::unique(need.begin(), need.end()), need.end());
-    if (!need.empty()) {
-        if ((rc = c.alloc(c.absq, sizeof(double) * need.size())) != TCM_OK) return rc;
-        std::vector<double> meta(need.size() * 8), sq(need.size());
-        for (size_t k = 0; k < need.size(); ++k) {
-            if (launch_abs_sum(need[k]->q, need[k]->n, (double*)c.absq.p + k, s) != hipSuccess ||
-                hipMemcpyAsync(&meta[8 * k], need[k]->meta.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
-                return TCM_EDEVICE;
-        }
-        if (hipMemcpyAsync(sq.data(), c.absq.p, sizeof(double) * need.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return TCM_EDEVICE;
-        for (size_t k = 0; k < need.size(); ++k) {
-            need[k]->radius_host = meta[8 * k + 3];
-            need[k]->absq_host = sq[k];
-        }
-    }
-    // 3. per pair, the smallest order whose bound meets tol (the maximum if none does), set
-    //    in the planned pair jobs, which then run against the resident moments
-    std::vector<int32_t> Lch((size_t)np, -1);
-    std::vector<double> bnd((size_t)np, std::nan(""));
-    for (size_t k = 0; k < rp.pj.size(); ++k) {
-        const int64_t i = rp.pj_req[k];
-        const Mol* ma = rp.side[2 * i];
-        const Mol* mb = rp.side[2 * i + 1];
-        const double R = std::sqrt(reqs[i].R[0] * reqs[i].R[0] + reqs[i].R[1] * reqs[i].R[1] + reqs[i].R[2] * reqs[i].R[2]);
-        // the bound at l = 0, 1, ... by running products of the two ratios (no pow per order)
-        int L = reqs[i].L;
-        double b = INFINITY;
-        const double al = ma->radius_host / R, be = mb->radius_host / R;
-        if (al + be < 1.0) {
-            const double pre = ma->absq_host * mb->absq_host / (R * (1.0 - al - be));
-            const double r1 = al / (1.0 - be), r2 = be / (1.0 - al);
-            double p1 = r1, p2 = r2;
-            for (int l = 0;; ++l, p1 *= r1, p2 *= r2) {
-                b = pre * (p1 + p2);
-                if (b <= tol || l == reqs[i].L) {
-                    L = l;
-                    break;
-                }
+            if (!m->absq_dev) {
+                m->absq_dev = true;
+                need.push_back(m);
             }
-        }
-        rp.pj[k].L = L;
-        Lch[i] = L;
-        bnd[i] = b;
     }
-    // 4. the contractions at the chosen orders
-    rc = run_requests(c, rp, np, U_out, status_out);
+    for (Mol* m : need)
+        if (launch_abs_sum(m->q, m->n, (double*)m->meta.p + 5, s) != hipSuccess) rc = TCM_EDEVICE;
+    if (rc != TCM_OK) {
+        for (Mol* m : need) m->absq_dev = false;
+        return rc;
+    }
+    if (launch_pairs_choose(bp.P, 0, npj, tol, dL, dB, s) != hipSuccess ||
+        launch_pairs(bp.P, 0, npj, s) != hipSuccess)
+        return TCM_EDEVICE;
+    std::vector<double> U(npj > 0 ? npj : 1), B(npj > 0 ? npj : 1);
+    std::vector<int32_t> st(npj > 0 ? npj : 1), Lc(npj > 0 ? npj : 1);
+    if (npj > 0 && (hipMemcpyAsync(U.data(), bp.P.U, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(B.data(), dB, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipMemcpyAsync(Lc.data(), dL, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess))
+        return TCM_EDEVICE;
+    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    mark_computed(rp);
     for (int64_t i = 0; i < np; ++i) {
-        if (L_out) L_out[i] = status_out[i] == TCM_OK ? Lch[i] : -1;
-        if (bound_out) bound_out[i] = status_out[i] == TCM_OK ? bnd[i] : std::nan("");
+        status_out[i] = rp.pre_status[i];
+        U_out[i] = std::nan("");
+        if (L_out) L_out[i] = -1;
+        if (bound_out) bound_out[i] = std::nan("");
     }
-    return rc;
+    for (int k = 0; k < npj; ++k) {
+        const int64_t i = rp.pj_req[k];
+        status_out[i] = st[k];
+        if (st[k] != TCM_OK) continue;
+        U_out[i] = U[k];
+        if (L_out) L_out[i] = Lc[k];
+        if (bound_out) bound_out[i] = B[k];
+    }
+    return first_error(status_out, np);
 }
 
 // ---------------------------------------------------------------- forces and torques
@@ -1683,7 +1768,7 @@ constexpr int FT_N = 10;
 extern "C" int tcm_pair_forces(tcm_ctx* t, tcm_mol_id a, tcm_mol_id b, const double* R, const double* quat_b, int L,
                                int flags, double* out, double* forces_A, double* forces_B)
 {
-    if (!t || !R || !out || L < 0 || L > LMAX) return TCM_EINVAL;
+    if (!t || !R || !out || L < 0 || L > LMAX || (flags & TCM_TRIANGULAR)) return TCM_EINVAL;
     Ctx& c = t->c;
     std::lock_guard<std::mutex> g(c.mu);
     (void)hipSetDevice(c.device);
@@ -1768,8 +1853,13 @@ extern "C" int tcm_batch_forces(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np
     std::lock_guard<std::mutex> g(c.mu);
     (void)hipSetDevice(c.device);
     hipStream_t s = c.stream;
+    // the force kernel differentiates the square truncation only: triangular items are
+    // invalid (given an order outside the accepted range, so that planning rejects them)
+    std::vector<tcm_pair_req> rq(reqs, reqs + np);
+    for (tcm_pair_req& r : rq)
+        if (r.flags & TCM_TRIANGULAR) r.L = -1;
     ReqPlan rp;
-    int rc = plan_requests(c, reqs, np, true, rp);
+    int rc = plan_requests(c, rq.data(), np, true, rp);
     if (rc != TCM_OK) return rc;
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
@@ -1807,6 +1897,7 @@ extern "C" int tcm_autotune_batch(tcm_ctx* t, const tcm_pair_req* reqs, int64_t 
     if (!t || npairs < 0 || (npairs > 0 && !reqs)) return TCM_EINVAL;
     Ctx& c = t->c;
     std::lock_guard<std::mutex> g(c.mu);
+    if (c.server) return TCM_EAGAIN;         // tilings are fixed while a server runs
     (void)hipSetDevice(c.device);
     hipStream_t s = c.stream;
     ReqPlan rp;
@@ -1827,7 +1918,10 @@ extern "C" int tcm_autotune_batch(tcm_ctx* t, const tcm_pair_req* reqs, int64_t 
     std::vector<hipEvent_t> ev(2 * sizes.size(), nullptr);
     for (auto& e : ev)
         if (rc == TCM_OK && hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
+    bool any64 = false;                                           // FP64 groups try every candidate
+    for (auto& kv : sizes) any64 |= kv.first.first == TCM_F64;
     for (int k = 16; rc == TCM_OK && k <= 256; k <<= 1) {
+        if (!any64 && k > std::max(16, c.f32_run_max)) break;     // FP32 groups are capped
         for (auto& kv : sizes)
             for (int64_t n : kv.second) c.tune[tune_key(kv.first.first, kv.first.second, n)] = k;
         BuiltPlan bp;
@@ -1857,8 +1951,9 @@ extern "C" int tcm_autotune_batch(tcm_ctx* t, const tcm_pair_req* reqs, int64_t 
         }
         for (int gi = 0; gi < ng && rc == TCM_OK; ++gi) {
             const std::pair<int, int> key{bp.groups[gi].prec, bp.groups[gi].L};
+            const int keff = key.first == TCM_F32C ? std::min(k, c.f32_run_max) : k;   // as kper_for applies it
             auto it = best.find(key);
-            if (it == best.end() || ms[gi] < it->second.first) best[key] = {ms[gi], k};
+            if (it == best.end() || ms[gi] < it->second.first) best[key] = {ms[gi], keff};
         }
     }
     for (auto& e : ev)
@@ -1885,6 +1980,7 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
         return TCM_EINVAL;
     Ctx& c = t->c;
     std::lock_guard<std::mutex> g(c.mu);
+    if (c.server) return TCM_EAGAIN;         // tilings are fixed while a server runs
     (void)hipSetDevice(c.device);
     hipStream_t s = c.stream;
     std::vector<double> coords(3 * n), charges(n);
@@ -1919,7 +2015,8 @@ extern "C" int tcm_autotune(tcm_ctx* t, int prec, int L, int64_t n, int* best_k,
     const int old = had ? c.tune[key] : 0;
     double bestt = 1e300;
     int bestk = 0;
-    for (int k = 8; rc == TCM_OK && k <= 256; k <<= 1) {
+    const int kmax = prec == TCM_F32C ? std::max(8, std::min(256, c.f32_run_max)) : 256;
+    for (int k = 8; rc == TCM_OK && k <= kmax; k <<= 1) {
         c.tune[key] = k;
         std::vector<MolJob> jobs(reps);
         for (int64_t r = 0; r < reps; ++r) {

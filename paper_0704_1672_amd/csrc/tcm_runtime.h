@@ -22,12 +22,15 @@ int num_blocks_for(int prec, int L);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevPlan& P, int begin, int end, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);
+// Adaptive truncation: lowers each pair's order in the plan to the smallest meeting tol.
+hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol, int32_t* Lout, double* bout,
+                               hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
 hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s);
-hipError_t launch_scan(const double* QA, const double* QB, int L, double rho, double aA, double aB, int unchecked,
-                       const double* invf, const double* rot, const double* quat, double* T, const double* R,
-                       int64_t nR, double* U, int32_t* status, hipStream_t s);
+hipError_t launch_scan(const double* QA, const double* QB, int L, int triangular, double rho, double aA, double aB,
+                       int unchecked, const double* invf, const double* rot, const double* quat, double* T,
+                       const double* R, int64_t nR, double* U, int32_t* status, hipStream_t s);
 // Forces and torques: FT[out][10] per pair (U, F_B, tau_A, tau_B); wscr and atab (both or
 // neither) receive the per-atom coefficient tables of the pairs (one pair per call when set).
 hipError_t launch_pairs_ft(const DevPlan& P, int begin, int end, double* FT, double* wscr, double* atab,
@@ -60,10 +63,11 @@ struct Mol {
     double centre[3] = {0, 0, 0};
     DevBuf moments;                // (Lcap+1)^2 FP64 resident moments
     DevBuf meta;                   // 5 FP64: centre, radius, scale
+    int plan_refs = 0;             // live plans whose launches read or write these buffers
     int Lcached = -1;              // order of valid resident moments (-1: none)
     double radius_host = -1.0;     // meta[3] read back to the host, -1 until then; reset
                                    // whenever the moments are recomputed
-    double absq_host = -1.0;       // sum |q_i| (truncation bound), -1 until computed; reset likewise
+    bool absq_dev = false;         // sum |q_i| (truncation bound) is in meta[5] on the device
     uint64_t last_use = 0;
     int plan_want = INT32_MIN;     // scratch of one request planning pass (under the context
     int plan_job = -1;             // lock): required order (-1 = reuse) and moment job index
@@ -97,12 +101,13 @@ struct PairJob {
 constexpr int NLANES = 2;          // streams the tile launches of a run are spread over
 
 struct Workspace {
-    DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS;
+    DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS, prot, pum;
     void* hstage = nullptr;        // pinned host staging for the blob
     size_t hstage_cap = 0;
-    hipStream_t aux[NLANES - 1] = {}; // the further lanes of tile launches
+    hipStream_t aux[NLANES] = {};  // the lanes of tile launches (forked from the run's stream)
     hipEvent_t fork = nullptr;
-    hipEvent_t join[NLANES - 1] = {};
+    hipEvent_t join[NLANES] = {};
+    std::vector<hipEvent_t> gev;   // per group: its statistics and centre/scale are done
 };
 
 struct BuiltPlan {
@@ -131,7 +136,7 @@ struct Ctx {
     int num_cu = 256;
     std::atomic<size_t> budget{0}; // 0 = unbounded
     std::atomic<size_t> used{0};
-    DevBuf t_invk, t_invf, t_rot;
+    DevBuf t_invk, t_invf, t_rot, t_fact;
     std::mutex mu;                 // guards molecules, tuning and the shared workspace
     std::unordered_map<int64_t, std::unique_ptr<Mol>> mols;
     int64_t next_id = 1;
@@ -140,11 +145,12 @@ struct Ctx {
     DevBuf tmp_atoms, tmp_q;       // one-shot uploads
     DevBuf scan_g, scan_r, scan_u, scan_s;   // translation scan: pair-tensor table, host-side I/O
     DevBuf force_ft, force_w, force_t, force_a, force_b;   // forces: outputs, coefficient tables, host-side I/O
-    DevBuf absq;                   // sum |q| of the molecules an adaptive batch needs
+    DevBuf adapt;                  // adaptive batches: chosen orders and bounds per pair
     DevBuf gather;                 // K record pointers, then K gathered 8-double records
     void* hpin = nullptr;          // pinned staging for one-shot uploads
     size_t hpin_cap = 0;
     std::map<int64_t, int> tune;   // key(prec, L, bucket) -> kper
+    int f32_run_max = 64;          // longest plain FP32 run of a thread (caps kper of TCM_F32C)
     // serving
     struct Server* server = nullptr;
 
@@ -185,4 +191,6 @@ struct tcm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int npairs = 0;
+    std::vector<tcm::Mol*> refs;   // molecules the plan names (pinned: not released while it lives)
+    std::vector<std::pair<tcm::Mol*, int>> computed;   // moments each run writes, and their order
 };

@@ -5,10 +5,13 @@
 //      mark the moments they computed as resident, release fragment references;
 //   2. while a launch slot is free and requests are pending: admit requests in arrival order
 //      into a batch -- a fragment that is resident is a cache hit; a new fragment is copied
-//      into server-owned device memory after HBM admission (LRU eviction of idle fragments
-//      when the context's budget would be exceeded; a request is admitted whole -- both of
-//      its fragments -- or waits, and a waiting request fetches nothing);
-//      a request whose fragment is being computed by an in-flight launch waits for it;
+//      into server-owned device memory after HBM admission (when the context's budget would
+//      be exceeded, the atoms of idle fragments are evicted least recently used first, while
+//      their moment tables -- 8.7 KB each -- stay resident, so a later request of the same
+//      fragment at an order it already holds is still served; a whole fragment is dropped only
+//      when the moment arena cannot grow); a request is admitted whole -- both of its
+//      fragments -- or waits, and a waiting request fetches nothing; a request whose fragment
+//      is being computed by an in-flight launch waits for it;
 //   3. launch the batch on the slot's own stream (statistics, per-order tile kernels, pair
 //      kernel -- the same kernels as tcm_batch_energy) followed by asynchronous copies of the
 //      results into the slot's pinned buffers and an event.
@@ -35,6 +38,7 @@ struct SMol {
     double* moments = nullptr;     // slot of the moment arena: (LMAX+1)^2 table + 8 meta
     int slot = -1;
     int Lcached = -1;              // valid resident order
+    bool atoms_gone = false;       // atoms evicted (moments kept): only orders <= Lcached are served
     int busy = 0;                  // being computed by an in-flight launch
     int refs = 0;                  // referenced by in-flight launches
     int pin = 0;                   // referenced by the batch being formed (not evictable)
@@ -92,6 +96,9 @@ struct Server {
     std::vector<Slot> slots;
     uint64_t next_ticket = 1;
     int64_t completed = 0, launches = 0, hits = 0, misses = 0, deferred = 0, evictions = 0;
+    int64_t dropped = 0;           // fragments dropped whole (moment slot reclaimed)
+    int64_t gone = 0;              // requests needing an order above the resident one of a
+                                   // fragment whose atoms were evicted (TCM_ENOTFOUND)
     int inflight = 0;
 };
 
@@ -102,6 +109,14 @@ static double seconds_since(clock_t_::time_point t)
 
 // Copied atoms are freed in stream order on `s`: no launch still reads them (refs == 0 or the
 // fragment was never launched), and the pool orders any reuse behind this point of `s`.
+// Borrowed atoms are only forgotten.
+static void drop_atoms(Server* S, SMol* m, hipStream_t s)
+{
+    S->c->release_async(m->atoms, s);
+    for (auto& p : m->src) p = nullptr;
+    m->atoms_gone = true;
+}
+
 static void free_mol(Server* S, SMol* m, hipStream_t s)
 {
     S->c->release_async(m->atoms, s);
@@ -110,14 +125,32 @@ static void free_mol(Server* S, SMol* m, hipStream_t s)
     m->moments = nullptr;
 }
 
-static bool take_slot(Server* S, SMol* m)
+static bool evictable(const SMol* m) { return m->refs == 0 && m->pin == 0 && !m->busy; }
+
+static bool take_slot(Server* S, SMol* m, hipStream_t s)
 {
     if (S->free_slots.empty()) {
         DevBuf b;
-        if (S->c->alloc(b, sizeof(double) * ARENA_SLOT * ARENA_CHUNK) != TCM_OK) return false;
-        const int base = (int)S->arena.size() * ARENA_CHUNK;
-        S->arena.push_back(b);
-        for (int i = ARENA_CHUNK - 1; i >= 0; --i) S->free_slots.push_back(base + i);
+        if (S->c->alloc(b, sizeof(double) * ARENA_SLOT * ARENA_CHUNK) == TCM_OK) {
+            const int base = (int)S->arena.size() * ARENA_CHUNK;
+            S->arena.push_back(b);
+            for (int i = ARENA_CHUNK - 1; i >= 0; --i) S->free_slots.push_back(base + i);
+        } else {
+            // the arena cannot grow: drop the least recently used idle fragment whole
+            for (auto it = S->lru.end(); it != S->lru.begin();) {
+                --it;
+                auto f = S->cache.find(*it);
+                SMol* v = f->second.get();
+                if (v != m && evictable(v) && v->slot >= 0) {
+                    free_mol(S, v, s);
+                    S->lru.erase(it);
+                    S->cache.erase(f);
+                    ++S->dropped;
+                    break;
+                }
+            }
+            if (S->free_slots.empty()) return false;
+        }
     }
     m->slot = S->free_slots.back();
     S->free_slots.pop_back();
@@ -134,10 +167,9 @@ static size_t mol_bytes(int64_t n, bool borrow)
     return b < 256 ? 256 : b;      // the allocator's minimum
 }
 
-static bool evictable(const SMol* m) { return m->refs == 0 && m->pin == 0 && !m->busy; }
-
-// Evict idle fragments (least recently used first) until `need` more bytes fit the budget.
-// Evicts nothing when even evicting every idle fragment would not make enough room.
+// Evict the atoms of idle fragments (least recently used first; their moment tables stay)
+// until `need` more bytes fit the budget.  Evicts nothing when even evicting every idle
+// fragment's atoms would not make enough room.
 static bool make_room(Server* S, size_t need, hipStream_t s)
 {
     Ctx* c = S->c;
@@ -149,15 +181,11 @@ static bool make_room(Server* S, size_t need, hipStream_t s)
         if (evictable(kv.second.get())) idle += kv.second->atoms.cap;
     const size_t used = c->used.load();
     if (used + need > budget + idle) return false;
-    auto it = S->lru.end();
-    while (c->used.load() + need > budget && it != S->lru.begin()) {
+    for (auto it = S->lru.end(); c->used.load() + need > budget && it != S->lru.begin();) {
         --it;
-        auto f = S->cache.find(*it);
-        SMol* m = f->second.get();
-        if (evictable(m)) {
-            free_mol(S, m, s);
-            it = S->lru.erase(it);
-            S->cache.erase(f);
+        SMol* m = S->cache.find(*it)->second.get();
+        if (evictable(m) && m->atoms.cap > 0) {
+            drop_atoms(S, m, s);
             ++S->evictions;
         }
     }
@@ -233,14 +261,18 @@ static void admit_and_launch(Server* S, Slot& sl)
     std::vector<int32_t> pre;
     std::deque<SReq> keep;
     // Resolve one side of a request without side effects: a resident fragment, a new one to
-    // fetch (fresh), or a status (TCM_EAGAIN: wait for an in-flight launch; TCM_ENOTFOUND).
+    // fetch (fresh), a resident one whose evicted atoms the request brings again (refetch),
+    // or a status (TCM_EAGAIN: wait for an in-flight launch; TCM_ENOTFOUND).
     struct Side {
         SMol* m = nullptr;
         bool fresh = false;
+        bool refetch = false;
+        bool gone = false;         // TCM_ENOTFOUND because the atoms were evicted
         int status = TCM_OK;
     };
     auto look = [&](int64_t key, const double* const atoms[4], int64_t n, int L) -> Side {
         Side sd;
+        const bool has = atoms[0] && atoms[1] && atoms[2] && atoms[3];
         auto f = S->cache.find(key);
         if (f != S->cache.end()) {
             SMol* m = f->second.get();
@@ -249,13 +281,34 @@ static void admit_and_launch(Server* S, Slot& sl)
             const bool recompute = m->Lcached < L && (nd == need.end() || nd->second < L);
             // an in-flight launch still reads this table: do not rewrite it
             if (recompute && m->refs > 0) { sd.status = TCM_EAGAIN; return sd; }
+            if (recompute && m->atoms_gone) {
+                // a higher order than the resident one needs the atoms back
+                if (!(has || n == 0) || n != m->n) { sd.status = TCM_ENOTFOUND; sd.gone = true; return sd; }
+                sd.refetch = true;
+            }
             sd.m = m;
             return sd;
         }
-        const bool has = atoms[0] && atoms[1] && atoms[2] && atoms[3];
         if (!(has || n == 0)) { sd.status = TCM_ENOTFOUND; return sd; }
         sd.fresh = true;
         return sd;
+    };
+    // Bring the evicted atoms of a resident fragment back (bytes already admitted).
+    auto refetch = [&](SMol* m, const double* const atoms[4], int flags) -> int {
+        if (flags & TCM_BORROW_ATOMS) {
+            for (int k = 0; k < 4; ++k) m->src[k] = atoms[k];
+        } else {
+            if (c->alloc_async(m->atoms, sizeof(double) * 4 * (size_t)(m->n > 0 ? m->n : 1), sl.stream) != TCM_OK)
+                return TCM_EAGAIN;
+            if (copy_atoms(m, atoms, (flags & TCM_HOST_ATOMS) != 0, sl.stream) != TCM_OK) {
+                S->c->release_async(m->atoms, sl.stream);
+                return TCM_EDEVICE;
+            }
+            const double* d = (const double*)m->atoms.p;
+            for (int k = 0; k < 4; ++k) m->src[k] = d + k * m->n;
+        }
+        m->atoms_gone = false;
+        return TCM_OK;
     };
     // Create a fragment whose device bytes have been admitted; its atoms are copied on the
     // launch stream of this batch, ahead of the kernels that read them.
@@ -265,7 +318,7 @@ static void admit_and_launch(Server* S, Slot& sl)
         m->key = key;
         m->n = n;
         m->prec = prec;
-        if (!take_slot(S, m.get())) { *status = TCM_EAGAIN; return nullptr; }
+        if (!take_slot(S, m.get(), sl.stream)) { *status = TCM_EAGAIN; return nullptr; }
         if (flags & TCM_BORROW_ATOMS) {
             for (int k = 0; k < 4; ++k) m->src[k] = atoms[k];
         } else {
@@ -324,11 +377,15 @@ static void admit_and_launch(Server* S, Slot& sl)
         const bool same = r.key_b == r.key_a;
         Side sa = look(r.key_a, r.atoms_a, r.n_a, r.L);
         Side sb = same ? sa : look(r.key_b, r.atoms_b, r.n_b, r.L);
-        if (sa.status == TCM_ENOTFOUND || sb.status == TCM_ENOTFOUND) return TCM_ENOTFOUND;
+        if (sa.status == TCM_ENOTFOUND || sb.status == TCM_ENOTFOUND) {
+            if (sa.gone || sb.gone) ++S->gone;
+            return TCM_ENOTFOUND;
+        }
         if (sa.status != TCM_OK || sb.status != TCM_OK) return TCM_EAGAIN;
         const bool borrow = (r.flags & TCM_BORROW_ATOMS) != 0;
         const int nfresh = (sa.fresh ? 1 : 0) + (sb.fresh && !same ? 1 : 0);
-        size_t bytes = (sa.fresh ? mol_bytes(r.n_a, borrow) : 0) + (sb.fresh && !same ? mol_bytes(r.n_b, borrow) : 0);
+        size_t bytes = (sa.fresh || sa.refetch ? mol_bytes(r.n_a, borrow) : 0) +
+                       (!same && (sb.fresh || sb.refetch) ? mol_bytes(r.n_b, borrow) : 0);
         if ((int)S->free_slots.size() < nfresh) bytes += sizeof(double) * ARENA_SLOT * ARENA_CHUNK;
         if (c->budget) bytes += growth_with(sa, sb, r);
         if (bytes) {
@@ -341,6 +398,9 @@ static void admit_and_launch(Server* S, Slot& sl)
             if (!ok) return TCM_EAGAIN;
         }
         int st = TCM_OK;
+        // atoms brought back for a higher order (their bytes were admitted above)
+        if (sa.refetch && (st = refetch(sa.m, r.atoms_a, r.flags)) != TCM_OK) return st;
+        if (!same && sb.refetch && (st = refetch(sb.m, r.atoms_b, r.flags)) != TCM_OK) return st;
         SMol* a = sa.m;
         if (sa.fresh && !(a = create(r.key_a, r.atoms_a, r.n_a, r.precision, r.flags, &st))) return st;
         SMol* b = same ? a : sb.m;
@@ -443,7 +503,7 @@ static void admit_and_launch(Server* S, Slot& sl)
         j.depA = fa == jobidx.end() ? -1 : fa->second;
         j.depB = fb == jobidx.end() ? -1 : fb->second;
         j.L = r.L;
-        j.flags = r.flags & TCM_UNCHECKED;
+        j.flags = r.flags & (TCM_UNCHECKED | TCM_TRIANGULAR);
         for (int d = 0; d < 3; ++d) j.R[d] = r.R[d];
         for (int d = 0; d < 4; ++d) j.quat[d] = r.quat_b[d];
         j.has_rot = !(r.quat_b[0] > 0 && r.quat_b[1] == 0 && r.quat_b[2] == 0 && r.quat_b[3] == 0);
@@ -630,7 +690,7 @@ extern "C" int tcm_server_stop(tcm_ctx* t)
 }
 
 extern "C" int tcm_server_stats(tcm_ctx* t, int64_t* completed, int64_t* launches, int64_t* hits, int64_t* misses,
-                                int64_t* deferred, int64_t* evictions)
+                                int64_t* deferred, int64_t* evictions, int64_t* dropped, int64_t* gone)
 {
     if (!t || !t->c.server) return TCM_EINVAL;
     Server* S = t->c.server;
@@ -641,5 +701,7 @@ extern "C" int tcm_server_stats(tcm_ctx* t, int64_t* completed, int64_t* launche
     if (misses) *misses = S->misses;
     if (deferred) *deferred = S->deferred;
     if (evictions) *evictions = S->evictions;
+    if (dropped) *dropped = S->dropped;
+    if (gone) *gone = S->gone;
     return TCM_OK;
 }

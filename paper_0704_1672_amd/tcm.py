@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tcm.h")
 TCM_OK, TCM_EINVAL, TCM_EDOMAIN, TCM_ENOMEM, TCM_EDEVICE, TCM_EAGAIN, TCM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 TCM_LMAX = 32
 TCM_F64, TCM_F32C = 0, 1
-TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS, TCM_BORROW_ATOMS, TCM_DEVICE_IO = 1, 2, 4, 8, 16
+TCM_UNCHECKED, TCM_REUSE, TCM_HOST_ATOMS, TCM_BORROW_ATOMS, TCM_DEVICE_IO, TCM_TRIANGULAR = 1, 2, 4, 8, 16, 32
 
 _dp = C.POINTER(C.c_double)
 _ip32 = C.POINTER(C.c_int32)
@@ -72,6 +72,7 @@ _SIGS = {
     "tcm_plan_destroy": (None, [_vp]),
     "tcm_tune_get": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32]),
     "tcm_tune_set": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, C.c_int]),
+    "tcm_set_fp32_run": (C.c_int, [_vp, C.c_int]),
     "tcm_autotune": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int64, _ip32, _dp]),
     "tcm_autotune_batch": (C.c_int, [_vp, _vp, C.c_int64, _dp]),
     "tcm_scan_translations": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int, _dp, C.c_int, _dp, C.c_int64, _dp,
@@ -87,7 +88,7 @@ _SIGS = {
     "tcm_submit": (C.c_int, [_vp, C.POINTER(tcm_request), C.POINTER(C.c_uint64)]),
     "tcm_poll": (C.c_int, [_vp, C.c_uint64, _dp, _ip32, _dp]),
     "tcm_server_stop": (C.c_int, [_vp]),
-    "tcm_server_stats": (C.c_int, [_vp, _ip64, _ip64, _ip64, _ip64, _ip64, _ip64]),
+    "tcm_server_stats": (C.c_int, [_vp, _ip64, _ip64, _ip64, _ip64, _ip64, _ip64, _ip64, _ip64]),
 }
 
 _lib = None
@@ -337,6 +338,10 @@ def tcm_tune_set(ctx, precision, L, n, kper):
     _check(lib().tcm_tune_set(ctx, precision, L, n, kper), "tcm_tune_set")
 
 
+def tcm_set_fp32_run(ctx, kmax):
+    _check(lib().tcm_set_fp32_run(ctx, int(kmax)), "tcm_set_fp32_run")
+
+
 def tcm_autotune(ctx, precision, L, n):
     k = C.c_int32()
     ms = C.c_double()
@@ -468,10 +473,10 @@ def tcm_server_stop(ctx):
 
 
 def tcm_server_stats(ctx):
-    v = [C.c_int64() for _ in range(6)]
+    v = [C.c_int64() for _ in range(8)]
     _check(lib().tcm_server_stats(ctx, *[C.byref(x) for x in v]), "tcm_server_stats")
-    return dict(zip(["completed", "launches", "cache_hits", "cache_misses", "deferred", "evictions"],
-                    [x.value for x in v]))
+    return dict(zip(["completed", "launches", "cache_hits", "cache_misses", "deferred", "evictions", "dropped",
+                     "evicted_misses"], [x.value for x in v]))
 
 
 def make_request(key_a, key_b, R, L, quat_b=(1.0, 0.0, 0.0, 0.0), atoms_a=None, n_a=0, atoms_b=None, n_b=0,

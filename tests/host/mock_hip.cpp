@@ -80,8 +80,9 @@ hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t) {
         for (int h = 0; h < nh(w.L); ++h) w.Q[h] = w.n; w.meta[3] = 0.5; }
     return 0; }
 hipError_t launch_tiles(int, int, const DevPlan&, int, int, hipStream_t) { return fail_now(g_fail_launch, g_launch_calls) ? 1 : 0; }
-hipError_t launch_scan(const double*, const double*, int, double, double, double, int, const double*, const double*,
-                       const double*, double*, const double*, int64_t nR, double* U, int32_t* status, hipStream_t) {
+hipError_t launch_scan(const double*, const double*, int, int, double, double, double, int, const double*,
+                       const double*, const double*, double*, const double*, int64_t nR, double* U, int32_t* status,
+                       hipStream_t) {
     for (int64_t k = 0; k < nR; ++k) { U[k] = 0.0; status[k] = 0; }
     return 0; }
 hipError_t launch_alu_probe(int, void*, int, int, hipStream_t) { return 0; }
@@ -98,6 +99,9 @@ hipError_t launch_pairs_ft(const DevPlan& P, int b, int e, double* FT, double*, 
     return 0; }
 hipError_t launch_atom_forces(const double*, int, int, const double*, const double*, const double*, const double*,
                               int64_t, const double*, double*, hipStream_t) { return 0; }
+hipError_t launch_pairs_choose(const DevPlan& P, int b, int e, double, int32_t* Lout, double* bout, hipStream_t) {
+    for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; Lout[w.out] = w.L; bout[w.out] = 0.0; }
+    return 0; }
 hipError_t launch_pairs(const DevPlan& P, int b, int e, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; double s = w.QA[0] + 1e-3 * w.QB[0];
         double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);

@@ -33,6 +33,24 @@ static int plan_lifecycle() {
         size_t u; tcm_mem_info(ctx, &u, nullptr);
         if (rep >= 10 && u != base) { printf("plan %d: used %zu != %zu after destroy\n", rep, u, base); return 5; }
     }
+    {   // a live plan pins its molecules; its moments count as resident only once it has run
+        tcm_mol_id c2;
+        if (tcm_mol_upload(ctx, xyz.data(), q.data(), 4000, nullptr, TCM_F32C, &c2)) return 6;
+        tcm_pair_req r = {};
+        r.a = a; r.b = c2; r.R[0] = 100.0; r.quat_b[0] = 1; r.L = 6;
+        tcm_plan* p;
+        if (tcm_plan_create(ctx, &r, 1, 0, &p)) return 7;
+        if (tcm_mol_release(ctx, c2) != TCM_EAGAIN) { printf("release of a planned molecule allowed\n"); return 8; }
+        std::vector<double> Q(49);
+        // not run yet: a reuse recomputes instead of reading the plan's unwritten table
+        if (tcm_mol_moments(ctx, c2, 6, TCM_REUSE, Q.data(), nullptr, nullptr) || Q[0] != 4000.0) {
+            printf("reuse before the plan ran read %g\n", Q[0]);
+            return 9;
+        }
+        if (tcm_plan_run(ctx, p)) return 10;
+        tcm_plan_destroy(p);
+        if (tcm_mol_release(ctx, c2) != TCM_OK) return 11;
+    }
     tcm_destroy(ctx);
     printf("plan lifecycle ok\n");
     return 0;
@@ -160,7 +178,7 @@ int main(int argc, char** argv) {
             }
             if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(20)) { printf("seed %d: stuck at %d/%d\n", seed, done, nreq); return 5; }
         }
-        int64_t c, l, h, m, d, e; tcm_server_stats(ctx, &c, &l, &h, &m, &d, &e);
+        int64_t c, l, h, m, d, e, dr, g; tcm_server_stats(ctx, &c, &l, &h, &m, &d, &e, &dr, &g);
         size_t u2, b2; tcm_mem_info(ctx, &u2, &b2);
         printf("seed %d: done %d bad %d nomem %d notfound %d edomain %d | launches %lld hits %lld misses %lld deferred %lld evictions %lld | used %zu <= budget %zu %s\n",
                seed, done, bad, nomem, nf, dom, (long long)l, (long long)h, (long long)m, (long long)d, (long long)e, u2, b2, u2 <= b2 ? "ok" : "OVER");
