@@ -89,8 +89,53 @@ struct DevPlan {
     const double* invk;            // 1/k_lm of the normalised recurrence, per packed index
     const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
     const double* rot;             // rotation tables (D and D^{-1} per l, compressed by sparsity)
+    const double* rotr;            // the same, row by row (rot + rot_tables_len())
     const double* fact;            // k!, k <= 2 LMAX + 1
+    const double* frame;           // per pair and side, [2][FRAME_N][npairs]: see side_frame
+    int32_t* gorder;               // largest order of each group of PAIR_LANES pairs
 };
+
+// Pair launches take the pairs PAIR_LANES at a time, one pair per lane of a wavefront.
+constexpr int PAIR_LANES = 64;
+constexpr int PAIR_WAVES = 4;      // wavefronts of a pair workgroup (threadIdx.y)
+
+// Frame of one side of a pair for the axial form of eq. (9): the rotation that takes R/|R| to
+// s z (s = the sign of R_z; side 1: applied after B's pose, the pose first), as e^{i gamma},
+// e^{i beta}, e^{i alpha} of its ZYZ Euler angles (rotation = Rz(alpha) Ry(beta) Rz(gamma)),
+// then 1/|R| and s.  No angles are formed: the shortest rotation taking n = R/|R| to s z is the
+// quaternion (1 + s n_z, s n_y, -s n_x, 0) normalised; for a unit quaternion (w, x, y, z) with
+// r1 = |(w, z)| and r2 = |(x, y)|, e^{i a+} = (w + i z)/r1 and e^{i a-} = (y - i x)/r2 (the angle
+// taken as 0 when its modulus vanishes), gamma = a+ - a-, alpha = a+ + a-, and
+// e^{i beta} = (r1 + i r2)^2 / (r1^2 + r2^2).  Computed by the host when a plan is built.
+constexpr int FRAME_N = 8;
+__host__ __device__ inline void side_frame(const double R[3], const double quat[4], bool pose, double f[FRAME_N])
+{
+    const double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    const double ir = Rn > 0.0 ? 1.0 / Rn : 0.0;
+    const double nx = R[0] * ir, ny = R[1] * ir, nz = R[2] * ir;
+    const double sg = nz < 0.0 ? -1.0 : 1.0;
+    double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx, z = 0.0;
+    const double qn = sqrt(w * w + x * x + y * y);
+    w /= qn; x /= qn; y /= qn;
+    if (pose) {                                  // frame * pose
+        const double a = w * quat[0] - x * quat[1] - y * quat[2];
+        const double b = w * quat[1] + x * quat[0] + y * quat[3];
+        const double c = w * quat[2] - x * quat[3] + y * quat[0];
+        const double d = w * quat[3] + x * quat[2] - y * quat[1];
+        const double pn = sqrt(a * a + b * b + c * c + d * d);
+        w = a / pn; x = b / pn; y = c / pn; z = d / pn;
+    }
+    const double r1 = sqrt(w * w + z * z), r2 = sqrt(x * x + y * y);
+    double pc = 1.0, ps = 0.0, mc = 1.0, ms = 0.0;
+    if (r1 > 0.0) { pc = w / r1; ps = z / r1; }
+    if (r2 > 0.0) { mc = y / r2; ms = -x / r2; }
+    const double rr = r1 * r1 + r2 * r2;
+    f[0] = pc * mc + ps * ms; f[1] = ps * mc - pc * ms;          // gamma
+    f[2] = (r1 * r1 - r2 * r2) / rr; f[3] = 2.0 * r1 * r2 / rr;    // beta
+    f[4] = pc * mc - ps * ms; f[5] = ps * mc + pc * ms;          // alpha
+    f[6] = ir;
+    f[7] = sg;
+}
 
 // Packed index helpers (layout of every moment table at the boundary):
 //   m = 0: l*l ; m > 0: Re at l*l + 2m - 1, Im at l*l + 2m.
@@ -112,6 +157,14 @@ __host__ __device__ constexpr int rot_block_offset(int l)
     if (l & 1) s += 8 * p * p + 18 * p + 4;    // the even order 2p
     return (LMAX + 1) + s;
 }
+
+// Doubles of order l's block in the rotation tables (2n row codes, 2Kn values), and of the
+// tables for all orders.  The device copy holds the tables twice: slot by slot as described
+// above, then row by row (same header and block offsets; in block l, row i of D at i (K+1) and
+// row i of D^{-1} at (n + i)(K+1), each the row's code followed by its K values, zero past its
+// count), the layout the pair launches read with scalar loads.
+__host__ __device__ constexpr int rot_block_len(int l) { return 2 * (2 * l + 1) * (l / 2 + 2); }
+__host__ __device__ constexpr int rot_tables_len() { return rot_block_offset(LMAX + 1); }
 
 // m-block partition of the (l, m >= 0) harmonics for the moment tile.  Accumulator cost
 // of the m-chain is (L-m+1) values (times 2 for m > 0: real and imaginary parts).

@@ -378,239 +378,323 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 // taking n = R/|R| to t = sign(n_z) z, (1 + n.t, n x t) normalised (1 + |n_z| >= 1, so it is
 // well conditioned for every direction).
 //
-// The pair launches take the pairs G at a time (G = 64, one wavefront; 32 when the order
-// exceeds 24, to keep the LDS of a workgroup within 64 KB), one pair per lane: every loop index (order,
-// row, slot, m) is then the same in all lanes of a wavefront, the rotation tables are read once
-// per group into LDS and shared by its pairs, and the vector units do the arithmetic of G pairs
-// per instruction.  A group runs to the largest order of its pairs (the launch lists pairs by
-// decreasing order, so groups are nearly uniform); a lane whose pair has a lower order skips
-// what it does not need.
-//   tcm_pairs_rot    (group, l, side): the order-l block of one side's table rotated into the
-//                    frame where R lies along z (B's pose folded in), scaled by R^-l / f_lm,
-//                    written to the plan's scratch [side][h][pair];
+// The pair launches take the pairs PAIR_LANES (64) at a time, one pair per lane: every loop
+// index (order, row, slot, m) is then the same in all lanes of a wavefront, the rotation tables
+// are read once per workgroup into LDS and shared by its pairs, and the vector units do the
+// arithmetic of 64 pairs per instruction.  A group runs to the largest order of its pairs (the
+// launch lists pairs by decreasing order, so groups are nearly uniform); a lane whose pair has a
+// lower order skips what it does not need.  The work of a pair is small (O(L^3)), so the kernels
+// are written for latency: every load a workgroup needs is issued before the first is used.
+//   tcm_pairs_rot    (group, l, side), highest orders first: the order-l block of one side's
+//                    table rotated into the frame where R lies along z (B's pose folded in; the
+//                    Euler phases come from the plan, computed by the host), scaled by
+//                    R^-l / f_lm, written to the plan's scratch [side][h][pair];
 //   tcm_pairs_sum_m  (group, m): for each pair the m-term of the axial contraction;
 //   tcm_pairs_final  (pair): U = (sum over m in order) / R and the status (eq. 2 checked here).
 // Each pair's arithmetic is its own lane's, in a fixed order: a result does not depend on the
 // other pairs of the launch.
-constexpr int PAIR_LANES = 64;
-using cdptr = const __attribute__((address_space(4))) double*;
+constexpr int PAIR_UNITS = (LMAX + PAIR_WAVES) / PAIR_WAVES;     // m-units of a wavefront, m = wv + u W
+constexpr int ROT_PAD = 4;        // zero rows after an LDS vector: the slots past a row's count read there
 
-// Largest order of the group's pairs (the launch lists pairs by decreasing order, but the
-// adaptive path lowers orders on the device after the listing).
-__device__ __forceinline__ int group_order(const DevPlan& P, int g0, int end)
+// Largest of v over the wavefront (the same value in every lane).
+__device__ __forceinline__ int wave_max(int v)
 {
-    const int G = blockDim.x;
-    int v = g0 + (int)threadIdx.x < end ? P.pairs[g0 + threadIdx.x].L : -1;
-    for (int off = G / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, G));
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Per-lane geometry of a pair: 1/R, the sign of R_z, and the unit quaternion of the side's
-// rotation (side 0: the frame rotation taking R/|R| to +-z; side 1: the frame after B's pose).
-__device__ __forceinline__ void pair_frame(const PairWork& pw, int side, double& ir, double& sg, double q[4])
+__device__ __forceinline__ void cmul(double& c, double& s, double bc, double bs)
 {
-    const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
-    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-    ir = Rn > 0.0 ? 1.0 / Rn : 0.0;
-    const double nx = Rx * ir, ny = Ry * ir, nz = Rz * ir;
-    sg = nz < 0.0 ? -1.0 : 1.0;
-    double w = 1.0 + sg * nz, x = sg * ny, y = -sg * nx;
-    const double qn = sqrt(w * w + x * x + y * y);
-    w /= qn; x /= qn; y /= qn;
-    if (side == 1 && pw.has_rot) {           // frame (x) pose: the pose applied first
-        const double* p = pw.quat;
-        q[0] = w * p[0] - x * p[1] - y * p[2];
-        q[1] = w * p[1] + x * p[0] + y * p[3];
-        q[2] = w * p[2] - x * p[3] + y * p[0];
-        q[3] = w * p[3] + x * p[2] - y * p[1];
-    } else {
-        q[0] = w; q[1] = x; q[2] = y; q[3] = 0.0;
-    }
+    const double t = c * bc - s * bs;
+    s = c * bs + s * bc;
+    c = t;
 }
 
-// e^{i gamma}, e^{i beta}, e^{i alpha} of the ZYZ Euler angles of the unit quaternion q
-// (R = Rz(alpha) Ry(beta) Rz(gamma)), without angles: with r1 = |(w, z)| and r2 = |(x, y)|,
-// e^{i a+} = (w + i z)/r1 and e^{i a-} = (y - i x)/r2 (either free, taken as 0, when its modulus
-// vanishes), gamma = a+ - a-, alpha = a+ + a-, e^{i beta} = (r1 + i r2)^2 / (r1^2 + r2^2).
-__device__ __forceinline__ void euler_bases(const double q[4], double e[3][2])
+// e^{i w phi} and e^{i W phi} from e^{i phi}: a wavefront w of W walks m = w, w + W, ...
+__device__ __forceinline__ void phase_walk(double ec, double es, int w, int W, double& c0, double& s0, double& cs,
+                                          double& ss)
 {
-    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-    const double r1 = sqrt(w * w + z * z), r2 = sqrt(x * x + y * y);
-    double pc = 1.0, ps = 0.0, mc = 1.0, ms = 0.0;
-    if (r1 > 0.0) { pc = w / r1; ps = z / r1; }
-    if (r2 > 0.0) { mc = y / r2; ms = -x / r2; }
-    const double rr = r1 * r1 + r2 * r2;
-    e[0][0] = pc * mc + ps * ms; e[0][1] = ps * mc - pc * ms;        // gamma
-    e[1][0] = (r1 * r1 - r2 * r2) / rr; e[1][1] = 2.0 * r1 * r2 / rr;  // beta
-    e[2][0] = pc * mc - ps * ms; e[2][1] = ps * mc + pc * ms;        // alpha
+    c0 = 1.0; s0 = 0.0;
+    for (int k = 0; k < w; ++k) cmul(c0, s0, ec, es);
+    cs = 1.0; ss = 0.0;
+    for (int k = 0; k < W; ++k) cmul(cs, ss, ec, es);
 }
 
-// One row of the order-l block of D (inverse: D^-1) applied to the LDS vectors v[j][lane]:
-// the row's code and values are wave-uniform (read from the block staged in LDS); the sum over
-// the K slots in the order of the tables (even and odd slots in two partial sums).
-__device__ __forceinline__ double rot_row_lanes(const double* blk, int n, int K, int i, bool inverse, const double* v,
-                                                int G)
+// One row of D or D^-1 (row-by-row tables: the code, then K values) applied to the LDS vector
+// v[j][lane]: the row is the same for every lane (scalar loads); slot 0 reads column max(0, jb),
+// slot k > 0 column jb + 4k (at most n + 3: the rows past n are zero, as are the values past the
+// row's count).  The sum over the slots in order, even and odd slots in two partial sums.
+using cdptr = const __attribute__((address_space(4))) double*;
+
+template <int K>
+__device__ __forceinline__ double rot_row_lanes(cdptr row, const double* v)
 {
-    const int code = (int)blk[(inverse ? n : 0) + i];
-    const int jb = (code & 0xffff) - 1;
-    const double* val = blk + 2 * n + (inverse ? K * n : 0) + i;
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        const int j = min(n - 1, max(0, jb + 4 * k));
-        const double x = val[k * n] * v[j * G];
-        if (k & 1) s1 += x; else s0 += x;
+    const int jb = ((int)row[0] & 0xffff) - 1;
+    const double* vb = v + jb * PAIR_LANES;
+    double s0 = row[1] * v[max(0, jb) * PAIR_LANES], s1 = 0.0;
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        const double t = row[1 + k] * vb[4 * k * PAIR_LANES];
+        if (k & 1) s1 += t; else s0 += t;
     }
     return s0 + s1;
 }
 
-// LDS of the rotation launch: the two vectors of the group ([2l+1][G] each) and the order's
-// table block (2n codes and 2Kn values); the group size keeps it within 64 KB.
-__host__ __device__ constexpr int rot_block_len(int l) { return 2 * (2 * l + 1) * (l / 2 + 2); }
-__host__ __device__ constexpr int pair_group(int Lm) { return Lm <= 24 ? 64 : 32; }
-
-__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_rot(DevPlan P, int begin, int end)
+// The order-l work of one (group, side): wavefront wv takes the units m = wv, wv + W, ... (the
+// rows of Re and Im of m), at most U of them; the rows of Z(beta) D are kept in registers until
+// every wavefront has read the vector, then written over it.
+template <int l>
+__device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, int side, double* sv)
 {
-    extern __shared__ __align__(16) double sv[];       // [2][2 pair_lmax + 1][G], table block
-    const int lane = threadIdx.x, G = blockDim.x;
-    const int g0 = begin + (int)blockIdx.x * G;
-    const int l = blockIdx.y, side = blockIdx.z;
-    if (l > group_order(P, g0, end)) return;             // beyond the group's largest order
+    constexpr int n = 2 * l + 1, K = l / 2 + 1, W = PAIR_WAVES, U = (l + W) / W;
+    const int lane = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
     const int p = min(g0 + lane, end - 1);
     const PairWork& pw = P.pairs[p];
-    const bool act = g0 + lane < end && pw.L >= l;
-    const int n = 2 * l + 1, K = l / 2 + 1;
-    double* v0 = sv + lane;
-    double* v1 = sv + (size_t)(2 * P.pair_lmax + 1) * G + lane;
-    double* tb = sv + (size_t)2 * (2 * P.pair_lmax + 1) * G;
-    {   // the order's table block, and the order-l block of the side's moments scaled by R^-l
-        const double* src = P.rot + rot_block_offset(l);
-        const int nb = rot_block_len(l);
-        for (int k = lane; k < nb; k += G) tb[k] = src[k];
+    // loads: the pair's order, frame and order-l moments
+    const int Lp = pw.L;
+    const size_t st = P.npairs;
+    const double* fr = P.frame + (size_t)side * FRAME_N * st + p;
+    double ec[3], es[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ec[k] = fr[(2 * k) * st];
+        es[k] = fr[(2 * k + 1) * st];
     }
-    double ir, sg, q[4], e[3][2];
-    pair_frame(pw, side, ir, sg, q);
+    const double ir = fr[6 * st];
+    const bool act = g0 + lane < end && Lp >= l;
+    const double* Q = (side ? pw.QB : pw.QA) + (act ? l * l : 0);   // order l exists when act
+    double qr[U], qi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = act ? min(wv + u * W, l) : 0;
+        qr[u] = Q[m == 0 ? 0 : 2 * m - 1];
+        qi[u] = Q[m == 0 ? 0 : 2 * m];
+    }
+    double* v = sv + lane;
+    if (wv == 0)
+#pragma unroll
+        for (int j = n; j < n + ROT_PAD; ++j) v[j * PAIR_LANES] = 0.0;
+    // Z(gamma) R^-l on the wavefront's units (e^{i m phi} by successive products along its walk)
     double sc = 1.0;
-    for (int k = 0; k < l; ++k) sc *= ir;                // R^-l by a chain of l products
-    {
-        const double* Q = (side ? pw.QB : pw.QA) + l * l;
-#pragma unroll 4
-        for (int j = 0; j < n; ++j) v0[j * G] = act ? Q[j] * sc : 0.0;
-    }
-    euler_bases(q, e);
-    // Z(gamma), in place: each lane its own entries, e^{i m gamma} by successive products
-    {
-        double c = 1.0, sn = 0.0;
-        for (int m = 1; m <= l; ++m) {
-            const double t = c * e[0][0] - sn * e[0][1];
-            sn = c * e[0][1] + sn * e[0][0];
-            c = t;
-            const double re = v0[(2 * m - 1) * G], im = v0[2 * m * G];
-            v0[(2 * m - 1) * G] = c * re - sn * im;
-            v0[2 * m * G] = sn * re + c * im;
+#pragma unroll
+    for (int k = 0; k < l; ++k) sc *= ir;
+    double c0, s0, cst, sst;
+    phase_walk(ec[0], es[0], wv, W, c0, s0, cst, sst);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = wv + u * W;
+        if (m > l) break;
+        const double re = act ? qr[u] * sc : 0.0, im = act ? qi[u] * sc : 0.0;
+        if (m == 0) {
+            v[0] = re;
+        } else {
+            v[(2 * m - 1) * PAIR_LANES] = c0 * re - s0 * im;
+            v[2 * m * PAIR_LANES] = s0 * re + c0 * im;
         }
+        cmul(c0, s0, cst, sst);
     }
     __syncthreads();
     // Z(beta) D
-    {
-        double c = 1.0, sn = 0.0;
-        v1[0] = rot_row_lanes(tb, n, K, 0, false, v0, G);
-        for (int m = 1; m <= l; ++m) {
-            const double t = c * e[1][0] - sn * e[1][1];
-            sn = c * e[1][1] + sn * e[1][0];
-            c = t;
-            const double re = rot_row_lanes(tb, n, K, 2 * m - 1, false, v0, G);
-            const double im = rot_row_lanes(tb, n, K, 2 * m, false, v0, G);
-            v1[(2 * m - 1) * G] = c * re - sn * im;
-            v1[2 * m * G] = sn * re + c * im;
+    cdptr Dr = (cdptr)P.rotr + rot_block_offset(l);
+    cdptr Di = Dr + n * (K + 1);
+    double r0[U], r1[U];
+    phase_walk(ec[1], es[1], wv, W, c0, s0, cst, sst);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = wv + u * W;
+        if (m > l) break;
+        if (m == 0) {
+            r0[u] = rot_row_lanes<K>(Dr, v);
+        } else {
+            const double re = rot_row_lanes<K>(Dr + (2 * m - 1) * (K + 1), v);
+            const double im = rot_row_lanes<K>(Dr + 2 * m * (K + 1), v);
+            r0[u] = c0 * re - s0 * im;
+            r1[u] = s0 * re + c0 * im;
+        }
+        cmul(c0, s0, cst, sst);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = wv + u * W;
+        if (m > l) break;
+        if (m == 0) {
+            v[0] = r0[u];
+        } else {
+            v[(2 * m - 1) * PAIR_LANES] = r0[u];
+            v[2 * m * PAIR_LANES] = r1[u];
         }
     }
     __syncthreads();
     // Z(alpha) D^-1, then 1/f_lm; out to the scratch [side][h][pair]
-    {
-        cdptr invf = (cdptr)P.invf + l * l;
-        double* out = P.prot + ((size_t)side * nh(P.pair_lmax) + l * l) * P.npairs + p;
-        const size_t st = P.npairs;
-        double c = 1.0, sn = 0.0;
-        const double r0 = rot_row_lanes(tb, n, K, 0, true, v1, G) * invf[0];
-        if (act) out[0] = r0;
-        for (int m = 1; m <= l; ++m) {
-            const double t = c * e[2][0] - sn * e[2][1];
-            sn = c * e[2][1] + sn * e[2][0];
-            c = t;
-            const double re = rot_row_lanes(tb, n, K, 2 * m - 1, true, v1, G);
-            const double im = rot_row_lanes(tb, n, K, 2 * m, true, v1, G);
+    cdptr invf = (cdptr)P.invf + l * l;
+    double* out = P.prot + ((size_t)side * nh(P.pair_lmax) + l * l) * st + p;
+    phase_walk(ec[2], es[2], wv, W, c0, s0, cst, sst);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int m = wv + u * W;
+        if (m > l) break;
+        if (m == 0) {
+            const double a0 = rot_row_lanes<K>(Di, v) * invf[0];
+            if (act) out[0] = a0;
+        } else {
+            const double re = rot_row_lanes<K>(Di + (2 * m - 1) * (K + 1), v);
+            const double im = rot_row_lanes<K>(Di + 2 * m * (K + 1), v);
             const double f = invf[2 * m - 1];
             if (act) {
-                out[(2 * m - 1) * st] = (c * re - sn * im) * f;
-                out[2 * m * st] = (sn * re + c * im) * f;
+                out[(2 * m - 1) * st] = (c0 * re - s0 * im) * f;
+                out[2 * m * st] = (s0 * re + c0 * im) * f;
             }
+        }
+        cmul(c0, s0, cst, sst);
+    }
+}
+
+// Binary dispatch of the block's (uniform) order onto the instantiations LO .. HI.
+template <int LO, int HI>
+__device__ __forceinline__ void rot_dispatch(int l, const DevPlan& P, int begin, int end, int side, double* sv)
+{
+    if constexpr (LO == HI) {
+        rot_order<LO>(P, begin, end, side, sv);
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (l <= MID) rot_dispatch<LO, MID>(l, P, begin, end, side, sv);
+        else rot_dispatch<MID + 1, HI>(l, P, begin, end, side, sv);
+    }
+}
+
+// Orders 0 .. LHI (a launch whose largest order is above 16 takes the second instantiation).
+template <int LHI>
+__global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_rot(DevPlan P, int begin, int end)
+{
+    extern __shared__ __align__(16) double sv[];       // v [2 pair_lmax + 1 + ROT_PAD][64]
+    const int l = P.pair_lmax - (int)blockIdx.y;         // highest orders first
+    if (l > P.gorder[blockIdx.x]) return;                // beyond the group's largest order
+    rot_dispatch<0, LHI>(l, P, begin, end, (int)blockIdx.z, sv);
+}
+template __global__ void tcm_pairs_rot<16>(DevPlan, int, int);
+template __global__ void tcm_pairs_rot<LMAX>(DevPlan, int, int);
+
+// In the frame where R lies along t = +-z (I_{L'0}(t) = (+-1)^{L'} L'!, every other M zero) and
+// with a, b the rotated moments divided by f R^l,
+//     U = (1/R) sum_m w_m (-1)^m sum_{l1, l2 >= m} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! Re(a_{l1 m} conj b_{l2 m})
+// (w_0 = 1, w_m = 2; square truncation l1, l2 <= L, triangular l1 + l2 <= L).  One workgroup
+// per (group, m): wavefront wv takes l1 = m + wv, m + wv + W, ...; it stages a_{l1 m} and
+// b_{l1 m} in LDS (every load issued first), then sums over l2 from LDS; the wavefronts'
+// partial sums are added in wavefront order.
+__global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_sum_m(DevPlan P, int begin, int end)
+{
+    extern __shared__ __align__(16) double sb[];       // fact, red [W][64], A, B [pair_lmax + 1][2][64]
+    const int lane = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y), W = PAIR_WAVES;
+    const int tid = wv * PAIR_LANES + lane;
+    const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
+    const int m = blockIdx.y, Lm = P.pair_lmax;
+    const int p = min(g0 + lane, end - 1);
+    const PairWork& pw = P.pairs[p];
+    const size_t st = P.npairs;
+    double* fs = sb;
+    double* red = sb + 2 * LMAX + 2;
+    double* sa = red + (size_t)W * PAIR_LANES + lane;
+    double* sbb = sa + (size_t)2 * (Lm + 1) * PAIR_LANES;
+    // loads: factorials, the pair's order and sign of R_z, a and b of the wavefront's orders
+    const int gL = P.gorder[blockIdx.x];
+    if (m > gL) return;                                  // past the group's largest order
+    const double fv = P.fact[min(tid, 2 * LMAX + 1)];
+    const int Lp = pw.L;
+    const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
+    const double sg = P.frame[7 * st + p];
+    const double* A = P.prot + p;
+    const double* B = P.prot + (size_t)nh(Lm) * st + p;
+    double ar[PAIR_UNITS], ai[PAIR_UNITS], br[PAIR_UNITS], bi[PAIR_UNITS];
+#pragma unroll
+    for (int u = 0; u < PAIR_UNITS; ++u) {
+        if (m + wv + u * W > gL) break;
+        const int l = m + wv + u * W;
+        const size_t h = m == 0 ? (size_t)l * l : (size_t)l * l + 2 * m - 1;
+        ar[u] = A[h * st];
+        br[u] = B[h * st];
+        ai[u] = 0.0;
+        bi[u] = 0.0;
+        if (m > 0) {
+            ai[u] = A[(h + 1) * st];
+            bi[u] = B[(h + 1) * st];
+        }
+    }
+    const bool act = g0 + lane < end && Lp >= m;
+    {
+        if (tid < 2 * LMAX + 2) fs[tid] = fv;
+        // (-1)^{l2} (+-1)^{l1+l2} = (+-1)^{l1} (-+1)^{l2}: each entry takes the sign of its
+        // order (sign changes only, no rounding); entries past the pair's order are zero
+#pragma unroll
+        for (int u = 0; u < PAIR_UNITS; ++u) {
+            const int l = m + wv + u * W;
+            if (l > gL) break;
+            const bool ok = act && l <= Lp;
+            const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
+            const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
+            sa[(2 * l) * PAIR_LANES] = ok ? s1 * ar[u] : 0.0;
+            sa[(2 * l + 1) * PAIR_LANES] = ok ? s1 * ai[u] : 0.0;
+            sbb[(2 * l) * PAIR_LANES] = ok ? s2 * br[u] : 0.0;
+            sbb[(2 * l + 1) * PAIR_LANES] = ok ? s2 * bi[u] : 0.0;
+        }
+        __syncthreads();
+        double Um = 0.0;
+#pragma unroll 1
+        for (int l1 = m + wv; l1 <= gL; l1 += W) {
+            if (!(act && l1 <= Lp)) continue;
+            const double a1 = sa[(2 * l1) * PAIR_LANES], a2 = sa[(2 * l1 + 1) * PAIR_LANES];
+            const int l2hi = tri ? Lp - l1 : Lp;
+            double cr = 0.0, ci = 0.0;                    // sum_l2 (l1+l2)! conj(signed b_{l2 m})
+#pragma unroll 4
+            for (int l2 = m; l2 <= l2hi; ++l2) {
+                const double f = fs[l1 + l2];
+                cr += f * sbb[(2 * l2) * PAIR_LANES];
+                ci -= f * sbb[(2 * l2 + 1) * PAIR_LANES];
+            }
+            Um += a1 * cr - a2 * ci;
+        }
+        red[wv * PAIR_LANES + lane] = Um;
+        __syncthreads();
+        if (wv == 0 && act) {
+            double u = red[lane];
+            for (int k = 1; k < W; ++k) u += red[k * PAIR_LANES + lane];
+            const double wt = m == 0 ? 1.0 : 2.0;
+            P.pum[(size_t)m * st + p] = (m & 1) ? -wt * u : wt * u;
         }
     }
 }
 
-// In the frame where R lies along t = +-z (I_{L'0}(t) = (+-1)^{L'} L'!, every other M zero) and
-// with a, b the rotated moments divided by f R^l,
-//     U = (1/R) sum_m w_m (-1)^m sum_{l1, l2 >= m} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! Re(a_{l1 m} conj(b_{l2 m}))
-// (w_0 = 1, w_m = 2; square truncation l1, l2 <= L, triangular l1 + l2 <= L).  One workgroup
-// per (group, m): the columns a_{. m}, b_{. m} of the group's pairs and the factorials staged in
-// LDS first (all loads in flight together), then the double sum from LDS.
-__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_sum_m(DevPlan P, int begin, int end)
+// U = (1/R) sum_{m = 0..L} (the m-terms, in order) and the status: eq. 2 (|R| > a_A + a_B,
+// strict) unless TCM_UNCHECKED; a zero R is invalid.
+__global__ __launch_bounds__(WG) void tcm_pairs_final(DevPlan P, int begin, int end)
 {
-    extern __shared__ __align__(16) double sb[];       // fact [2 LMAX + 2], then A, B [pair_lmax + 1][2][G]
-    const int lane = threadIdx.x, G = blockDim.x;
-    const int g0 = begin + (int)blockIdx.x * G;
-    const int m = blockIdx.y;
-    const int gL = group_order(P, g0, end);
-    if (m > gL) return;
-    const int p = min(g0 + lane, end - 1);
+    const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
+    if (p >= end) return;
     const PairWork& pw = P.pairs[p];
-    const int Lp = pw.L;
-    const bool act = g0 + lane < end && Lp >= m;
-    const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
-    const double sg = pw.R[2] < 0.0 ? -1.0 : 1.0;
+    const int Lp = pw.L, flags = pw.flags, out = pw.out;
+    const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
+    const double* mA = pw.metaA;
+    const double* mB = pw.metaB;
+    const double* pum = P.pum + p;
     const size_t st = P.npairs;
-    double* fs = sb;
-    double* sa = sb + 2 * LMAX + 2;
-    double* sbb = sa + (size_t)2 * (P.pair_lmax + 1) * G;
-    for (int k = lane; k < 2 * LMAX + 2; k += G) fs[k] = P.fact[k];
-    // (-1)^{l2} (+-1)^{l1+l2} = (+-1)^{l1} (-+1)^{l2}: each column is staged with the sign of its
-    // order (sign changes only, no rounding)
-    {
-        const double* A = P.prot + p;
-        const double* B = P.prot + (size_t)nh(P.pair_lmax) * st + p;
-#pragma unroll 4
-        for (int l = m; l <= gL; ++l) {
-            const int h = m == 0 ? l * l : l * l + 2 * m - 1;
-            const bool ok = act && l <= Lp;
-            const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
-            const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
-            sa[(2 * l) * G + lane] = ok ? s1 * A[h * st] : 0.0;
-            sa[(2 * l + 1) * G + lane] = (ok && m > 0) ? s1 * A[(h + 1) * st] : 0.0;
-            sbb[(2 * l) * G + lane] = ok ? s2 * B[h * st] : 0.0;
-            sbb[(2 * l + 1) * G + lane] = (ok && m > 0) ? s2 * B[(h + 1) * st] : 0.0;
-        }
+    double t[LMAX + 1];                                  // every load issued before the first use
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) t[m] = pum[(size_t)min(m, Lp) * st];
+    const double aA = mA[3], aB = mB[3];
+    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    if (!(Rn > 0.0) || (!(flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
+        P.status[out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
+        P.U[out] = __builtin_nan("");
+        return;
     }
-    __syncthreads();
-    double Um = 0.0;
-    for (int l1 = m; l1 <= gL; ++l1) {
-        if (!(act && l1 <= Lp)) continue;
-        const double ar = sa[(2 * l1) * G + lane], ai = sa[(2 * l1 + 1) * G + lane];
-        const int l2hi = tri ? Lp - l1 : Lp;
-        double cr = 0.0, ci = 0.0;                        // sum_l2 (l1+l2)! conj(signed b_{l2 m})
-#pragma unroll 4
-        for (int l2 = m; l2 <= l2hi; ++l2) {
-            const double f = fs[l1 + l2];
-            cr += f * sbb[(2 * l2) * G + lane];
-            ci -= f * sbb[(2 * l2 + 1) * G + lane];
-        }
-        Um += ar * cr - ai * ci;
-    }
-    if (act) {
-        const double wt = m == 0 ? 1.0 : 2.0;
-        P.pum[(size_t)m * st + p] = (m & 1) ? -wt * Um : wt * Um;
-    }
+    double u = 0.0;
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) u += m <= Lp ? t[m] : 0.0;   // (adding zero changes nothing)
+    P.U[out] = u / Rn;
+    P.status[out] = TCM_OK;
 }
 
 // Adaptive truncation: per pair, the smallest order L' <= L whose rigorous bound of the
@@ -623,49 +707,33 @@ __global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int
                                                        double* bout)
 {
     const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
-    if (p >= end) return;
-    PairWork& pw = const_cast<PairWork&>(P.pairs[p]);
-    const double R = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
-    const double al = pw.metaA[3] / R, be = pw.metaB[3] / R;
-    int L = pw.L;
-    double b = __builtin_inf();
-    if (al + be < 1.0) {
-        const double pre = pw.metaA[5] * pw.metaB[5] / (R * (1.0 - al - be));
-        const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
-        const double r1 = tri ? al + be : al / (1.0 - be), r2 = tri ? 0.0 : be / (1.0 - al);
-        double p1 = r1, p2 = r2;
-        for (int l = 0;; ++l, p1 *= r1, p2 *= r2) {
-            b = pre * (p1 + p2);
-            if (b <= tol || l == pw.L) {
-                L = l;
-                break;
+    int L = -1;
+    if (p < end) {
+        PairWork& pw = const_cast<PairWork&>(P.pairs[p]);
+        const double R = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
+        const double al = pw.metaA[3] / R, be = pw.metaB[3] / R;
+        L = pw.L;
+        double b = __builtin_inf();
+        if (al + be < 1.0) {
+            const double pre = pw.metaA[5] * pw.metaB[5] / (R * (1.0 - al - be));
+            const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
+            const double r1 = tri ? al + be : al / (1.0 - be), r2 = tri ? 0.0 : be / (1.0 - al);
+            double p1 = r1, p2 = r2;
+            for (int l = 0;; ++l, p1 *= r1, p2 *= r2) {
+                b = pre * (p1 + p2);
+                if (b <= tol || l == pw.L) {
+                    L = l;
+                    break;
+                }
             }
         }
+        pw.L = L;
+        Lout[pw.out] = L;
+        bout[pw.out] = b;
     }
-    pw.L = L;
-    Lout[pw.out] = L;
-    bout[pw.out] = b;
-}
-
-// U = (1/R) sum_{m = 0..L} (the m-terms, in order) and the status: eq. 2 (|R| > a_A + a_B,
-// strict) unless TCM_UNCHECKED; a zero R is invalid.
-__global__ __launch_bounds__(WG) void tcm_pairs_final(DevPlan P, int begin, int end)
-{
-    const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
-    if (p >= end) return;
-    const PairWork& pw = P.pairs[p];
-    const double Rn = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
-    const double aA = pw.metaA[3], aB = pw.metaB[3];
-    if (!(Rn > 0.0) || (!(pw.flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
-        P.status[pw.out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
-        P.U[pw.out] = __builtin_nan("");
-        return;
-    }
-    double u = 0.0;
-#pragma unroll 4
-    for (int m = 0; m <= pw.L; ++m) u += P.pum[(size_t)m * P.npairs + p];
-    P.U[pw.out] = u / Rn;
-    P.status[pw.out] = TCM_OK;
+    // a wavefront covers one group of the pair launches: its new largest order
+    const int gmax = wave_max(L);
+    if ((threadIdx.x & (PAIR_LANES - 1)) == 0 && p < end) P.gorder[(p - begin) / PAIR_LANES] = gmax;
 }
 
 // ------------------------------------------------------------------ translation scan
@@ -1431,14 +1499,20 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
 {
     if (end <= begin) return hipSuccess;
     const int Lm = P.pair_lmax;
-    const int G = pair_group(Lm);
-    const unsigned groups = (unsigned)((end - begin + G - 1) / G);
-    const size_t rot_lds = sizeof(double) * (2 * (2 * (size_t)Lm + 1) * G + rot_block_len(Lm));
-    const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + 4 * ((size_t)Lm + 1) * G);
-    hipLaunchKernelGGL(tcm_pairs_rot, dim3(groups, Lm + 1, 2), dim3(G), rot_lds, s, P, begin, end);
+    const unsigned groups = (unsigned)((end - begin + PAIR_LANES - 1) / PAIR_LANES);
+    const size_t rot_lds = sizeof(double) * (2 * (size_t)Lm + 1 + ROT_PAD) * PAIR_LANES;
+    const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + (size_t)PAIR_WAVES * PAIR_LANES +
+                                             4 * ((size_t)Lm + 1) * PAIR_LANES);
+    if (Lm <= 16)
+        hipLaunchKernelGGL(tcm_pairs_rot<16>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
+                           begin, end);
+    else
+        hipLaunchKernelGGL(tcm_pairs_rot<LMAX>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
+                           begin, end);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(G), sum_lds, s, P, begin, end);
+    hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(PAIR_LANES, PAIR_WAVES), sum_lds, s, P, begin,
+                       end);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end);
     return hipGetLastError();

@@ -344,8 +344,9 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
     const size_t nmol = mols.size(), np = pairs.size();
     int plmax = 0;
     for (const PairJob& j : pairs) plmax = std::max(plmax, j.L);
-    const size_t blob = sizeof(MolWork) * nmol + sizeof(PairWork) * np + 2 * sizeof(int32_t) * (size_t)off_s +
-                        2 * sizeof(int32_t) * (size_t)nitems + 1024;
+    const size_t blob = sizeof(MolWork) * nmol + (sizeof(PairWork) + sizeof(double) * 2 * FRAME_N) * np +
+                        sizeof(int32_t) * (np / PAIR_LANES + 1) + 2 * sizeof(int32_t) * (size_t)off_s +
+                        2 * sizeof(int32_t) * (size_t)nitems + 1536;
     const size_t np1 = np > 0 ? np : 1;
     const size_t need[10] = {blob, sizeof(int32_t),
                              sizeof(float) * (size_t)(off_f > 0 ? off_f : 1), sizeof(double) * (size_t)(off_d > 0 ? off_d : 1),
@@ -483,7 +484,10 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     const size_t o_pw = align_up(o_mw + sizeof(MolWork) * nmol, 256);
     const size_t o_sp = align_up(o_pw + sizeof(PairWork) * npairs, 256);
     const size_t o_ti = align_up(o_sp + sizeof(int32_t) * 2 * (size_t)(sp[nmol] > 0 ? sp[nmol] : 1), 256);
-    const size_t blob = align_up(o_ti + sizeof(int32_t) * 2 * (size_t)(nitems > 0 ? nitems : 1), 256);
+    const size_t o_fr = align_up(o_ti + sizeof(int32_t) * 2 * (size_t)(nitems > 0 ? nitems : 1), 256);
+    const size_t o_go = align_up(o_fr + sizeof(double) * 2 * FRAME_N * (size_t)npairs, 256);
+    const int64_t pgroups = (npairs + PAIR_LANES - 1) / PAIR_LANES;
+    const size_t blob = align_up(o_go + sizeof(int32_t) * (size_t)(pgroups > 0 ? pgroups : 1), 256);
     int rc;
     if ((rc = c->alloc(ws.blob, blob)) != TCM_OK) return rc;
     if (blob > ws.hstage_cap) {
@@ -515,6 +519,18 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
             w.has_rot = j.has_rot;
             w.out = p;
         }
+        // the rotation frames of both sides, [side][FRAME_N][pair]
+        double* fr = (double*)(h + o_fr);
+        for (int k = 0; k < npairs; ++k) {
+            double f[2][FRAME_N];
+            side_frame(pw[k].R, pw[k].quat, false, f[0]);
+            side_frame(pw[k].R, pw[k].quat, pw[k].has_rot != 0, f[1]);
+            for (int side = 0; side < 2; ++side)
+                for (int c = 0; c < FRAME_N; ++c) fr[((size_t)side * FRAME_N + c) * npairs + k] = f[side][c];
+        }
+        int32_t* go = (int32_t*)(h + o_go);
+        for (int64_t g = 0; g < pgroups; ++g) go[g] = -1;
+        for (int k = 0; k < npairs; ++k) go[k / PAIR_LANES] = std::max(go[k / PAIR_LANES], pw[k].L);
     }
     {
         int32_t* si = (int32_t*)(h + o_sp);                // (molecule, chunk) of each STATS item
@@ -560,6 +576,8 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.n_stats = sp[nmol];
     P.n_tiles = tp[nmol];
     P.err = (int32_t*)ws.sync.p;
+    P.frame = (const double*)(d + o_fr);
+    P.gorder = (int32_t*)(d + o_go);
     P.part_f = (float*)ws.part_f.p;
     P.part_d = (double*)ws.part_d.p;
     P.stats_part = (double*)ws.stats.p;
@@ -569,6 +587,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.invk = (const double*)c->t_invk.p;
     P.invf = (const double*)c->t_invf.p;
     P.rot = (const double*)c->t_rot.p;
+    P.rotr = P.rot + rot_tables_len();
     P.fact = (const double*)c->t_fact.p;
     P.prot = (double*)ws.prot.p;
     P.pum = (double*)ws.pum.p;
@@ -782,9 +801,22 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
     std::vector<double> invk, invf;
     build_norm_tables(LMAX, invk, invf);
     std::vector<double> rot = build_rotation_tables(LMAX);
-    if (rot.empty()) {                       // the rotation matrices lost their sparsity pattern
+    if (rot.size() != (size_t)rot_tables_len()) {   // the rotation matrices lost their sparsity pattern
         tcm_destroy(t);
         return TCM_EDEVICE;
+    }
+    // the row-by-row copy read by the pair launches
+    rot.resize(2 * (size_t)rot_tables_len(), 0.0);
+    for (int l = 0; l <= LMAX; ++l) {
+        const int n = 2 * l + 1, K = l / 2 + 1;
+        const double* src = rot.data() + rot_block_offset(l);
+        double* dst = rot.data() + rot_tables_len() + rot_block_offset(l);
+        for (int inv = 0; inv < 2; ++inv)
+            for (int i = 0; i < n; ++i) {
+                double* row = dst + (size_t)(inv * n + i) * (K + 1);
+                row[0] = src[inv * n + i];
+                for (int k = 0; k < K; ++k) row[1 + k] = src[2 * n + (size_t)inv * K * n + (size_t)k * n + i];
+            }
     }
     std::vector<double> fact(2 * LMAX + 2);  // k! (long double products, rounded once)
     {

@@ -172,3 +172,44 @@ def test_serving_errors(synth):
         rc, U, st, lat = tcm.tcm_poll(c.h, 10**9)
         assert rc == tcm.TCM_ENOTFOUND
         tcm.tcm_server_stop(c.h)
+
+
+def test_reuse_after_atom_eviction(synth, orc):
+    """A fragment whose atoms were evicted keeps its moment table: a request at an order it
+    holds is served from it (same result as before the eviction, a cache hit); a higher order
+    without atoms is ENOTFOUND and counted as an evicted miss; with atoms it is computed again."""
+    F = frags(synth)
+    quats = synth.quaternions(14, 2, 3)
+    with tcm.Context(0) as c:
+        tcm.tcm_server_start(c.h, max_inflight_batches=1, max_batch_pairs=4, queue_capacity=64)
+        first = run_all(c.h, [request(F, 1, 3, 12)])
+        used, _ = tcm.tcm_mem_info(c.h)
+        # room for fragments 7 and 0 only once the atoms of 1 and 3 are gone
+        gone = 32 * (F[1]["n"] + F[3]["n"])
+        # (64 KiB of slack for the launch's workspace growth, far less than either fragment's atoms)
+        tcm.tcm_set_budget(c.h, used - gone + 32 * (F[7]["n"] + F[0]["n"]) + (1 << 16))
+        other = run_all(c.h, [request(F, 7, 0, 8)])
+        s1 = tcm.tcm_server_stats(c.h)
+        again = run_all(c.h, [request(F, 1, 3, 12, with_atoms=False)] +
+                        [request(F, 1, 3, 10, quats[i], with_atoms=False) for i in range(3)])
+        higher = run_all(c.h, [request(F, 1, 3, 16, with_atoms=False)])
+        s2 = tcm.tcm_server_stats(c.h)
+        tcm.tcm_set_budget(c.h, 0)
+        refetched = run_all(c.h, [request(F, 1, 3, 16, quats[0])])
+        s3 = tcm.tcm_server_stats(c.h)
+        tcm.tcm_server_stop(c.h)
+    assert first[0][1] == 0 and other[0][1] == 0
+    assert s1["evictions"] >= 2 and s1["dropped"] == 0
+    assert all(st == 0 for _, st, _ in again)
+    assert again[0][0] == first[0][0]                       # the kept table, the same kernels
+    assert s2["cache_hits"] - s1["cache_hits"] == 8         # both sides of the four reuse requests
+    assert higher[0][1] == tcm.TCM_ENOTFOUND and np.isnan(higher[0][0])
+    assert s2["evicted_misses"] == 1 and s1["evicted_misses"] == 0
+    assert refetched[0][1] == 0 and s3["evicted_misses"] == 1
+    cA, cB = orc.centroid(F[1]["xyz"]), orc.centroid(F[3]["xyz"])
+    for L, q, U in [(10, quats[1], again[2][0]), (16, quats[0], refetched[0][0])]:
+        r = request(F, 1, 3, L, q, with_atoms=False)
+        xBr = orc.pose(F[3]["xyz"], cB, q, cB)
+        d = orc.energy(orc.moments(F[1]["xyz"], F[1]["q"], cA, L), orc.moments(xBr, F[3]["q"], cB, L),
+                       np.array(list(r.R)), L, full=True)
+        assert abs(U - d["U"]) <= 1e-5 * d["abs_sum"], (L, U, d["U"])
