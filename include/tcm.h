@@ -115,6 +115,24 @@ int tcm_moments(tcm_ctx *ctx, const double *coords, const double *charges, int64
 int tcm_pair_energy(tcm_ctx *ctx, const double *QA, double aA, const double *QB, double aB,
                     const double *R, const double *quat_b, int L, int flags, double *U_out);
 
+/* The moment pass of tcm_moments without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid the
+ * allocator).  d_x, d_y, d_z, d_q: the molecule's atoms on the device (FP64 structure of
+ * arrays, n each; the caller's, read by the kernels).  centre: host FP64[3] or NULL
+ * (centroid).  d_Q: device FP64[(L+1)^2] receiving the packed moments; d_meta: device FP64[8]
+ * receiving [0..2] the centre, [3] the radius a, [4] the internal coordinate scale ([5..7]
+ * unspecified).  Same tiling and kernels as tcm_moments: the results are the same bit for bit.
+ * Every scratch byte lives in one static 32 MiB array per device, held until the process
+ * ends; a molecule whose plan does not fit it (roughly: more than ~3800 tiles at L = 32,
+ * ~14000 at L = 16, a tile being 256 kper atoms) returns TCM_ENOMEM before anything is
+ * launched; TCM_EINVAL as tcm_moments (null pointers, n < 0, L or precision out of range,
+ * non-finite centre).  Asynchronous: the kernels are queued on the context's stream and the
+ * outputs are ready when that stream is.  All calls on one device share the array: calls that
+ * overlap on a device (two contexts' streams, or threads) race; issue them in stream order. */
+int tcm_moments_noalloc(tcm_ctx *ctx, const double *d_x, const double *d_y, const double *d_z,
+                        const double *d_q, int64_t n, const double *centre, int L, int precision,
+                        double *d_Q, double *d_meta);
+
 /* ---- device-resident molecules ---------------------------------------------------- */
 
 /* Copy a molecule's atoms (host AoS FP64) to the device, in the library's resident layout

@@ -22,7 +22,8 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
 
 SOURCES = [("tcm_tiles_f32_%s.hip" % k, True) for k in "abcd"] + \
           [("tcm_tiles_f64_%s.hip" % k, True) for k in "abcd"] + \
-          [("tcm_kernels.hip", True), ("tcm_runtime.cpp", False), ("tcm_server.cpp", False)]
+          [("tcm_kernels.hip", True), ("tcm_noalloc.hip", True), ("tcm_runtime.cpp", False),
+           ("tcm_server.cpp", False)]
 
 
 def _compile(src, device, verbose):

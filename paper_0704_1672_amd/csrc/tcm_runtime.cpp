@@ -321,7 +321,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // a larger molecule gives each item a run of consecutive chunks (the kernel derives the run
 // length from the chunk and item counts), so its centre/scale merge reads few records.
 constexpr int64_t STATS_ITEMS_MAX = 8192;
-static int64_t stats_items_for(int64_t n)
+int64_t stats_items_for(int64_t n)
 {
     const int64_t nch = n > 0 ? (n + STATS_CHUNK - 1) / STATS_CHUNK : 1;
     const int64_t per = (nch + STATS_ITEMS_MAX - 1) / STATS_ITEMS_MAX;
@@ -777,6 +777,8 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
         return TCM_EDEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) return TCM_EDEVICE;
+    // the static scratch of tcm_moments_noalloc on this device (its address, looked up once)
+    if (noalloc_init(device) != TCM_OK) return TCM_EDEVICE;
     tcm_ctx* t = new (std::nothrow) tcm_ctx();
     if (!t) return TCM_ENOMEM;
     Ctx& c = t->c;

@@ -19,6 +19,11 @@
 namespace tcm {
 
 int num_blocks_for(int prec, int L);
+// Statistics items of a molecule of n atoms (one per chunk of STATS_CHUNK atoms, at most 8192).
+int64_t stats_items_for(int64_t n);
+// Looks up, once per device (that device current), the device address of the static scratch
+// array of the allocation-free entry point.
+int noalloc_init(int device);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevPlan& P, int begin, int end, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);

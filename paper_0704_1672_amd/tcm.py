@@ -56,6 +56,7 @@ _SIGS = {
     "tcm_mem_info": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "tcm_set_budget": (C.c_int, [_vp, C.c_size_t]),
     "tcm_moments": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, C.c_int, _dp, _dp, _dp]),
+    "tcm_moments_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, _dp, C.c_int, C.c_int, _vp, _vp]),
     "tcm_pair_energy": (C.c_int, [_vp, _dp, C.c_double, _dp, C.c_double, _dp, _dp, C.c_int, C.c_int, _dp]),
     "tcm_mol_upload": (C.c_int, [_vp, _dp, _dp, C.c_int64, _dp, C.c_int, _ip64]),
     "tcm_mol_register_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, _dp, C.c_int, _ip64]),
@@ -223,6 +224,14 @@ def tcm_mol_upload(ctx, coords, charges, centre=None, precision=TCM_F32C):
     mid = C.c_int64()
     _check(lib().tcm_mol_upload(ctx, _p(x), _p(q), len(q), _p(c), precision, C.byref(mid)), "tcm_mol_upload")
     return mid.value
+
+
+def tcm_moments_noalloc(ctx, x, y, z, q, n, centre, L, precision, Q, meta):
+    """eq. (8) without allocation: device atoms (x, y, z, q), device outputs Q ((L+1)^2) and
+    meta (8: centre, radius, scale); queued on the context's stream."""
+    c = _f64(centre, (3,)) if centre is not None else None
+    _check(lib().tcm_moments_noalloc(ctx, _addr(x), _addr(y), _addr(z), _addr(q), int(n), _p(c), int(L),
+                                     int(precision), _addr(Q), _addr(meta)), "tcm_moments_noalloc")
 
 
 def tcm_mol_register_device(ctx, x, y, z, q, n, centre=None, precision=TCM_F32C):
