@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # together with the SHA-256 of every source the tile kernels are built from; it is reported
 # only while those sources are unchanged
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_uneven_batch_1024.md")
-TILE_SOURCES = ["paper_0704_1672_amd/csrc/tcm_device.h", "paper_0704_1672_amd/csrc/tcm_internal.h"] + \
+TILE_SOURCES = ["paper_0704_1672_amd/csrc/tcm_device.h", "paper_0704_1672_amd/csrc/tcm_internal.h",
+                "paper_0704_1672_amd/csrc/tcm_runtime.cpp"] + \
                [f"paper_0704_1672_amd/csrc/tcm_tiles_f32_{k}.hip" for k in "abcd"]
 
 
@@ -470,8 +471,8 @@ def forces_section(tcm, synth, torch, L=16, npose=4096, reps=10):
     return res
 
 
-def adaptive_section(tcm, synth, L=24, npose=4096, fracs=(1e-3, 1e-5)):
-    """Adaptive truncation: two 50k-charge balls, 4096 random poses at 3..6 radii of gyration,
+def adaptive_section(tcm, synth, L=24, npose=32768, fracs=(1e-3, 1e-5)):
+    """Adaptive truncation: two 50k-charge balls, 32768 random poses at 3..6 radii of gyration,
     maximum order 24, resident moments; each tolerance is a fraction of S_A S_B / median |R|
     (S = sum |q|, the scale of the rigorous bound).  Times the adaptive call against the fixed
     order-24 batch on the same requests (median of 5 calls each) and reports the orders chosen

@@ -136,10 +136,13 @@ int tcm_moments_noalloc(tcm_ctx *ctx, const double *d_x, const double *d_y, cons
 /* ---- device-resident molecules ---------------------------------------------------- */
 
 /* Copy a molecule's atoms (host AoS FP64) to the device, in the library's resident layout
- * (FP64 structure of arrays).  centre: FP64[3] or NULL (centroid).  precision: the moment
- * pass used for this molecule.  Its resident moment table (33^2 FP64, every order the
- * library accepts) is allocated here too, so later computations on it allocate nothing for
- * it.  The id stays valid until tcm_mol_release / tcm_destroy. */
+ * (FP64 structure of arrays): the charges q_i at R_i of eq. 1, whose eq. 8 moments about the
+ * centre later calls compute on demand.  centre: FP64[3] or NULL (centroid; the paper leaves
+ * the centre free, section II).  precision: the moment pass used for this molecule.  Its
+ * resident moment table (33^2 FP64, every order the library accepts) is allocated here too,
+ * so later computations on it allocate nothing for it.  The id stays valid until
+ * tcm_mol_release / tcm_destroy.  TCM_EINVAL for null pointers, n < 0 or non-finite input,
+ * TCM_ENOMEM beyond the context's budget. */
 int tcm_mol_upload(tcm_ctx *ctx, const double *coords, const double *charges, int64_t n,
                    const double *centre, int precision, tcm_mol_id *id_out);
 
@@ -172,10 +175,11 @@ typedef struct {
     int32_t flags;
 } tcm_pair_req;
 
-/* Energies of npairs requests in one batched run: moments of every molecule the batch names
- * are computed on the device (or reused, per TCM_REUSE) with the molecules of each
- * (precision, L) group in one launch, then every pair is rotated and contracted in one
- * launch.  U_out[npairs], status_out[npairs] (host).  Returns TCM_OK if
+/* Energies of npairs requests in one batched run: the eq. 8 moments of every molecule the
+ * batch names are computed on the device (or reused, per TCM_REUSE) with the molecules of each
+ * (precision, L) group in one launch, then every pair's eq. 9 (square truncation, or
+ * triangular with TCM_TRIANGULAR) is evaluated after the eq. 2 test (|R0| > a_A + a_B, else
+ * TCM_EDOMAIN for that item).  U_out[npairs], status_out[npairs] (host).  Returns TCM_OK if
  * every item succeeded, else the first failing item's code.  Synchronous. */
 int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double *U_out,
                      int32_t *status_out);

@@ -521,9 +521,10 @@ __device__ __forceinline__ void tile_item_entry(const DevPlan& P, int mol, int j
 // workgroup per item (the grid is the item count), so the hardware dispatcher hands out the
 // items as slots free up -- in blockIdx order, i.e. in decreasing cost, so the last items to
 // start are the cheapest -- and the workgroups of concurrently running launches (the groups of
-// other orders on forked streams) interleave with these as the slots free up.  The order does
-// not touch any result: each item writes its own partial slot and the partials are merged in
-// tile order afterwards.
+// other orders on forked streams) interleave with these as the slots free up.  The listing puts
+// the m-blocks of one tile on one XCD (positions b with the same b mod 8, back to back) and
+// may hold empty positions (molecule -1).  The order does not touch any result: each item
+// writes its own partial slot and the partials are merged in tile order afterwards.
 template <typename F, int L>
 __global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int begin, int end)
 {
@@ -532,6 +533,7 @@ __global__ __launch_bounds__(WG) void tcm_tiles(DevPlan P, int begin, int end)
     if (item >= end) return;
     const int j = item - P.n_stats;
     const int mol = __builtin_amdgcn_readfirstlane(P.tile_items[2 * j]);
+    if (mol < 0) return;                                 // a padding position of the listing
     tile_item_entry<F, L>(P, mol, __builtin_amdgcn_readfirstlane(P.tile_items[2 * j + 1]), smem);
 }
 

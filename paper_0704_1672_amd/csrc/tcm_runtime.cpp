@@ -335,7 +335,7 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
         const int kper = c->kper_for(j.prec, j.L, j.n);
         const int64_t ta = (int64_t)WG * kper;
         const int64_t nt = j.n > 0 ? (j.n + ta - 1) / ta : 1;
-        nitems += nt * num_blocks_for(j.prec, j.L);
+        nitems += nt * num_blocks_for(j.prec, j.L) + 8 * num_blocks_for(j.prec, j.L);   // with the padding
         const int64_t ns = stats_items_for(j.n);
         if (j.prec == TCM_F32C) off_f += 2 * nt * nh(j.L); else off_d += nt * nh(j.L);
         off_s += ns;
@@ -435,50 +435,66 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         for (int k = 1; k <= pair_lmax + 1; ++k) start[k] += start[k - 1];
         for (int p = 0; p < npairs; ++p) porder[start[pair_lmax - pairs_in[p].L]++] = p;
     }
-    // tile items of each (precision, L) group in decreasing estimated cost (per-thread
-    // instructions: atoms x (recurrence + set-up) + the compensated reduction)
-    const int64_t nitems = tp[nmol];
-    std::vector<int32_t> items(2 * (size_t)nitems);
+    // tile items of each (precision, L) group: the tiles in decreasing estimated cost (per-thread
+    // instructions: atoms x (recurrence + set-up) + the compensated reduction, summed over the
+    // tile's m-blocks), and the m-blocks of one tile on one XCD back to back: workgroup b of a
+    // launch runs on XCD b mod 8, so tile j of the group takes the positions
+    // 8 (nblk floor(j / 8) + blk) + j mod 8 -- its atoms are read from HBM once and the other
+    // m-blocks find them in that XCD's L2.  Positions past the group's tiles (the last round of
+    // eight) hold no item (molecule -1).
+    std::vector<int64_t> gbeg, gend;                    // item range of each group
+    std::vector<int32_t> items;
     {
-        std::vector<std::pair<int64_t, int64_t>> key;     // (-cost, item)
+        std::vector<std::pair<int64_t, int64_t>> key;     // (-cost, tile: molecule << 32 | t)
         int i0 = 0;
+        int64_t pos0 = 0;
         while (i0 < nmol) {
             int i1 = i0;
             while (i1 < nmol && mols[i1].prec == mols[i0].prec && mols[i1].L == mols[i0].L) ++i1;
             key.clear();
+            const int nblk = mw[i0].nblk;
             for (int i = i0; i < i1; ++i) {
                 const MolWork& w = mw[i];
                 const Partition part = make_partition(w.L, w.prec == TCM_F32C ? BUDGET_F32 : BUDGET_F64);
                 for (int t = 0; t < w.ntiles; ++t) {
                     const int64_t span = std::min<int64_t>(w.n - (int64_t)t * WG * w.kper, (int64_t)WG * w.kper);
                     const int64_t per_thread = (std::max<int64_t>(span, 0) + WG - 1) / WG;
+                    int64_t cost = 0;
                     for (int b = 0; b < w.nblk; ++b) {
                         int acc = 0;
                         for (int m = part.start[b]; m < part.start[b + 1]; ++m) acc += chain_cost(w.L, m);
-                        const int64_t cost = per_thread * (5 * acc / 2 + 40) + 9 * acc + 300;
-                        key.push_back({-cost, (int64_t)tp[i] + (int64_t)t * w.nblk + b});
+                        cost += per_thread * (5 * acc / 2 + 40) + 9 * acc + 300;
                     }
+                    key.push_back({-cost, ((int64_t)i << 32) | t});
                 }
             }
             std::stable_sort(key.begin(), key.end(),
                              [](const std::pair<int64_t, int64_t>& u, const std::pair<int64_t, int64_t>& v) {
                                  return u.first < v.first;
                              });
-            int64_t pos = tp[i0];
-            for (const auto& kv : key) {
-                // owner of item kv.second: the molecule whose prefix range holds it
-                int lo = i0, hi = i1;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) / 2;
-                    if (tp[mid] <= kv.second) lo = mid; else hi = mid;
-                }
-                items[2 * pos] = lo;
-                items[2 * pos + 1] = (int32_t)(kv.second - tp[lo]);
-                ++pos;
+            const int64_t T = (int64_t)key.size();
+            const int64_t ng = 8 * (int64_t)nblk * ((T + 7) / 8);
+            if (pos0 + ng > (1 << 30)) return TCM_EINVAL;
+            items.resize(2 * (size_t)(pos0 + ng));
+            for (int64_t q = pos0; q < pos0 + ng; ++q) {
+                items[2 * q] = -1;
+                items[2 * q + 1] = 0;
             }
+            for (int64_t jt = 0; jt < T; ++jt) {
+                const int i = (int)(key[jt].second >> 32), t = (int)(key[jt].second & 0xffffffff);
+                for (int b = 0; b < nblk; ++b) {
+                    const int64_t q = pos0 + 8 * ((int64_t)nblk * (jt / 8) + b) + jt % 8;
+                    items[2 * q] = i;
+                    items[2 * q + 1] = t * nblk + b;
+                }
+            }
+            gbeg.push_back(pos0);
+            gend.push_back(pos0 + ng);
+            pos0 += ng;
             i0 = i1;
         }
     }
+    const int64_t nitems = (int64_t)items.size() / 2;
     // blob layout
     const size_t o_mw = 0;
     const size_t o_pw = align_up(o_mw + sizeof(MolWork) * nmol, 256);
@@ -543,11 +559,12 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     if (nitems) std::memcpy(h + o_ti, items.data(), sizeof(int32_t) * 2 * (size_t)nitems);
     bp.groups.clear();
     for (int i = 0; i < nmol; ++i) {
-        if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L)
-            bp.groups.push_back({mols[i].prec, mols[i].L, tp[i], tp[i], i, i, sp[i], sp[i], 0.0});
+        if (bp.groups.empty() || bp.groups.back().prec != mols[i].prec || bp.groups.back().L != mols[i].L) {
+            const int64_t g = (int64_t)bp.groups.size();
+            bp.groups.push_back({mols[i].prec, mols[i].L, (int32_t)gbeg[g], (int32_t)gend[g], i, i, sp[i], sp[i], 0.0});
+        }
         BuiltPlan::Group& G = bp.groups.back();
         G.work += 6.0 * (mols[i].L + 1) * (mols[i].L + 2) * (double)mols[i].n;
-        G.end = tp[i + 1];
         G.mol_end = i + 1;
         G.stats_end = sp[i + 1];
     }
@@ -574,7 +591,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.npairs = npairs;
     P.pair_lmax = pair_lmax;
     P.n_stats = sp[nmol];
-    P.n_tiles = tp[nmol];
+    P.n_tiles = (int32_t)nitems;
     P.err = (int32_t*)ws.sync.p;
     P.frame = (const double*)(d + o_fr);
     P.gorder = (int32_t*)(d + o_go);
@@ -592,7 +609,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.prot = (double*)ws.prot.p;
     P.pum = (double*)ws.pum.p;
     bp.n_stats = P.n_stats;
-    bp.n_tiles = P.n_tiles;
+    bp.n_tiles = tp[nmol];                                  // work items (no padding positions)
     bp.npairs = npairs;
     bp.n_items = P.n_stats + P.n_tiles + npairs;
     bp.sync_ints = sync_ints;
