@@ -654,7 +654,7 @@ def orientation_scan_section(tcm, synth, torch, steps=20):
            "phase_ms": {"stats": ph[0], "moment_tiles": ph[1], "moment_finalise": ph[2], "pairs": ph[3]},
            "pair_roofline": {"bound": "fp64 vector", "achieved": pair_tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": pair_tf / FP64_VECTOR_PEAK_TFLOPS,
-                             "work": "2 (L+1)^4 flops per posed pair (eq. 9 as written), per launch of tcm_pairs"},
+                             "work": "2 (L+1)^4 flops per posed pair (eq. 9 as written), over the pair phase (rotation, contraction and final-sum launches)"},
            "error_vs_oracle": e}
     tcm.tcm_mol_release(ctx.h, mA)
     tcm.tcm_mol_release(ctx.h, mB)
@@ -747,6 +747,9 @@ def main():
     ap.add_argument("--large-molecule", type=int, default=0, metavar="N",
                     help="only time the moment pass of one molecule of N atoms (L = 8, uniform random "
                          "coordinates and charges in device memory) by phase, and exit")
+    ap.add_argument("--only", choices=["chain-pair", "orientation-scan", "serving", "scan", "all-pairs", "forces",
+                                       "adaptive", "single-pair"], default=None,
+                    help="run one section alone (no batch step, no JSON contract line; for profiling) and exit")
     ap.add_argument("--alu-calibration", action="store_true",
                     help="only measure the sustained plain FP32 and FP64 FMA rates and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -772,6 +775,18 @@ def main():
     from paper_0704_1672_amd import synth, tcm
     if args.large_molecule > 0:
         print(json.dumps(large_molecule(tcm, torch, args.large_molecule)), flush=True)
+        return
+    if args.only:
+        sec = {"chain-pair": lambda: chain_pair_section(tcm, synth, check=False),
+               "orientation-scan": lambda: orientation_scan_section(tcm, synth, torch),
+               "serving": lambda: serving_section(tcm, synth, torch, nreq=args.serve_requests,
+                                                  inflight=args.serve_inflight, batch=args.serve_batch),
+               "scan": lambda: scan_section(tcm, synth, torch, check=False),
+               "all-pairs": lambda: all_pairs_section(tcm, synth),
+               "forces": lambda: forces_section(tcm, synth, torch),
+               "adaptive": lambda: adaptive_section(tcm, synth),
+               "single-pair": lambda: single_pair_section(tcm, synth, check=False)}[args.only]
+        print(json.dumps({"section": args.only, "result": sec()}), flush=True)
         return
     if args.alu_calibration:
         ctx = tcm.Context(0)

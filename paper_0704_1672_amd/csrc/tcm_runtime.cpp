@@ -506,6 +506,16 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     const size_t blob = align_up(o_go + sizeof(int32_t) * (size_t)(pgroups > 0 ? pgroups : 1), 256);
     int rc;
     if ((rc = c->alloc(ws.blob, blob)) != TCM_OK) return rc;
+    // the staging buffer may still feed the previous plan's copy: wait for that copy only (not
+    // for the rest of the stream, where a server slot has just queued its atom copies)
+    if (!ws.staged) {
+        if (hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming) != hipSuccess) {
+            ws.staged = nullptr;
+            return TCM_EDEVICE;
+        }
+    } else if (hipEventSynchronize(ws.staged) != hipSuccess) {
+        return TCM_EDEVICE;
+    }
     if (blob > ws.hstage_cap) {
         if (ws.hstage) (void)hipHostFree(ws.hstage);
         ws.hstage = nullptr;
@@ -516,8 +526,6 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         }
         ws.hstage_cap = blob;
     }
-    // the staging buffer may still feed an earlier asynchronous copy
-    if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
     {
@@ -580,7 +588,9 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     const size_t np1 = npairs > 0 ? (size_t)npairs : 1;
     if ((rc = c->alloc(ws.prot, sizeof(double) * 2 * (size_t)nh(pair_lmax) * np1)) != TCM_OK) return rc;
     if ((rc = c->alloc(ws.pum, sizeof(double) * (size_t)(pair_lmax + 1) * np1)) != TCM_OK) return rc;
-    if (hipMemcpyAsync(ws.blob.p, ws.hstage, blob, hipMemcpyHostToDevice, s) != hipSuccess) return TCM_EDEVICE;
+    if (hipMemcpyAsync(ws.blob.p, ws.hstage, blob, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(ws.staged, s) != hipSuccess)
+        return TCM_EDEVICE;
     char* d = (char*)ws.blob.p;
     DevPlan& P = bp.P;
     P.mols = (const MolWork*)(d + o_mw);
@@ -757,9 +767,12 @@ void free_workspace(Ctx* c, Workspace& ws)
     c->release(ws.blob); c->release(ws.sync); c->release(ws.part_f); c->release(ws.part_d);
     c->release(ws.stats); c->release(ws.r2); c->release(ws.outU); c->release(ws.outS);
     c->release(ws.prot); c->release(ws.pum);
+    if (ws.staged) (void)hipEventSynchronize(ws.staged);
     if (ws.hstage) (void)hipHostFree(ws.hstage);
     ws.hstage = nullptr;
     ws.hstage_cap = 0;
+    if (ws.staged) (void)hipEventDestroy(ws.staged);
+    ws.staged = nullptr;
 }
 
 }  // namespace tcm

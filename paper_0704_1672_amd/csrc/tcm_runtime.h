@@ -109,6 +109,7 @@ struct Workspace {
     DevBuf blob, sync, part_f, part_d, stats, r2, outU, outS, prot, pum;
     void* hstage = nullptr;        // pinned host staging for the blob
     size_t hstage_cap = 0;
+    hipEvent_t staged = nullptr;   // recorded after the last copy out of hstage
     hipStream_t aux[NLANES] = {};  // the lanes of tile launches (forked from the run's stream)
     hipEvent_t fork = nullptr;
     hipEvent_t join[NLANES] = {};
