@@ -736,6 +736,38 @@ __global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int
     if ((threadIdx.x & (PAIR_LANES - 1)) == 0 && p < end) P.gorder[(p - begin) / PAIR_LANES] = gmax;
 }
 
+// Regrouping after the order choice: the pairs listed again by decreasing chosen order, so that
+// a group of PAIR_LANES pairs runs to (about) the orders its pairs need.  cnt[0 .. LMAX] counts
+// the pairs of each order (zeroed before), cnt[LMAX + 1 ..] are the placement cursors.  The
+// place of a pair within its order is taken by an atomic (any order: a pair's arithmetic is its
+// own lane's and its result goes to U[out], so its value does not depend on where it lands).
+__global__ __launch_bounds__(WG) void tcm_pairs_count(DevPlan P, int npairs, int32_t* cnt)
+{
+    const int p = (int)(blockIdx.x * WG + threadIdx.x);
+    if (p < npairs) atomicAdd(&cnt[P.pairs[p].L], 1);
+}
+
+__global__ __launch_bounds__(WG) void tcm_pairs_regroup(DevPlan P, int npairs, int32_t* cnt, PairWork* pairs2,
+                                                        double* frame2)
+{
+    const int p = (int)(blockIdx.x * WG + threadIdx.x);
+    if (p >= npairs) return;
+    const PairWork w = P.pairs[p];
+    int base = 0;
+    for (int L = LMAX; L > w.L; --L) base += cnt[L];
+    const int q = base + atomicAdd(&cnt[LMAX + 1 + w.L], 1);
+    pairs2[q] = w;
+    const size_t st = (size_t)npairs;
+#pragma unroll
+    for (int c = 0; c < 2 * FRAME_N; ++c) frame2[c * st + q] = P.frame[c * st + p];
+}
+
+__global__ __launch_bounds__(WG) void tcm_pairs_group_orders(const PairWork* pairs2, int npairs, int32_t* gorder)
+{
+    const int g = (int)(blockIdx.x * WG + threadIdx.x);
+    if (g * PAIR_LANES < npairs) gorder[g] = pairs2[g * PAIR_LANES].L;    // the first is the largest
+}
+
 // ------------------------------------------------------------------ translation scan
 // Regrouping eq. (9) by L' = l1 + l2 and M = m1 + m2 (the geometric factor depends on them
 // only) gives, for B translated without rotation,
@@ -1524,6 +1556,23 @@ hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol,
     if (end <= begin) return hipSuccess;
     hipLaunchKernelGGL(tcm_pairs_choose, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end,
                        tol, Lout, bout);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, int32_t* cnt, PairWork* pairs2, double* frame2,
+                                int32_t* gorder2, hipStream_t s)
+{
+    if (npairs <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((npairs + WG - 1) / WG);
+    hipError_t e;
+    if ((e = launch_clear(cnt, 2 * (LMAX + 1), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(tcm_pairs_count, dim3(grid), dim3(WG), 0, s, P, npairs, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(tcm_pairs_regroup, dim3(grid), dim3(WG), 0, s, P, npairs, cnt, pairs2, frame2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int groups = (npairs + PAIR_LANES - 1) / PAIR_LANES;
+    hipLaunchKernelGGL(tcm_pairs_group_orders, dim3((unsigned)((groups + WG - 1) / WG)), dim3(WG), 0, s, pairs2,
+                       npairs, gorder2);
     return hipGetLastError();
 }
 

@@ -1778,9 +1778,22 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
     const int npj = (int)rp.pj.size();
-    if ((rc = c.alloc(c.adapt, (sizeof(double) + sizeof(int32_t)) * (size_t)(npj > 0 ? npj : 1))) != TCM_OK) return rc;
-    double* dB = (double*)c.adapt.p;
-    int32_t* dL = (int32_t*)(dB + (npj > 0 ? npj : 1));
+    // per pair: bound, chosen order, the pair record and frames listed again by chosen order;
+    // then the group orders of that listing and the regrouping's counters
+    const size_t np1 = npj > 0 ? (size_t)npj : 1, ngr = (np1 + PAIR_LANES - 1) / PAIR_LANES;
+    const size_t o_L = align_up(sizeof(double) * np1, 256);
+    const size_t o_pw = align_up(o_L + sizeof(int32_t) * np1, 256);
+    const size_t o_fr = align_up(o_pw + sizeof(PairWork) * np1, 256);
+    const size_t o_go = align_up(o_fr + sizeof(double) * 2 * FRAME_N * np1, 256);
+    const size_t o_cn = align_up(o_go + sizeof(int32_t) * ngr, 256);
+    if ((rc = c.alloc(c.adapt, o_cn + sizeof(int32_t) * 2 * (LMAX + 1))) != TCM_OK) return rc;
+    char* ad = (char*)c.adapt.p;
+    double* dB = (double*)ad;
+    int32_t* dL = (int32_t*)(ad + o_L);
+    DevPlan P2 = bp.P;                                   // the contraction over the regrouped listing
+    P2.pairs = (const PairWork*)(ad + o_pw);
+    P2.frame = (const double*)(ad + o_fr);
+    P2.gorder = (int32_t*)(ad + o_go);
     if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;
     std::vector<Mol*> need;
     for (int64_t i = 0; i < np; ++i) {
@@ -1798,7 +1811,9 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
         return rc;
     }
     if (launch_pairs_choose(bp.P, 0, npj, tol, dL, dB, s) != hipSuccess ||
-        launch_pairs(bp.P, 0, npj, s) != hipSuccess)
+        launch_pairs_regroup(bp.P, npj, (int32_t*)(ad + o_cn), (PairWork*)(ad + o_pw), (double*)(ad + o_fr),
+                             P2.gorder, s) != hipSuccess ||
+        launch_pairs(P2, 0, npj, s) != hipSuccess)
         return TCM_EDEVICE;
     std::vector<double> U(npj > 0 ? npj : 1), B(npj > 0 ? npj : 1);
     std::vector<int32_t> st(npj > 0 ? npj : 1), Lc(npj > 0 ? npj : 1);

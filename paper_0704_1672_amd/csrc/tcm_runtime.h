@@ -30,6 +30,10 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);
 // Adaptive truncation: lowers each pair's order in the plan to the smallest meeting tol.
 hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol, int32_t* Lout, double* bout,
                                hipStream_t s);
+// Lists the pairs again by decreasing (chosen) order into pairs2 / frame2 and writes the group
+// orders of that listing; cnt: 2 (LMAX + 1) ints of scratch.
+hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, int32_t* cnt, PairWork* pairs2, double* frame2,
+                                int32_t* gorder2, hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
 hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s);

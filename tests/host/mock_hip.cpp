@@ -103,6 +103,18 @@ hipError_t launch_atom_forces(const double*, int, int, const double*, const doub
 hipError_t launch_pairs_choose(const DevPlan& P, int b, int e, double, int32_t* Lout, double* bout, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; Lout[w.out] = w.L; bout[w.out] = 0.0; }
     return 0; }
+hipError_t launch_pairs_regroup(const DevPlan& P, int n, int32_t*, PairWork* pairs2, double* frame2, int32_t* go,
+                                hipStream_t) {
+    int q = 0;
+    for (int L = LMAX; L >= 0; --L)
+        for (int p = 0; p < n; ++p)
+            if (P.pairs[p].L == L) {
+                pairs2[q] = P.pairs[p];
+                for (int c = 0; c < 2 * FRAME_N; ++c) frame2[(size_t)c * n + q] = P.frame[(size_t)c * n + p];
+                ++q;
+            }
+    for (int g = 0; g * PAIR_LANES < n; ++g) go[g] = pairs2[g * PAIR_LANES].L;
+    return 0; }
 hipError_t launch_pairs(const DevPlan& P, int b, int e, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; double s = w.QA[0] + 1e-3 * w.QB[0];
         double R = sqrt(w.R[0]*w.R[0]+w.R[1]*w.R[1]+w.R[2]*w.R[2]);
