@@ -81,7 +81,8 @@ struct DevPlan {
     double* stats_part;            // STATS partials, 10 doubles per item
     double* r2_part;               // per-tile max |r|^2 (FP64)
     double* prot;                  // pair launches: rotated moments [2][nh(pair_lmax)][npairs]
-    double* pum;                   // pair launches: per-m partial energies [pair_lmax+1][npairs]
+    double* pum;                   // pair launches: per-m partial energies [pair_lmax+1][npairs], then
+                                   // per pair |R| or its failure status (a negative code)
     // outputs
     double* U;
     int32_t* status;
@@ -93,6 +94,7 @@ struct DevPlan {
     const double* fact;            // k!, k <= 2 LMAX + 1
     const double* frame;           // per pair and side, [2][FRAME_N][npairs]: see side_frame
     int32_t* gorder;               // largest order of each group of PAIR_LANES pairs
+    int32_t gorder_uniform;        // 1: every group's largest order is pair_lmax (gorder not read)
 };
 
 // Pair launches take the pairs PAIR_LANES at a time, one pair per lane of a wavefront.

@@ -389,12 +389,30 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 //                    table rotated into the frame where R lies along z (B's pose folded in; the
 //                    Euler phases come from the plan, computed by the host), scaled by
 //                    R^-l / f_lm, written to the plan's scratch [side][h][pair];
-//   tcm_pairs_sum_m  (group, m): for each pair the m-term of the axial contraction;
-//   tcm_pairs_final  (pair): U = (sum over m in order) / R and the status (eq. 2 checked here).
+//   tcm_pairs_sum_w  (group, m), one wavefront, largest order up to SW_L, or tcm_pairs_sum_m
+//                    (group, m), four wavefronts, larger orders: for each pair the m-term of the
+//                    axial contraction;
+//   tcm_pairs_final  (pair): U = (sum over m) / R and the status (eq. 2 checked here).
 // Each pair's arithmetic is its own lane's, in a fixed order: a result does not depend on the
-// other pairs of the launch.
-constexpr int PAIR_UNITS = (LMAX + PAIR_WAVES) / PAIR_WAVES;     // m-units of a wavefront, m = wv + u W
+// other pairs of the launch, nor on which of the two contraction paths the launch takes.
 constexpr int ROT_PAD = 4;        // zero rows after an LDS vector: the slots past a row's count read there
+
+// The largest order of the workgroup's group of pairs: the plan's largest when every group
+// reaches it (no load), else from the plan.
+__device__ __forceinline__ int group_order(const DevPlan& P)
+{
+    return P.gorder_uniform ? P.pair_lmax : P.gorder[blockIdx.x];
+}
+
+// The pair's |R| for U = u / |R|, or its status when it fails: eq. 2 (|R| > a_A + a_B, strict)
+// unless TCM_UNCHECKED (TCM_EDOMAIN), a zero R (TCM_EINVAL); stored in the last row of pum.
+__device__ __forceinline__ double pair_check(const PairWork& pw)
+{
+    const double Rn = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
+    if (!(Rn > 0.0)) return (double)TCM_EINVAL;
+    if (!(pw.flags & TCM_UNCHECKED) && !(Rn > pw.metaA[3] + pw.metaB[3])) return (double)TCM_EDOMAIN;
+    return Rn;
+}
 
 // Largest of v over the wavefront (the same value in every lane).
 __device__ __forceinline__ int wave_max(int v)
@@ -571,7 +589,7 @@ __global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_rot(DevPlan
 {
     extern __shared__ __align__(16) double sv[];       // v [2 pair_lmax + 1 + ROT_PAD][64]
     const int l = P.pair_lmax - (int)blockIdx.y;         // highest orders first
-    if (l > P.gorder[blockIdx.x]) return;                // beyond the group's largest order
+    if (l > group_order(P)) return;                      // beyond the group's largest order
     rot_dispatch<0, LHI>(l, P, begin, end, (int)blockIdx.z, sv);
 }
 template __global__ void tcm_pairs_rot<16>(DevPlan, int, int);
@@ -579,122 +597,250 @@ template __global__ void tcm_pairs_rot<LMAX>(DevPlan, int, int);
 
 // In the frame where R lies along t = +-z (I_{L'0}(t) = (+-1)^{L'} L'!, every other M zero) and
 // with a, b the rotated moments divided by f R^l,
-//     U = (1/R) sum_m w_m (-1)^m sum_{l1, l2 >= m} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! Re(a_{l1 m} conj b_{l2 m})
-// (w_0 = 1, w_m = 2; square truncation l1, l2 <= L, triangular l1 + l2 <= L).  One workgroup
-// per (group, m): wavefront wv takes l1 = m + wv, m + wv + W, ...; it stages a_{l1 m} and
-// b_{l1 m} in LDS (every load issued first), then sums over l2 from LDS; the wavefronts'
-// partial sums are added in wavefront order.
+//     U = (1/R) sum_m w_m (-1)^m T_m,   T_m = sum_{l1, l2 >= m} (-1)^{l2} (+-1)^{l1+l2} (l1+l2)! Re(a_{l1 m} conj b_{l2 m})
+// (w_0 = 1, w_m = 2; square truncation l1, l2 <= L, triangular l1 + l2 <= L).  Both contraction
+// paths add the same terms in the same order, so that a pair's result does not depend on which
+// one its launch takes.  With a and b signed, (+-1)^{l1} and (-+1)^{l2}, and j = l2 - m:
+//     d_j = sum_{l1 = m, m+1, ...} (l1 + l2)! a_{l1 m}    (a chain of fused multiply-adds from 0),
+//     e_j = fma(Re d_j, Re b_{l2 m}, Im d_j Im b_{l2 m})   (e_j = Re d_j Re b_{l2 m} for m = 0),
+//     T_m = (S_0 + S_1) + (S_2 + S_3),   S_r = sum of e_j over j = r mod 4, in increasing j,
+//     U = [(V_0 + V_1) + (V_2 + V_3)] / R,   V_r = sum of w_m (-1)^m T_m over m = r mod 4, in
+// increasing m.  The four partial sums and the independent d_j keep several multiply-add chains
+// in flight: a dependent FP64 multiply-add waits about forty clocks for its predecessor.
+// Terms past a pair's order are exact zeros, so the group's largest order does not change them.
+
+// Largest order up to SW_L: one wavefront per (group, m).  The a_{l1 m} and b_{l2 m} of its 64
+// pairs (l1, l2 = m .. m + SW_L) are held in registers, zero past the group's largest order
+// (the terms they add are exact zeros), and the factorials (2m)! .. (2m + 2 SW_L)! in scalar
+// registers; every loop is unrolled, and the d_j of JB consecutive j are formed together.  The
+// terms and their order are those of the larger-order path.
+constexpr int SW_L = 16, SW_N = SW_L + 1;
+
+template <bool IM, bool MASK>
+__device__ __forceinline__ double sw_sum(const double* ar, const double* ai, const double* br, const double* bi,
+                                         cdptr f2, int tl)
+{
+#pragma clang fp contract(off)                           // e_j, S_r and T_m exactly as written
+    constexpr int N = SW_N, JB = 4;
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j0 = 0; j0 < N; j0 += JB) {
+        double dr[JB], di[JB];
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) dr[jj] = di[jj] = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                if (j0 + jj >= N) continue;
+                double f = f2[k + j0 + jj];
+                if (MASK) f = k + j0 + jj <= tl ? f : 0.0;
+                dr[jj] = fma(f, ar[k], dr[jj]);
+                if (IM) di[jj] = fma(f, ai[k], di[jj]);
+            }
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) {
+            const int j = j0 + jj;
+            if (j >= N) continue;
+            S[j & 3] += IM ? fma(dr[jj], br[j], di[jj] * bi[j]) : dr[jj] * br[j];
+        }
+    }
+    return (S[0] + S[1]) + (S[2] + S[3]);
+}
+
+__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_sum_w(DevPlan P, int begin, int end)
+{
+    constexpr int N = SW_N;
+    const int lane = threadIdx.x;
+    const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
+    const int m = blockIdx.y;
+    const int p = min(g0 + lane, end - 1);
+    const bool valid = g0 + lane < end;
+    const size_t st = P.npairs;
+    // loads: the group's largest order; the pair's order, flags and sign of R_z; a and b of m
+    const int gL = group_order(P);
+    if (m > gL) return;                                  // past the group's largest order
+    const PairWork& pw = P.pairs[p];
+    const int Lp = pw.L;
+    const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
+    const double sg = P.frame[7 * st + p];
+    const double* A = P.prot + p;
+    const double* B = P.prot + (size_t)nh(P.pair_lmax) * st + p;
+    double ar[N], ai[N], br[N], bi[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int l = m + k;
+        ar[k] = ai[k] = br[k] = bi[k] = 0.0;
+        if (l <= gL) {
+            const size_t h = m == 0 ? (size_t)l * l : (size_t)l * l + 2 * m - 1;
+            ar[k] = A[h * st];
+            br[k] = B[h * st];
+            if (m > 0) {
+                ai[k] = A[(h + 1) * st];
+                bi[k] = B[(h + 1) * st];
+            }
+        }
+    }
+    // (+-1)^{l1} on a, (-+1)^{l2} on b; zero past the pair's order
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int l = m + k;
+        const bool ok = valid && l <= Lp;
+        const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
+        const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
+        ar[k] = ok ? s1 * ar[k] : 0.0;
+        ai[k] = ok ? s1 * ai[k] : 0.0;
+        br[k] = ok ? s2 * br[k] : 0.0;
+        bi[k] = ok ? s2 * bi[k] : 0.0;
+    }
+    const bool mask = __any(valid && tri);               // some lane truncates triangularly
+    const int tl = tri ? Lp - 2 * m : 2 * LMAX;
+    const cdptr f2 = (cdptr)P.fact + 2 * m;
+    double T;
+    if (m == 0) T = mask ? sw_sum<false, true>(ar, ai, br, bi, f2, tl) : sw_sum<false, false>(ar, ai, br, bi, f2, tl);
+    else T = mask ? sw_sum<true, true>(ar, ai, br, bi, f2, tl) : sw_sum<true, false>(ar, ai, br, bi, f2, tl);
+    if (valid) {
+        const double wt = m == 0 ? 1.0 : 2.0;
+        P.pum[(size_t)m * st + p] = (m & 1) ? -wt * T : wt * T;
+        if (m == 0) P.pum[(size_t)(P.pair_lmax + 1) * st + p] = pair_check(pw);
+    }
+}
+
+// Orders above SW_L: one workgroup per (group, m).  The signed a_{l1 m} and b_{l2 m} are staged
+// in LDS, wavefront w forms d_j for j = w, w + W, ..., and wavefront 0 forms T_m from them and
+// writes the signed, weighted T_m for tcm_pairs_final.
 __global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_sum_m(DevPlan P, int begin, int end)
 {
-    extern __shared__ __align__(16) double sb[];       // fact, red [W][64], A, B [pair_lmax + 1][2][64]
+    extern __shared__ __align__(16) double sb[];       // fact [2 LMAX + 2], a then d, b: [pair_lmax + 1][2][64]
+    constexpr int W = PAIR_WAVES, UN = (LMAX + W) / W;  // k or j of a wavefront: wv + u W, u < UN
     const int lane = threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y), W = PAIR_WAVES;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int tid = wv * PAIR_LANES + lane;
     const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
     const int m = blockIdx.y, Lm = P.pair_lmax;
     const int p = min(g0 + lane, end - 1);
+    const bool valid = g0 + lane < end;
     const PairWork& pw = P.pairs[p];
     const size_t st = P.npairs;
     double* fs = sb;
-    double* red = sb + 2 * LMAX + 2;
-    double* sa = red + (size_t)W * PAIR_LANES + lane;
-    double* sbb = sa + (size_t)2 * (Lm + 1) * PAIR_LANES;
-    // loads: factorials, the pair's order and sign of R_z, a and b of the wavefront's orders
-    const int gL = P.gorder[blockIdx.x];
+    double* sa = sb + 2 * LMAX + 2 + lane;               // a_{m+k, m}, later d_{m+j}: [k][re, im][64]
+    double* sbv = sa + (size_t)2 * (Lm + 1) * PAIR_LANES;  // b_{m+j, m}: [j][re, im][64]
+    // loads: factorials, the pair's order, flags and sign of R_z, a and b of the wavefront's rows
+    const int gL = group_order(P);
     if (m > gL) return;                                  // past the group's largest order
+    const int C = gL - m;
     const double fv = P.fact[min(tid, 2 * LMAX + 1)];
     const int Lp = pw.L;
     const bool tri = (pw.flags & TCM_TRIANGULAR) != 0;
     const double sg = P.frame[7 * st + p];
     const double* A = P.prot + p;
     const double* B = P.prot + (size_t)nh(Lm) * st + p;
-    double ar[PAIR_UNITS], ai[PAIR_UNITS], br[PAIR_UNITS], bi[PAIR_UNITS];
+    double ar[UN], ai[UN], br[UN], bi[UN];
 #pragma unroll
-    for (int u = 0; u < PAIR_UNITS; ++u) {
-        if (m + wv + u * W > gL) break;
-        const int l = m + wv + u * W;
-        const size_t h = m == 0 ? (size_t)l * l : (size_t)l * l + 2 * m - 1;
-        ar[u] = A[h * st];
-        br[u] = B[h * st];
-        ai[u] = 0.0;
-        bi[u] = 0.0;
-        if (m > 0) {
-            ai[u] = A[(h + 1) * st];
-            bi[u] = B[(h + 1) * st];
+    for (int u = 0; u < UN; ++u) {
+        const int k = wv + u * W, l = m + k;
+        ar[u] = ai[u] = br[u] = bi[u] = 0.0;
+        if (k <= C) {
+            const size_t h = m == 0 ? (size_t)l * l : (size_t)l * l + 2 * m - 1;
+            ar[u] = A[h * st];
+            br[u] = B[h * st];
+            if (m > 0) {
+                ai[u] = A[(h + 1) * st];
+                bi[u] = B[(h + 1) * st];
+            }
         }
     }
-    const bool act = g0 + lane < end && Lp >= m;
-    {
-        if (tid < 2 * LMAX + 2) fs[tid] = fv;
-        // (-1)^{l2} (+-1)^{l1+l2} = (+-1)^{l1} (-+1)^{l2}: each entry takes the sign of its
-        // order (sign changes only, no rounding); entries past the pair's order are zero
+    if (tid < 2 * LMAX + 2) fs[tid] = fv;
 #pragma unroll
-        for (int u = 0; u < PAIR_UNITS; ++u) {
-            const int l = m + wv + u * W;
-            if (l > gL) break;
-            const bool ok = act && l <= Lp;
-            const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
-            const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
-            sa[(2 * l) * PAIR_LANES] = ok ? s1 * ar[u] : 0.0;
-            sa[(2 * l + 1) * PAIR_LANES] = ok ? s1 * ai[u] : 0.0;
-            sbb[(2 * l) * PAIR_LANES] = ok ? s2 * br[u] : 0.0;
-            sbb[(2 * l + 1) * PAIR_LANES] = ok ? s2 * bi[u] : 0.0;
+    for (int u = 0; u < UN; ++u) {
+        const int k = wv + u * W, l = m + k;
+        const bool ok = valid && l <= Lp;
+        const double s1 = ((l & 1) && sg < 0.0) ? -1.0 : 1.0;
+        const double s2 = ((l & 1) && sg > 0.0) ? -1.0 : 1.0;
+        if (k <= C) {
+            sa[(2 * k) * PAIR_LANES] = ok ? s1 * ar[u] : 0.0;
+            sa[(2 * k + 1) * PAIR_LANES] = ok ? s1 * ai[u] : 0.0;
+            sbv[(2 * k) * PAIR_LANES] = ok ? s2 * br[u] : 0.0;
+            sbv[(2 * k + 1) * PAIR_LANES] = ok ? s2 * bi[u] : 0.0;
         }
-        __syncthreads();
-        double Um = 0.0;
-#pragma unroll 1
-        for (int l1 = m + wv; l1 <= gL; l1 += W) {
-            if (!(act && l1 <= Lp)) continue;
-            const double a1 = sa[(2 * l1) * PAIR_LANES], a2 = sa[(2 * l1 + 1) * PAIR_LANES];
-            const int l2hi = tri ? Lp - l1 : Lp;
-            double cr = 0.0, ci = 0.0;                    // sum_l2 (l1+l2)! conj(signed b_{l2 m})
-#pragma unroll 4
-            for (int l2 = m; l2 <= l2hi; ++l2) {
-                const double f = fs[l1 + l2];
-                cr += f * sbb[(2 * l2) * PAIR_LANES];
-                ci -= f * sbb[(2 * l2 + 1) * PAIR_LANES];
+    }
+    __syncthreads();
+    // d_{m+j} for the wavefront's j = wv + u W, all together (2 UN chains; the j past C read a
+    // clamped factorial and are not used): a term counts where k + j <= tl (triangular:
+    // l1 + l2 <= Lp)
+    const int tl = tri ? Lp - 2 * m : 2 * LMAX;
+    double dr[UN], di[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) dr[u] = di[u] = 0.0;
+#pragma unroll 2
+    for (int k = 0; k <= C; ++k) {
+        const double a_r = sa[(2 * k) * PAIR_LANES], a_i = sa[(2 * k + 1) * PAIR_LANES];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int j = wv + u * W;
+            const double f = k + j <= tl ? fs[min(2 * m + k + j, 2 * LMAX + 1)] : 0.0;
+            dr[u] = fma(f, a_r, dr[u]);
+            di[u] = fma(f, a_i, di[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+        const int j = wv + u * W;
+        if (j <= C) {
+            sa[(2 * j) * PAIR_LANES] = dr[u];
+            sa[(2 * j + 1) * PAIR_LANES] = di[u];
+        }
+    }
+    __syncthreads();
+    if (wv == 0 && valid) {
+#pragma clang fp contract(off)                           // e_j, S_r and T_m exactly as written
+        double S[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j0 = 0; j0 <= C; j0 += 4)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r;
+                if (j > C) break;
+                const double* d = sa + (size_t)(2 * j) * PAIR_LANES;
+                const double* b = sbv + (size_t)(2 * j) * PAIR_LANES;
+                S[r] += m > 0 ? fma(d[0], b[0], d[PAIR_LANES] * b[PAIR_LANES]) : d[0] * b[0];
             }
-            Um += a1 * cr - a2 * ci;
-        }
-        red[wv * PAIR_LANES + lane] = Um;
-        __syncthreads();
-        if (wv == 0 && act) {
-            double u = red[lane];
-            for (int k = 1; k < W; ++k) u += red[k * PAIR_LANES + lane];
-            const double wt = m == 0 ? 1.0 : 2.0;
-            P.pum[(size_t)m * st + p] = (m & 1) ? -wt * u : wt * u;
-        }
+        const double T = (S[0] + S[1]) + (S[2] + S[3]);
+        const double wt = m == 0 ? 1.0 : 2.0;
+        P.pum[(size_t)m * st + p] = (m & 1) ? -wt * T : wt * T;
+        if (m == 0) P.pum[(size_t)(Lm + 1) * st + p] = pair_check(pw);
     }
 }
 
-// U = (1/R) sum_{m = 0..L} (the m-terms, in order) and the status: eq. 2 (|R| > a_A + a_B,
-// strict) unless TCM_UNCHECKED; a zero R is invalid.
+// U = (1/R) sum_{m = 0..L} (the m-terms of tcm_pairs_sum_w or tcm_pairs_sum_m) and the status
+// (from the check row of pum); every load issued at once (rows past the pair's order are read
+// and not added).
 __global__ __launch_bounds__(WG) void tcm_pairs_final(DevPlan P, int begin, int end)
 {
     const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
     if (p >= end) return;
-    const PairWork& pw = P.pairs[p];
-    const int Lp = pw.L, flags = pw.flags, out = pw.out;
-    const double Rx = pw.R[0], Ry = pw.R[1], Rz = pw.R[2];
-    const double* mA = pw.metaA;
-    const double* mB = pw.metaB;
     const double* pum = P.pum + p;
     const size_t st = P.npairs;
-    double t[LMAX + 1];                                  // every load issued before the first use
+    const int Lm = P.pair_lmax;
+    double t[LMAX + 1];
 #pragma unroll
-    for (int m = 0; m <= LMAX; ++m) t[m] = pum[(size_t)min(m, Lp) * st];
-    const double aA = mA[3], aB = mB[3];
-    const double Rn = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-    if (!(Rn > 0.0) || (!(flags & TCM_UNCHECKED) && !(Rn > aA + aB))) {
-        P.status[out] = (Rn > 0.0) ? TCM_EDOMAIN : TCM_EINVAL;
+    for (int m = 0; m <= LMAX; ++m) t[m] = pum[(size_t)min(m, Lm) * st];
+    const double rn = pum[(size_t)(Lm + 1) * st];
+    const PairWork& pw = P.pairs[p];
+    const int Lp = pw.L, out = pw.out;
+    if (!(rn > 0.0)) {
+        P.status[out] = (int32_t)rn;
         P.U[out] = __builtin_nan("");
         return;
     }
-    double u = 0.0;
+    {
+#pragma clang fp contract(off)
+        double V[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m <= LMAX; ++m) u += m <= Lp ? t[m] : 0.0;   // (adding zero changes nothing)
-    P.U[out] = u / Rn;
-    P.status[out] = TCM_OK;
+        for (int m = 0; m <= LMAX; ++m) V[m & 3] += m <= Lp ? t[m] : 0.0;   // (adding zero changes nothing)
+        P.U[out] = ((V[0] + V[1]) + (V[2] + V[3])) / rn;
+        P.status[out] = TCM_OK;
+    }
 }
 
 // Adaptive truncation: per pair, the smallest order L' <= L whose rigorous bound of the
@@ -1533,18 +1679,21 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
     const int Lm = P.pair_lmax;
     const unsigned groups = (unsigned)((end - begin + PAIR_LANES - 1) / PAIR_LANES);
     const size_t rot_lds = sizeof(double) * (2 * (size_t)Lm + 1 + ROT_PAD) * PAIR_LANES;
-    const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + (size_t)PAIR_WAVES * PAIR_LANES +
-                                             4 * ((size_t)Lm + 1) * PAIR_LANES);
+    hipError_t e;
     if (Lm <= 16)
         hipLaunchKernelGGL(tcm_pairs_rot<16>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
                            begin, end);
     else
         hipLaunchKernelGGL(tcm_pairs_rot<LMAX>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
                            begin, end);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(PAIR_LANES, PAIR_WAVES), sum_lds, s, P, begin,
-                       end);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (Lm <= SW_L) {
+        hipLaunchKernelGGL(tcm_pairs_sum_w, dim3(groups, Lm + 1), dim3(PAIR_LANES), 0, s, P, begin, end);
+    } else {
+        const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + 4 * ((size_t)Lm + 1) * PAIR_LANES);
+        hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(PAIR_LANES, PAIR_WAVES), sum_lds, s, P, begin,
+                           end);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end);
     return hipGetLastError();

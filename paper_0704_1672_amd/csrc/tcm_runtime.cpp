@@ -528,6 +528,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     }
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
+    bool uniform = true;                                  // every group reaches pair_lmax
     {
         PairWork* pw = (PairWork*)(h + o_pw);
         for (int k = 0; k < npairs; ++k) {
@@ -555,6 +556,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
         int32_t* go = (int32_t*)(h + o_go);
         for (int64_t g = 0; g < pgroups; ++g) go[g] = -1;
         for (int k = 0; k < npairs; ++k) go[k / PAIR_LANES] = std::max(go[k / PAIR_LANES], pw[k].L);
+        for (int64_t g = 0; g < pgroups; ++g) uniform = uniform && go[g] == pair_lmax;
     }
     {
         int32_t* si = (int32_t*)(h + o_sp);                // (molecule, chunk) of each STATS item
@@ -587,7 +589,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     if ((rc = c->alloc(ws.outS, sizeof(int32_t) * (npairs > 0 ? npairs : 1))) != TCM_OK) return rc;
     const size_t np1 = npairs > 0 ? (size_t)npairs : 1;
     if ((rc = c->alloc(ws.prot, sizeof(double) * 2 * (size_t)nh(pair_lmax) * np1)) != TCM_OK) return rc;
-    if ((rc = c->alloc(ws.pum, sizeof(double) * (size_t)(pair_lmax + 1) * np1)) != TCM_OK) return rc;
+    if ((rc = c->alloc(ws.pum, sizeof(double) * (size_t)(pair_lmax + 2) * np1)) != TCM_OK) return rc;
     if (hipMemcpyAsync(ws.blob.p, ws.hstage, blob, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipEventRecord(ws.staged, s) != hipSuccess)
         return TCM_EDEVICE;
@@ -605,6 +607,7 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.err = (int32_t*)ws.sync.p;
     P.frame = (const double*)(d + o_fr);
     P.gorder = (int32_t*)(d + o_go);
+    P.gorder_uniform = uniform ? 1 : 0;
     P.part_f = (float*)ws.part_f.p;
     P.part_d = (double*)ws.part_d.p;
     P.stats_part = (double*)ws.stats.p;
@@ -1794,6 +1797,7 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
     P2.pairs = (const PairWork*)(ad + o_pw);
     P2.frame = (const double*)(ad + o_fr);
     P2.gorder = (int32_t*)(ad + o_go);
+    P2.gorder_uniform = 0;                               // the orders are chosen on the device
     if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;
     std::vector<Mol*> need;
     for (int64_t i = 0; i < np; ++i) {
