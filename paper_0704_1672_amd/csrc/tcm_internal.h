@@ -95,7 +95,21 @@ struct DevPlan {
     const double* frame;           // per pair and side, [2][FRAME_N][npairs]: see side_frame
     int32_t* gorder;               // largest order of each group of PAIR_LANES pairs
     int32_t gorder_uniform;        // 1: every group's largest order is pair_lmax (gorder not read)
+    const double* qa_all;          // the A (B) table of every pair of the launch when they share
+    const double* qb_all;          // one (its order is then at least pair_lmax), else null
 };
+
+// The first column of the rotation-table rows of one class: a 90 degree rotation about x maps
+// the real functions of one type (cos, sin) and m parity onto one type and parity, whose
+// packed columns are max(0, jb + 4k).  Row of type sin_row and order m at degree l: jb = 2p - 1
+// when m and l have the same parity, else 2 (p = 1) or 4 (p = 0), with p = l mod 2 for cos rows
+// and (l + 1) mod 2 for sin rows.  The table builder checks every row against it.
+__host__ __device__ constexpr int rot_class_jb(bool sin_row, int m, int l)
+{
+    const bool same = ((m ^ l) & 1) == 0;
+    const int p = sin_row ? ((l + 1) & 1) : (l & 1);
+    return same ? 2 * p - 1 : (p ? 2 : 4);
+}
 
 // Pair launches take the pairs PAIR_LANES at a time, one pair per lane of a wavefront.
 constexpr int PAIR_LANES = 64;

@@ -441,13 +441,14 @@ __device__ __forceinline__ void phase_walk(double ec, double es, int w, int W, d
 // One row of D or D^-1 (row-by-row tables: the code, then K values) applied to the LDS vector
 // v[j][lane]: the row is the same for every lane (scalar loads); slot 0 reads column max(0, jb),
 // slot k > 0 column jb + 4k (at most n + 3: the rows past n are zero, as are the values past the
-// row's count).  The sum over the slots in order, even and odd slots in two partial sums.
+// row's count), jb the first column of the row's class (rot_class_jb, computed, so that the
+// LDS reads do not wait for the table).  The sum over the slots in order, even and odd slots in
+// two partial sums.
 using cdptr = const __attribute__((address_space(4))) double*;
 
 template <int K>
-__device__ __forceinline__ double rot_row_lanes(cdptr row, const double* v)
+__device__ __forceinline__ double rot_row_lanes(cdptr row, const double* v, int jb)
 {
-    const int jb = ((int)row[0] & 0xffff) - 1;
     const double* vb = v + jb * PAIR_LANES;
     double s0 = row[1] * v[max(0, jb) * PAIR_LANES], s1 = 0.0;
 #pragma unroll
@@ -482,13 +483,23 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
     }
     const double ir = fr[6 * st];
     const bool act = g0 + lane < end && Lp >= l;
-    const double* Q = (side ? pw.QB : pw.QA) + (act ? l * l : 0);   // order l exists when act
     double qr[U], qi[U];
+    const double* qall = side ? P.qb_all : P.qa_all;
+    if (qall) {                                          // one table for every pair: order l is in it
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int m = act ? min(wv + u * W, l) : 0;
-        qr[u] = Q[m == 0 ? 0 : 2 * m - 1];
-        qi[u] = Q[m == 0 ? 0 : 2 * m];
+        for (int u = 0; u < U; ++u) {
+            const int m = min(wv + u * W, l);
+            qr[u] = qall[l * l + (m == 0 ? 0 : 2 * m - 1)];
+            qi[u] = qall[l * l + (m == 0 ? 0 : 2 * m)];
+        }
+    } else {
+        const double* Q = (side ? pw.QB : pw.QA) + (act ? l * l : 0);   // order l exists when act
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = act ? min(wv + u * W, l) : 0;
+            qr[u] = Q[m == 0 ? 0 : 2 * m - 1];
+            qi[u] = Q[m == 0 ? 0 : 2 * m];
+        }
     }
     double* v = sv + lane;
     if (wv == 0)
@@ -514,7 +525,8 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
         cmul(c0, s0, cst, sst);
     }
     __syncthreads();
-    // Z(beta) D
+    // Z(beta) D; the wavefront's m all have the parity of wv (W is even)
+    const int jc = rot_class_jb(false, wv, l), js = rot_class_jb(true, wv, l);
     cdptr Dr = (cdptr)P.rotr + rot_block_offset(l);
     cdptr Di = Dr + n * (K + 1);
     double r0[U], r1[U];
@@ -524,10 +536,10 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
         const int m = wv + u * W;
         if (m > l) break;
         if (m == 0) {
-            r0[u] = rot_row_lanes<K>(Dr, v);
+            r0[u] = rot_row_lanes<K>(Dr, v, jc);
         } else {
-            const double re = rot_row_lanes<K>(Dr + (2 * m - 1) * (K + 1), v);
-            const double im = rot_row_lanes<K>(Dr + 2 * m * (K + 1), v);
+            const double re = rot_row_lanes<K>(Dr + (2 * m - 1) * (K + 1), v, jc);
+            const double im = rot_row_lanes<K>(Dr + 2 * m * (K + 1), v, js);
             r0[u] = c0 * re - s0 * im;
             r1[u] = s0 * re + c0 * im;
         }
@@ -555,11 +567,11 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
         const int m = wv + u * W;
         if (m > l) break;
         if (m == 0) {
-            const double a0 = rot_row_lanes<K>(Di, v) * invf[0];
+            const double a0 = rot_row_lanes<K>(Di, v, jc) * invf[0];
             if (act) out[0] = a0;
         } else {
-            const double re = rot_row_lanes<K>(Di + (2 * m - 1) * (K + 1), v);
-            const double im = rot_row_lanes<K>(Di + 2 * m * (K + 1), v);
+            const double re = rot_row_lanes<K>(Di + (2 * m - 1) * (K + 1), v, jc);
+            const double im = rot_row_lanes<K>(Di + 2 * m * (K + 1), v, js);
             const double f = invf[2 * m - 1];
             if (act) {
                 out[(2 * m - 1) * st] = (c0 * re - s0 * im) * f;

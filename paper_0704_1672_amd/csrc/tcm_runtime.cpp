@@ -271,6 +271,13 @@ static std::vector<double> build_rotation_tables(int Lmax)
         if (compress_rotation(Dd, n, blk, blk + 2 * n) != 0 ||
             compress_rotation(Di, n, blk + n, blk + 2 * n + (size_t)K * n) != 0)
             return {};
+        // the pair kernels take a row's first column from its class (rot_class_jb)
+        for (int inv = 0; inv < 2; ++inv)
+            for (int i = 0; i < n; ++i) {
+                const bool sn = i > 0 && !(i & 1);
+                const int m = i == 0 ? 0 : sn ? i / 2 : (i + 1) / 2;
+                if (std::fmod(blk[inv * n + i], 65536.0) != (double)(rot_class_jb(sn, m, l) + 1)) return {};
+            }
     }
     return out;
 }
@@ -529,6 +536,8 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
     bool uniform = true;                                  // every group reaches pair_lmax
+    const double* qa_all = npairs > 0 ? pairs_in[porder[0]].QA : nullptr;
+    const double* qb_all = npairs > 0 ? pairs_in[porder[0]].QB : nullptr;
     {
         PairWork* pw = (PairWork*)(h + o_pw);
         for (int k = 0; k < npairs; ++k) {
@@ -536,6 +545,8 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
             const PairJob& j = pairs_in[p];
             PairWork& w = pw[k];
             w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
+            if (j.QA != qa_all) qa_all = nullptr;
+            if (j.QB != qb_all) qb_all = nullptr;
             w.depA = j.depA >= 0 ? newidx[j.depA] : -1;
             w.depB = j.depB >= 0 ? newidx[j.depB] : -1;
             w.L = j.L; w.flags = j.flags;
@@ -608,6 +619,8 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     P.frame = (const double*)(d + o_fr);
     P.gorder = (int32_t*)(d + o_go);
     P.gorder_uniform = uniform ? 1 : 0;
+    P.qa_all = qa_all;
+    P.qb_all = qb_all;
     P.part_f = (float*)ws.part_f.p;
     P.part_d = (double*)ws.part_d.p;
     P.stats_part = (double*)ws.stats.p;
