@@ -396,6 +396,7 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 // Each pair's arithmetic is its own lane's, in a fixed order: a result does not depend on the
 // other pairs of the launch, nor on which of the two contraction paths the launch takes.
 constexpr int ROT_PAD = 4;        // zero rows after an LDS vector: the slots past a row's count read there
+constexpr int ROT_WAVES = 4;      // wavefronts of a rotation workgroup (even: a wavefront's m share a parity)
 
 // The largest order of the workgroup's group of pairs: the plan's largest when every group
 // reaches it (no load), else from the plan.
@@ -428,14 +429,37 @@ __device__ __forceinline__ void cmul(double& c, double& s, double bc, double bs)
     c = t;
 }
 
-// e^{i w phi} and e^{i W phi} from e^{i phi}: a wavefront w of W walks m = w, w + W, ...
-__device__ __forceinline__ void phase_walk(double ec, double es, int w, int W, double& c0, double& s0, double& cs,
+// x^N by squaring (N fixed at compile time): a chain of about log2 N products, not N.
+template <int N>
+__device__ __forceinline__ double pow_ct(double x)
+{
+    if constexpr (N == 0) {
+        return 1.0;
+    } else if constexpr (N == 1) {
+        return x;
+    } else {
+        const double h = pow_ct<N / 2>(x);
+        return (N & 1) ? h * h * x : h * h;
+    }
+}
+
+// e^{i w phi} and e^{i W phi} from e^{i phi} (W a power of two, w < W): a wavefront w of W
+// walks m = w, w + W, ...; the powers by repeated squaring, e^{i w phi} as the product of those
+// of w's bits (fewer dependent products than one step at a time).
+template <int W>
+__device__ __forceinline__ void phase_walk(double ec, double es, int w, double& c0, double& s0, double& cs,
                                           double& ss)
 {
+    static_assert((W & (W - 1)) == 0, "W is a power of two");
     c0 = 1.0; s0 = 0.0;
-    for (int k = 0; k < w; ++k) cmul(c0, s0, ec, es);
-    cs = 1.0; ss = 0.0;
-    for (int k = 0; k < W; ++k) cmul(cs, ss, ec, es);
+    cs = ec; ss = es;                                    // e^{i b phi}, b = 1, 2, 4, ...
+#pragma unroll
+    for (int b = 1; b < W; b <<= 1) {
+        if (w & b) cmul(c0, s0, cs, ss);
+        const double c2 = cs * cs - ss * ss;
+        ss = 2.0 * cs * ss;
+        cs = c2;
+    }
 }
 
 // One row of D or D^-1 (row-by-row tables: the code, then K values) applied to the LDS vector
@@ -465,7 +489,7 @@ __device__ __forceinline__ double rot_row_lanes(cdptr row, const double* v, int 
 template <int l>
 __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, int side, double* sv)
 {
-    constexpr int n = 2 * l + 1, K = l / 2 + 1, W = PAIR_WAVES, U = (l + W) / W;
+    constexpr int n = 2 * l + 1, K = l / 2 + 1, W = ROT_WAVES, U = (l + W) / W;
     const int lane = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
@@ -506,11 +530,9 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
 #pragma unroll
         for (int j = n; j < n + ROT_PAD; ++j) v[j * PAIR_LANES] = 0.0;
     // Z(gamma) R^-l on the wavefront's units (e^{i m phi} by successive products along its walk)
-    double sc = 1.0;
-#pragma unroll
-    for (int k = 0; k < l; ++k) sc *= ir;
+    const double sc = pow_ct<l>(ir);
     double c0, s0, cst, sst;
-    phase_walk(ec[0], es[0], wv, W, c0, s0, cst, sst);
+    phase_walk<W>(ec[0], es[0], wv, c0, s0, cst, sst);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int m = wv + u * W;
@@ -530,7 +552,7 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
     cdptr Dr = (cdptr)P.rotr + rot_block_offset(l);
     cdptr Di = Dr + n * (K + 1);
     double r0[U], r1[U];
-    phase_walk(ec[1], es[1], wv, W, c0, s0, cst, sst);
+    phase_walk<W>(ec[1], es[1], wv, c0, s0, cst, sst);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int m = wv + u * W;
@@ -561,7 +583,7 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
     // Z(alpha) D^-1, then 1/f_lm; out to the scratch [side][h][pair]
     cdptr invf = (cdptr)P.invf + l * l;
     double* out = P.prot + ((size_t)side * nh(P.pair_lmax) + l * l) * st + p;
-    phase_walk(ec[2], es[2], wv, W, c0, s0, cst, sst);
+    phase_walk<W>(ec[2], es[2], wv, c0, s0, cst, sst);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int m = wv + u * W;
@@ -597,7 +619,7 @@ __device__ __forceinline__ void rot_dispatch(int l, const DevPlan& P, int begin,
 
 // Orders 0 .. LHI (a launch whose largest order is above 16 takes the second instantiation).
 template <int LHI>
-__global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_rot(DevPlan P, int begin, int end)
+__global__ __launch_bounds__(PAIR_LANES * ROT_WAVES) void tcm_pairs_rot(DevPlan P, int begin, int end)
 {
     extern __shared__ __align__(16) double sv[];       // v [2 pair_lmax + 1 + ROT_PAD][64]
     const int l = P.pair_lmax - (int)blockIdx.y;         // highest orders first
@@ -624,8 +646,8 @@ template __global__ void tcm_pairs_rot<LMAX>(DevPlan, int, int);
 // Largest order up to SW_L: one wavefront per (group, m).  The a_{l1 m} and b_{l2 m} of its 64
 // pairs (l1, l2 = m .. m + SW_L) are held in registers, zero past the group's largest order
 // (the terms they add are exact zeros), and the factorials (2m)! .. (2m + 2 SW_L)! in scalar
-// registers; every loop is unrolled, and the d_j of JB consecutive j are formed together.  The
-// terms and their order are those of the larger-order path.
+// registers; every loop is unrolled, and the d_j of four consecutive j are formed together
+// (eight multiply-add chains).  The terms and their order are those of the larger-order path.
 constexpr int SW_L = 16, SW_N = SW_L + 1;
 
 template <bool IM, bool MASK>
@@ -1693,10 +1715,10 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
     const size_t rot_lds = sizeof(double) * (2 * (size_t)Lm + 1 + ROT_PAD) * PAIR_LANES;
     hipError_t e;
     if (Lm <= 16)
-        hipLaunchKernelGGL(tcm_pairs_rot<16>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
+        hipLaunchKernelGGL(tcm_pairs_rot<16>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, ROT_WAVES), rot_lds, s, P,
                            begin, end);
     else
-        hipLaunchKernelGGL(tcm_pairs_rot<LMAX>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, PAIR_WAVES), rot_lds, s, P,
+        hipLaunchKernelGGL(tcm_pairs_rot<LMAX>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, ROT_WAVES), rot_lds, s, P,
                            begin, end);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (Lm <= SW_L) {
