@@ -91,7 +91,7 @@ struct DevPlan {
     const double* invf;            // 1/sqrt((l+m)!(l-m)!), per packed index
     const double* rot;             // rotation tables (D and D^{-1} per l, compressed by sparsity)
     const double* rotr;            // the same, row by row (rot + rot_tables_len())
-    const double* fact;            // k!, k <= 2 LMAX + 1
+    const double* fact;            // k!, k < FACT_N
     const double* frame;           // per pair and side, [2][FRAME_N][npairs]: see side_frame
     int32_t* gorder;               // largest order of each group of PAIR_LANES pairs
     int32_t gorder_uniform;        // 1: every group's largest order is pair_lmax (gorder not read)
@@ -110,6 +110,10 @@ __host__ __device__ constexpr int rot_class_jb(bool sin_row, int m, int l)
     const int p = sin_row ? ((l + 1) & 1) : (l & 1);
     return same ? 2 * p - 1 : (p ? 2 : 4);
 }
+
+// Entries of the device factorial table (k! for k < FACT_N; the register contraction reads up
+// to (2 L + 2 (N - 1))! with N - 1 >= L, the entries past (2 L)! only against zero moments).
+constexpr int FACT_N = 128;
 
 // Pair launches take the pairs PAIR_LANES at a time, one pair per lane of a wavefront.
 constexpr int PAIR_LANES = 64;

@@ -389,7 +389,7 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 //                    table rotated into the frame where R lies along z (B's pose folded in; the
 //                    Euler phases come from the plan, computed by the host), scaled by
 //                    R^-l / f_lm, written to the plan's scratch [side][h][pair];
-//   tcm_pairs_sum_w  (group, m), one wavefront, largest order up to SW_L, or tcm_pairs_sum_m
+//   tcm_pairs_sum_w<N> (group, m), one wavefront, largest order up to SW_L, or tcm_pairs_sum_m
 //                    (group, m), four wavefronts, larger orders: for each pair the m-term of the
 //                    axial contraction;
 //   tcm_pairs_final  (pair): U = (sum over m) / R and the status (eq. 2 checked here).
@@ -643,19 +643,19 @@ template __global__ void tcm_pairs_rot<LMAX>(DevPlan, int, int);
 // in flight: a dependent FP64 multiply-add waits about forty clocks for its predecessor.
 // Terms past a pair's order are exact zeros, so the group's largest order does not change them.
 
-// Largest order up to SW_L: one wavefront per (group, m).  The a_{l1 m} and b_{l2 m} of its 64
-// pairs (l1, l2 = m .. m + SW_L) are held in registers, zero past the group's largest order
-// (the terms they add are exact zeros), and the factorials (2m)! .. (2m + 2 SW_L)! in scalar
-// registers; every loop is unrolled, and the d_j of four consecutive j are formed together
+// Largest order below N (N = 17 or 25): one wavefront per (group, m).  The a_{l1 m} and b_{l2 m}
+// of its 64 pairs (l1, l2 = m .. m + N - 1) are held in registers, zero past the group's largest
+// order (the terms they add are exact zeros), and the factorials (2m)! .. (2m + 2N - 2)! in
+// scalar registers; every loop is unrolled, and the d_j of four consecutive j are formed together
 // (eight multiply-add chains).  The terms and their order are those of the larger-order path.
-constexpr int SW_L = 16, SW_N = SW_L + 1;
+constexpr int SW_L = 24;                                 // the largest order of the register path
 
-template <bool IM, bool MASK>
+template <int N, bool IM, bool MASK>
 __device__ __forceinline__ double sw_sum(const double* ar, const double* ai, const double* br, const double* bi,
                                          cdptr f2, int tl)
 {
 #pragma clang fp contract(off)                           // e_j, S_r and T_m exactly as written
-    constexpr int N = SW_N, JB = 4;
+    constexpr int JB = 4;
     double S[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j0 = 0; j0 < N; j0 += JB) {
@@ -682,9 +682,10 @@ __device__ __forceinline__ double sw_sum(const double* ar, const double* ai, con
     return (S[0] + S[1]) + (S[2] + S[3]);
 }
 
+template <int N>
 __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_sum_w(DevPlan P, int begin, int end)
 {
-    constexpr int N = SW_N;
+    static_assert(2 * (N - 1) + 2 * (N - 1) < FACT_N, "the factorials read stay in the table");
     const int lane = threadIdx.x;
     const int g0 = begin + (int)blockIdx.x * PAIR_LANES;
     const int m = blockIdx.y;
@@ -731,14 +732,18 @@ __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_sum_w(DevPlan P, int beg
     const int tl = tri ? Lp - 2 * m : 2 * LMAX;
     const cdptr f2 = (cdptr)P.fact + 2 * m;
     double T;
-    if (m == 0) T = mask ? sw_sum<false, true>(ar, ai, br, bi, f2, tl) : sw_sum<false, false>(ar, ai, br, bi, f2, tl);
-    else T = mask ? sw_sum<true, true>(ar, ai, br, bi, f2, tl) : sw_sum<true, false>(ar, ai, br, bi, f2, tl);
+    if (m == 0)
+        T = mask ? sw_sum<N, false, true>(ar, ai, br, bi, f2, tl) : sw_sum<N, false, false>(ar, ai, br, bi, f2, tl);
+    else
+        T = mask ? sw_sum<N, true, true>(ar, ai, br, bi, f2, tl) : sw_sum<N, true, false>(ar, ai, br, bi, f2, tl);
     if (valid) {
         const double wt = m == 0 ? 1.0 : 2.0;
         P.pum[(size_t)m * st + p] = (m & 1) ? -wt * T : wt * T;
         if (m == 0) P.pum[(size_t)(P.pair_lmax + 1) * st + p] = pair_check(pw);
     }
 }
+template __global__ void tcm_pairs_sum_w<17>(DevPlan, int, int);
+template __global__ void tcm_pairs_sum_w<25>(DevPlan, int, int);
 
 // Orders above SW_L: one workgroup per (group, m).  The signed a_{l1 m} and b_{l2 m} are staged
 // in LDS, wavefront w forms d_j for j = w, w + W, ..., and wavefront 0 forms T_m from them and
@@ -1721,8 +1726,10 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
         hipLaunchKernelGGL(tcm_pairs_rot<LMAX>, dim3(groups, Lm + 1, 2), dim3(PAIR_LANES, ROT_WAVES), rot_lds, s, P,
                            begin, end);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (Lm <= SW_L) {
-        hipLaunchKernelGGL(tcm_pairs_sum_w, dim3(groups, Lm + 1), dim3(PAIR_LANES), 0, s, P, begin, end);
+    if (Lm <= 16) {
+        hipLaunchKernelGGL(tcm_pairs_sum_w<17>, dim3(groups, Lm + 1), dim3(PAIR_LANES), 0, s, P, begin, end);
+    } else if (Lm <= SW_L) {
+        hipLaunchKernelGGL(tcm_pairs_sum_w<25>, dim3(groups, Lm + 1), dim3(PAIR_LANES), 0, s, P, begin, end);
     } else {
         const size_t sum_lds = sizeof(double) * (2 * LMAX + 2 + 4 * ((size_t)Lm + 1) * PAIR_LANES);
         hipLaunchKernelGGL(tcm_pairs_sum_m, dim3(groups, Lm + 1), dim3(PAIR_LANES, PAIR_WAVES), sum_lds, s, P, begin,

@@ -866,7 +866,7 @@ extern "C" int tcm_create(tcm_ctx** out, int device, size_t budget, int flags)
                 for (int k = 0; k < K; ++k) row[1 + k] = src[2 * n + (size_t)inv * K * n + (size_t)k * n + i];
             }
     }
-    std::vector<double> fact(2 * LMAX + 2);  // k! (long double products, rounded once)
+    std::vector<double> fact(FACT_N);        // k! (long double products, rounded once)
     {
         long double f = 1.0L;
         for (int k = 0; k < (int)fact.size(); ++k) {
