@@ -923,24 +923,46 @@ __global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int
 
 // Regrouping after the order choice: the pairs listed again by decreasing chosen order, so that
 // a group of PAIR_LANES pairs runs to (about) the orders its pairs need.  cnt[0 .. LMAX] counts
-// the pairs of each order (zeroed before), cnt[LMAX + 1 ..] are the placement cursors.  The
-// place of a pair within its order is taken by an atomic (any order: a pair's arithmetic is its
+// the pairs of each order (zeroed before), cnt[LMAX + 1 ..] are the placement cursors.  Each
+// workgroup counts its pairs per order in LDS and takes its places with one global atomic per
+// order (one per pair put thousands of atomics on a few addresses: 0.25 ms for 32k pairs).  The
+// place of a pair within its order is taken by atomics (any order: a pair's arithmetic is its
 // own lane's and its result goes to U[out], so its value does not depend on where it lands).
 __global__ __launch_bounds__(WG) void tcm_pairs_count(DevPlan P, int npairs, int32_t* cnt)
 {
-    const int p = (int)(blockIdx.x * WG + threadIdx.x);
-    if (p < npairs) atomicAdd(&cnt[P.pairs[p].L], 1);
+    __shared__ int h[LMAX + 1];
+    const int tid = (int)threadIdx.x;
+    if (tid <= LMAX) h[tid] = 0;
+    __syncthreads();
+    const int p = (int)blockIdx.x * WG + tid;
+    if (p < npairs) atomicAdd(&h[P.pairs[p].L], 1);
+    __syncthreads();
+    if (tid <= LMAX && h[tid] > 0) atomicAdd(&cnt[tid], h[tid]);
 }
 
 __global__ __launch_bounds__(WG) void tcm_pairs_regroup(DevPlan P, int npairs, int32_t* cnt, PairWork* pairs2,
                                                         double* frame2)
 {
-    const int p = (int)(blockIdx.x * WG + threadIdx.x);
+    __shared__ int h[LMAX + 1], base[LMAX + 1];
+    const int tid = (int)threadIdx.x;
+    if (tid <= LMAX) h[tid] = 0;
+    __syncthreads();
+    const int p = (int)blockIdx.x * WG + tid;
+    PairWork w{};
+    int r = 0;                                           // the pair's rank among the workgroup's of its order
+    if (p < npairs) {
+        w = P.pairs[p];
+        r = atomicAdd(&h[w.L], 1);
+    }
+    __syncthreads();
+    if (tid <= LMAX && h[tid] > 0) {
+        int b = 0;
+        for (int L = LMAX; L > tid; --L) b += cnt[L];
+        base[tid] = b + atomicAdd(&cnt[LMAX + 1 + tid], h[tid]);
+    }
+    __syncthreads();
     if (p >= npairs) return;
-    const PairWork w = P.pairs[p];
-    int base = 0;
-    for (int L = LMAX; L > w.L; --L) base += cnt[L];
-    const int q = base + atomicAdd(&cnt[LMAX + 1 + w.L], 1);
+    const int q = base[w.L] + r;
     pairs2[q] = w;
     const size_t st = (size_t)npairs;
 #pragma unroll
