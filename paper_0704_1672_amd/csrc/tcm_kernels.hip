@@ -379,8 +379,8 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 // well conditioned for every direction).
 //
 // The pair launches take the pairs PAIR_LANES (64) at a time, one pair per lane: every loop
-// index (order, row, slot, m) is then the same in all lanes of a wavefront, the rotation tables
-// are read once per workgroup into LDS and shared by its pairs, and the vector units do the
+// index (order, row, slot, m) is then the same in all lanes of a wavefront, the rotation-table
+// rows are the same for every lane (scalar loads, scalar operands), and the vector units do the
 // arithmetic of 64 pairs per instruction.  A group runs to the largest order of its pairs (the
 // launch lists pairs by decreasing order, so groups are nearly uniform); a lane whose pair has a
 // lower order skips what it does not need.  The work of a pair is small (O(L^3)), so the kernels
@@ -392,7 +392,8 @@ __device__ inline void rotate_moments2(const double* rot, double* va, double* vb
 //   tcm_pairs_sum_w<N> (group, m), one wavefront, largest order up to SW_L, or tcm_pairs_sum_m
 //                    (group, m), four wavefronts, larger orders: for each pair the m-term of the
 //                    axial contraction;
-//   tcm_pairs_final  (pair): U = (sum over m) / R and the status (eq. 2 checked here).
+//   tcm_pairs_final  (pair): U = (sum over m) / R and the status (eq. 2 checked by the m = 0
+//                    contraction, which stores |R| or the failure in a check row).
 // Each pair's arithmetic is its own lane's, in a fixed order: a result does not depend on the
 // other pairs of the launch, nor on which of the two contraction paths the launch takes.
 constexpr int ROT_PAD = 4;        // zero rows after an LDS vector: the slots past a row's count read there

@@ -353,3 +353,41 @@ def test_register_device_matches_upload(ctx, synth):
             tcm.tcm_mol_release(ctx, m1)
             tcm.tcm_mol_release(ctx, m2)
         torch.cuda.synchronize()
+
+
+def test_contraction_kernels_give_the_same_bits(ctx, synth):
+    """A pair's energy does not depend on the contraction kernel its launch takes: alone at
+    order L (largest order <= 16: the 17-order register kernel), beside a pair of order 20 (the
+    25-order register kernel) and beside a pair of order 28 (the LDS-staged kernel) it is the
+    same to the bit, square and triangular.  The moments are computed once at order 28 and
+    reused, so every call contracts the same tables."""
+    xa, qa = synth.ball(71, 0, 400, 4.0)
+    xb, qb = synth.ball(72, 0, 500, 5.0)
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    b = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F64)
+    try:
+        rng = np.random.default_rng(73)
+        n = 70                                            # two groups of 64, the second ragged
+        R = rng.normal(size=(n, 3))
+        R *= (rng.uniform(14.0, 30.0, n) / np.linalg.norm(R, axis=1))[:, None]
+        quats = synth.quaternions(74, 0, n + 1)
+        _, st, rc = tcm.tcm_batch_energy(ctx, tcm.make_requests(a, b, [20.0, 0.0, 0.0], 28))
+        assert rc == tcm.TCM_OK
+        reuse = tcm.TCM_REUSE
+        for flags in (0, tcm.TCM_TRIANGULAR):
+            for L in (6, 12):
+                alone = np.empty(n)
+                for k in range(n):
+                    U, st, rc = tcm.tcm_batch_energy(
+                        ctx, tcm.make_requests(a, b, R[k], L, quats[k], flags=flags | reuse))
+                    assert rc == tcm.TCM_OK
+                    alone[k] = U[0]
+                for Lf in (20, 28):                      # a last pair raises the launch's largest order
+                    req = tcm.make_requests(a, b, np.vstack([R, [[0.0, 0.0, 25.0]]]), [L] * n + [Lf],
+                                            quats, flags=flags | reuse)
+                    U, st, rc = tcm.tcm_batch_energy(ctx, req)
+                    assert rc == tcm.TCM_OK
+                    assert np.array_equal(U[:n], alone), (flags, L, Lf)
+    finally:
+        tcm.tcm_mol_release(ctx, a)
+        tcm.tcm_mol_release(ctx, b)
