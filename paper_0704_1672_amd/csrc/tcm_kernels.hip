@@ -581,7 +581,8 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
         }
     }
     __syncthreads();
-    // Z(alpha) D^-1, then 1/f_lm; out to the scratch [side][h][pair]
+    // Z(alpha) D^-1, then 1/f_lm; out to the scratch [side][h][pair] with streaming stores (the
+    // scratch, 2 (L+1)^2 doubles per pair, is read once, by the next launch)
     cdptr invf = (cdptr)P.invf + l * l;
     double* out = P.prot + ((size_t)side * nh(P.pair_lmax) + l * l) * st + p;
     phase_walk<W>(ec[2], es[2], wv, c0, s0, cst, sst);
@@ -591,14 +592,14 @@ __device__ __forceinline__ void rot_order(const DevPlan& P, int begin, int end, 
         if (m > l) break;
         if (m == 0) {
             const double a0 = rot_row_lanes<K>(Di, v, jc) * invf[0];
-            if (act) out[0] = a0;
+            if (act) __builtin_nontemporal_store(a0, out);
         } else {
             const double re = rot_row_lanes<K>(Di + (2 * m - 1) * (K + 1), v, jc);
             const double im = rot_row_lanes<K>(Di + 2 * m * (K + 1), v, js);
             const double f = invf[2 * m - 1];
             if (act) {
-                out[(2 * m - 1) * st] = (c0 * re - s0 * im) * f;
-                out[2 * m * st] = (s0 * re + c0 * im) * f;
+                __builtin_nontemporal_store((c0 * re - s0 * im) * f, out + (2 * m - 1) * st);
+                __builtin_nontemporal_store((s0 * re + c0 * im) * f, out + 2 * m * st);
             }
         }
         cmul(c0, s0, cst, sst);
