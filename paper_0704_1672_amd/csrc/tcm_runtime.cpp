@@ -370,6 +370,27 @@ size_t workspace_growth(Ctx* c, const Workspace& ws, const std::vector<MolJob>& 
     return grow;
 }
 
+// body(k0, k1) over [0, n) in contiguous chunks, on up to 8 host threads when n is large
+// (the chunks must touch disjoint memory).
+template <typename F>
+static void host_parallel(int n, F&& body)
+{
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int nt = n >= 8192 ? (int)std::min(8u, hc > 0 ? hc : 1u) : 1;
+    if (nt <= 1) {
+        body(0, n);
+        return;
+    }
+    const int per = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) {
+        const int k0 = t * per, k1 = std::min(n, k0 + per);
+        if (k0 < k1) th.emplace_back([&body, k0, k1] { body(k0, k1); });
+    }
+    body(0, std::min(n, per));
+    for (std::thread& x : th) x.join();
+}
+
 int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const std::vector<PairJob>& pairs_in,
                BuiltPlan& bp, hipStream_t s)
 {
@@ -536,34 +557,37 @@ int build_plan(Ctx* c, Workspace& ws, const std::vector<MolJob>& mols_in, const 
     char* h = (char*)ws.hstage;
     if (nmol) std::memcpy(h + o_mw, mw.data(), sizeof(MolWork) * nmol);
     bool uniform = true;                                  // every group reaches pair_lmax
-    const double* qa_all = npairs > 0 ? pairs_in[porder[0]].QA : nullptr;
-    const double* qb_all = npairs > 0 ? pairs_in[porder[0]].QB : nullptr;
+    const double* qa_all = npairs > 0 ? pairs_in[0].QA : nullptr;
+    const double* qb_all = npairs > 0 ? pairs_in[0].QB : nullptr;
+    for (const PairJob& j : pairs_in) {
+        if (j.QA != qa_all) qa_all = nullptr;
+        if (j.QB != qb_all) qb_all = nullptr;
+    }
     {
+        // the pair records in launch order and the rotation frames of both sides,
+        // [side][FRAME_N][pair] (each pair's own: the chunks of pairs are independent)
         PairWork* pw = (PairWork*)(h + o_pw);
-        for (int k = 0; k < npairs; ++k) {
-            const int p = porder[k];
-            const PairJob& j = pairs_in[p];
-            PairWork& w = pw[k];
-            w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
-            if (j.QA != qa_all) qa_all = nullptr;
-            if (j.QB != qb_all) qb_all = nullptr;
-            w.depA = j.depA >= 0 ? newidx[j.depA] : -1;
-            w.depB = j.depB >= 0 ? newidx[j.depB] : -1;
-            w.L = j.L; w.flags = j.flags;
-            for (int d = 0; d < 3; ++d) w.R[d] = j.R[d];
-            for (int d = 0; d < 4; ++d) w.quat[d] = j.quat[d];
-            w.has_rot = j.has_rot;
-            w.out = p;
-        }
-        // the rotation frames of both sides, [side][FRAME_N][pair]
         double* fr = (double*)(h + o_fr);
-        for (int k = 0; k < npairs; ++k) {
-            double f[2][FRAME_N];
-            side_frame(pw[k].R, pw[k].quat, false, f[0]);
-            side_frame(pw[k].R, pw[k].quat, pw[k].has_rot != 0, f[1]);
-            for (int side = 0; side < 2; ++side)
-                for (int c = 0; c < FRAME_N; ++c) fr[((size_t)side * FRAME_N + c) * npairs + k] = f[side][c];
-        }
+        host_parallel(npairs, [&](int k0, int k1) {
+            for (int k = k0; k < k1; ++k) {
+                const int p = porder[k];
+                const PairJob& j = pairs_in[p];
+                PairWork& w = pw[k];
+                w.QA = j.QA; w.QB = j.QB; w.metaA = j.metaA; w.metaB = j.metaB;
+                w.depA = j.depA >= 0 ? newidx[j.depA] : -1;
+                w.depB = j.depB >= 0 ? newidx[j.depB] : -1;
+                w.L = j.L; w.flags = j.flags;
+                for (int d = 0; d < 3; ++d) w.R[d] = j.R[d];
+                for (int d = 0; d < 4; ++d) w.quat[d] = j.quat[d];
+                w.has_rot = j.has_rot;
+                w.out = p;
+                double f[2][FRAME_N];
+                side_frame(w.R, w.quat, false, f[0]);
+                side_frame(w.R, w.quat, w.has_rot != 0, f[1]);
+                for (int side = 0; side < 2; ++side)
+                    for (int cc = 0; cc < FRAME_N; ++cc) fr[((size_t)side * FRAME_N + cc) * npairs + k] = f[side][cc];
+            }
+        });
         int32_t* go = (int32_t*)(h + o_go);
         for (int64_t g = 0; g < pgroups; ++g) go[g] = -1;
         for (int k = 0; k < npairs; ++k) go[k / PAIR_LANES] = std::max(go[k / PAIR_LANES], pw[k].L);
@@ -775,6 +799,39 @@ int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s)
     if (hipMemcpyAsync(&err, bp.P.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
     return err ? TCM_EDEVICE : TCM_OK;
+}
+
+// Device arrays of a finished plan read back through the context's pinned buffer, then the
+// plan's error flag checked: into pinned memory the copies stay asynchronous and are waited on
+// once (into pageable memory each copy is staged and waited on by itself).  dst[k] receives
+// bytes[k] from src[k].  The context is locked; the pinned buffer is grown only after the
+// stream has drained (an upload queued earlier may still read it).
+static int read_back(Ctx& c, const BuiltPlan& bp, hipStream_t s, int n, const void* const* src, void* const* dst,
+                     const size_t* bytes)
+{
+    size_t total = 64;
+    for (int k = 0; k < n; ++k) total += (bytes[k] + 15) & ~size_t(15);
+    if (total > c.hpin_cap && hipStreamSynchronize(s) != hipSuccess) return TCM_EDEVICE;
+    int rc;
+    if ((rc = c.ensure_pinned(total)) != TCM_OK) return rc;
+    char* h = (char*)c.hpin;
+    int32_t* herr = (int32_t*)h;
+    size_t off = 64;
+    for (int k = 0; k < n; ++k) {
+        if (bytes[k] && hipMemcpyAsync(h + off, src[k], bytes[k], hipMemcpyDeviceToHost, s) != hipSuccess)
+            return TCM_EDEVICE;
+        off += (bytes[k] + 15) & ~size_t(15);
+    }
+    if (hipMemcpyAsync(herr, bp.P.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (*herr) return TCM_EDEVICE;
+    off = 64;
+    for (int k = 0; k < n; ++k) {
+        if (bytes[k]) std::memcpy(dst[k], h + off, bytes[k]);
+        off += (bytes[k] + 15) & ~size_t(15);
+    }
+    return TCM_OK;
 }
 
 void free_workspace(Ctx* c, Workspace& ws)
@@ -1325,10 +1382,12 @@ static int run_requests(Ctx& c, ReqPlan& rp, int64_t np, double* U_out, int32_t*
     const int npj = (int)rp.pj.size();
     std::vector<double> U(npj > 0 ? npj : 1);
     std::vector<int32_t> st(npj > 0 ? npj : 1);
-    if (npj > 0 && (hipMemcpyAsync(U.data(), bp.P.U, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess))
-        return TCM_EDEVICE;
-    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    {
+        const void* src[2] = {bp.P.U, bp.P.status};
+        void* dst[2] = {U.data(), st.data()};
+        const size_t bytes[2] = {sizeof(double) * (size_t)npj, sizeof(int32_t) * (size_t)npj};
+        if ((rc = read_back(c, bp, s, 2, src, dst, bytes)) != TCM_OK) return rc;
+    }
     mark_computed(rp);
     for (int64_t i = 0; i < np; ++i) {
         status_out[i] = rp.pre_status[i];
@@ -1834,12 +1893,13 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
         return TCM_EDEVICE;
     std::vector<double> U(npj > 0 ? npj : 1), B(npj > 0 ? npj : 1);
     std::vector<int32_t> st(npj > 0 ? npj : 1), Lc(npj > 0 ? npj : 1);
-    if (npj > 0 && (hipMemcpyAsync(U.data(), bp.P.U, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipMemcpyAsync(B.data(), dB, sizeof(double) * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipMemcpyAsync(Lc.data(), dL, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess))
-        return TCM_EDEVICE;
-    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    {
+        const void* src[4] = {bp.P.U, bp.P.status, dB, dL};
+        void* dst[4] = {U.data(), st.data(), B.data(), Lc.data()};
+        const size_t nd = sizeof(double) * (size_t)npj, ni = sizeof(int32_t) * (size_t)npj;
+        const size_t bytes[4] = {nd, ni, nd, ni};
+        if ((rc = read_back(c, bp, s, 4, src, dst, bytes)) != TCM_OK) return rc;
+    }
     mark_computed(rp);
     for (int64_t i = 0; i < np; ++i) {
         status_out[i] = rp.pre_status[i];
