@@ -1125,9 +1125,12 @@ extern "C" int tcm_pair_energy(tcm_ctx* t, const double* QA, double aA, const do
     if ((rc = run_plan(&c, bp, s, false, nullptr)) != TCM_OK) return rc;
     double U = 0.0;
     int32_t st = 0;
-    if (hipMemcpyAsync(&U, bp.P.U, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
-    if (hipMemcpyAsync(&st, bp.P.status, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return TCM_EDEVICE;
-    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    {
+        const void* src[2] = {bp.P.U, bp.P.status};
+        void* dst[2] = {&U, &st};
+        const size_t bytes[2] = {sizeof(double), sizeof(int32_t)};
+        if ((rc = read_back(c, bp, s, 2, src, dst, bytes)) != TCM_OK) return rc;
+    }
     if (st != TCM_OK) return st;
     *U_out = U;
     return TCM_OK;
