@@ -2028,12 +2028,15 @@ extern "C" int tcm_batch_forces(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np
     std::vector<int32_t> st(npj > 0 ? npj : 1);
     if (npj > 0) {
         if ((rc = c.alloc(c.force_ft, sizeof(double) * FT_N * npj)) != TCM_OK) return rc;
-        if (launch_pairs_ft(bp.P, 0, npj, (double*)c.force_ft.p, nullptr, nullptr, s) != hipSuccess ||
-            hipMemcpyAsync(ft.data(), c.force_ft.p, sizeof(double) * FT_N * npj, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(st.data(), bp.P.status, sizeof(int32_t) * npj, hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (launch_pairs_ft(bp.P, 0, npj, (double*)c.force_ft.p, nullptr, nullptr, s) != hipSuccess)
             return TCM_EDEVICE;
     }
-    if ((rc = check_err(&c, bp, s)) != TCM_OK) return rc;
+    {
+        const void* src[2] = {c.force_ft.p, bp.P.status};
+        void* dst[2] = {ft.data(), st.data()};
+        const size_t bytes[2] = {npj > 0 ? sizeof(double) * FT_N * (size_t)npj : 0, sizeof(int32_t) * (size_t)npj};
+        if ((rc = read_back(c, bp, s, 2, src, dst, bytes)) != TCM_OK) return rc;
+    }
     mark_computed(rp);
     for (int64_t i = 0; i < np; ++i) {
         status_out[i] = rp.pre_status[i];
