@@ -391,3 +391,35 @@ def test_contraction_kernels_give_the_same_bits(ctx, synth):
     finally:
         tcm.tcm_mol_release(ctx, a)
         tcm.tcm_mol_release(ctx, b)
+
+
+def test_large_batch_planned_on_threads_equals_small_batches(ctx, synth):
+    """From 8192 pairs on the plan's pair records and rotation frames are filled on several
+    host threads: 9000 posed pairs (mixed orders, some triangular) in one batch must equal, to the
+    bit, the same pairs in two batches of 4500 planned on one thread."""
+    xa, qa = synth.ball(81, 0, 300, 4.0)
+    xb, qb = synth.ball(82, 0, 350, 4.5)
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    b = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F64)
+    try:
+        rng = np.random.default_rng(83)
+        n = 9000
+        R = rng.normal(size=(n, 3))
+        R *= (rng.uniform(12.0, 40.0, n) / np.linalg.norm(R, axis=1))[:, None]
+        L = rng.integers(2, 15, n)
+        flags = np.where(rng.random(n) < 0.3, tcm.TCM_TRIANGULAR, 0) | tcm.TCM_REUSE
+        quats = synth.quaternions(84, 0, n)
+        _, _, rc = tcm.tcm_batch_energy(ctx, tcm.make_requests(a, b, [20.0, 0.0, 0.0], 14))
+        assert rc == tcm.TCM_OK
+        U, st, rc = tcm.tcm_batch_energy(ctx, tcm.make_requests(a, b, R, L, quats, flags=flags))
+        assert rc == tcm.TCM_OK and np.all(st == 0)
+        parts = []
+        for s0 in (0, n // 2):
+            sl = slice(s0, s0 + n // 2)
+            Up, stp, rcp = tcm.tcm_batch_energy(ctx, tcm.make_requests(a, b, R[sl], L[sl], quats[sl], flags=flags[sl]))
+            assert rcp == tcm.TCM_OK
+            parts.append(Up)
+        assert np.array_equal(U, np.concatenate(parts))
+    finally:
+        tcm.tcm_mol_release(ctx, a)
+        tcm.tcm_mol_release(ctx, b)
