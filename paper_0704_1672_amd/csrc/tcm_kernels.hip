@@ -856,9 +856,9 @@ __global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_sum_m(DevPl
 // U = (1/R) sum_{m = 0..L} (the m-terms of tcm_pairs_sum_w or tcm_pairs_sum_m) and the status
 // (from the check row of pum); every load issued at once (rows past the pair's order are read
 // and not added).
-__global__ __launch_bounds__(WG) void tcm_pairs_final(DevPlan P, int begin, int end)
+__global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_final(DevPlan P, int begin, int end)
 {
-    const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
+    const int p = begin + (int)blockIdx.x * PAIR_LANES + (int)threadIdx.x;
     if (p >= end) return;
     const double* pum = P.pum + p;
     const size_t st = P.npairs;
@@ -1760,7 +1760,8 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
                            end);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + WG - 1) / WG)), dim3(WG), 0, s, P, begin, end);
+    hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + PAIR_LANES - 1) / PAIR_LANES)), dim3(PAIR_LANES), 0,
+                       s, P, begin, end);
     return hipGetLastError();
 }
 
