@@ -423,3 +423,37 @@ def test_large_batch_planned_on_threads_equals_small_batches(ctx, synth):
     finally:
         tcm.tcm_mol_release(ctx, a)
         tcm.tcm_mol_release(ctx, b)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 129])
+def test_group_edge_counts_match_single_pair_path(ctx, synth, n):
+    """The pair kernels take 64 pairs per wavefront: batches that end one short of, at and one
+    past a group of 64 (mixed orders, some triangular) give each pair the energy of the
+    single-pair path on the same moments, to the bit."""
+    xa, qa = synth.ball(91, 0, 300, 4.0)
+    xb, qb = synth.ball(92, 0, 250, 3.5)
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    b = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F64)
+    try:
+        Lmax = 14
+        _, _, rc = tcm.tcm_batch_energy(ctx, tcm.make_requests(a, b, [20.0, 0.0, 0.0], Lmax))
+        assert rc == tcm.TCM_OK                                  # both tables resident at Lmax
+        QA, aA, _ = tcm.tcm_mol_moments(ctx, a, Lmax, flags=tcm.TCM_REUSE)
+        QB, aB, _ = tcm.tcm_mol_moments(ctx, b, Lmax, flags=tcm.TCM_REUSE)
+        rng = np.random.default_rng(93 + n)
+        R = rng.normal(size=(n, 3))
+        R *= (rng.uniform(12.0, 40.0, n) / np.linalg.norm(R, axis=1))[:, None]
+        L = rng.integers(1, Lmax + 1, n)
+        tri = rng.random(n) < 0.3
+        quats = synth.quaternions(94, n, n)
+        U, st, rc = tcm.tcm_batch_energy(ctx, tcm.make_requests(
+            a, b, R, L, quats, flags=np.where(tri, tcm.TCM_TRIANGULAR, 0) | tcm.TCM_REUSE))
+        assert rc == tcm.TCM_OK and np.all(st == 0)
+        for k in range(n):
+            h = (int(L[k]) + 1) ** 2
+            Us = tcm.tcm_pair_energy(ctx, QA[:h], aA, QB[:h], aB, R[k], int(L[k]), quat_b=quats[k],
+                                     flags=tcm.TCM_TRIANGULAR if tri[k] else 0)
+            assert Us == U[k], (n, k, int(L[k]), bool(tri[k]), Us, U[k])
+    finally:
+        tcm.tcm_mol_release(ctx, a)
+        tcm.tcm_mol_release(ctx, b)
