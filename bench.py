@@ -475,7 +475,8 @@ def adaptive_section(tcm, synth, L=24, npose=32768, fracs=(1e-3, 1e-5)):
     """Adaptive truncation: two 50k-charge balls, 32768 random poses at 3..6 radii of gyration,
     maximum order 24, resident moments; each tolerance is a fraction of S_A S_B / median |R|
     (S = sum |q|, the scale of the rigorous bound).  Times the adaptive call against the fixed
-    order-24 batch on the same requests (median of 5 calls each) and reports the orders chosen
+    order-24 batch on the same requests (calls of the two alternating, median of 11 each, so that
+    a drift of the device or host during the section weighs on both) and reports the orders chosen
     and the largest |U_adaptive - U_24| over the sum of the two bounds (at most 1 up to the
     moment pass's rounding, since each bound covers its own truncation)."""
     w = synth.orientation_scan(seed=3, n=50_000, nposes=npose, L=L)
@@ -494,29 +495,48 @@ def adaptive_section(tcm, synth, L=24, npose=32768, fracs=(1e-3, 1e-5)):
             ts.append(time.perf_counter() - t0)
         return float(np.median(ts)), r
 
-    t_fix, (U24, st24, _) = med(lambda: tcm.tcm_batch_energy(ctx.h, req))
+    def alternate(fa, fb, k=11):
+        """Medians of k calls of fa and of fb, made alternately (after one warm-up call each)."""
+        ra, rb = fa(), fb()
+        ta, tb = [], []
+        for _ in range(k):
+            t0 = time.perf_counter()
+            ra = fa()
+            ta.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            rb = fb()
+            tb.append(time.perf_counter() - t0)
+        return float(np.median(ta)), ra, float(np.median(tb)), rb, ta
+
+    fixed = lambda: tcm.tcm_batch_energy(ctx.h, req)
+    U24, st24, _ = fixed()
     _, _, b24, _, _ = tcm.tcm_batch_energy_adaptive(ctx.h, req, 1e-300)     # the bound at order 24
     scale = float(np.sum(np.abs(w["qA"])) * np.sum(np.abs(w["qB"])) / np.median(np.linalg.norm(w["R"], axis=1)))
     runs = {}
+    t_fix_all = []
     for f in fracs:
         tol = f * scale
-        t_ad, (U, Lu, b, st, rc) = med(lambda: tcm.tcm_batch_energy_adaptive(ctx.h, req, tol))
+        t_fx, _, t_ad, (U, Lu, b, st, rc), ts_fix = alternate(fixed, lambda: tcm.tcm_batch_energy_adaptive(ctx.h, req, tol))
+        t_fix_all += ts_fix
         ok = (st == 0) & (st24 == 0)
         met = ok & (b <= tol)
         reqL = req.copy()
         reqL["L"] = np.maximum(Lu, 0)
         t_at, _ = med(lambda: tcm.tcm_batch_energy(ctx.h, reqL))     # the same orders, given
         runs[f"{f:g}"] = {"tol": tol, "ms": 1e3 * t_ad, "pairs_per_s": npose / t_ad,
-                          "speedup_vs_fixed_L": t_fix / t_ad, "statuses_ok": int(np.sum(st == 0)),
+                          "fixed_L_ms_alternated": 1e3 * t_fx,
+                          "speedup_vs_fixed_L": t_fx / t_ad, "statuses_ok": int(np.sum(st == 0)),
                           "batch_at_chosen_orders_ms": 1e3 * t_at,
                           "L_used": {"min": int(Lu[ok].min()), "median": float(np.median(Lu[ok])),
                                      "mean": float(Lu[ok].mean()), "max": int(Lu[ok].max())},
                           "pairs_meeting_tol": int(np.sum(met)),
                           "max_diff_over_bounds": float(np.max(np.abs(U[ok] - U24[ok]) / (b[ok] + b24[ok])))}
+    t_fix = float(np.median(t_fix_all))
     res = {"workload": f"two 50k-charge balls (q ~ U[-1, 1]), {npose} poses at 3..6 Rg, maximum L = {L}, "
                        "FP32-compensated resident moments; tol = fraction x S_A S_B / median |R|",
            "fixed_L": {"L": L, "ms": 1e3 * t_fix, "pairs_per_s": npose / t_fix}, "adaptive": runs,
-           "timing": "median of 5 calls"}
+           "timing": "median of 11 calls; each tolerance's adaptive calls alternate with fixed-order calls, "
+                     "against which its speedup is taken (batch_at_chosen_orders_ms: median of 5)"}
     tcm.tcm_mol_release(ctx.h, mA)
     tcm.tcm_mol_release(ctx.h, mB)
     ctx.close()
@@ -998,7 +1018,8 @@ def main():
         t_s = time.time()
         adaptive = adaptive_section(tcm, synth)
         log(f"bench: adaptive section in {time.time() - t_s:.1f}s: fixed L {adaptive['fixed_L']['ms']:.2f} ms; " +
-            "; ".join(f"tol {k}: {v['ms']:.2f} ms (same orders given {v['batch_at_chosen_orders_ms']:.2f} ms), "
+            "; ".join(f"tol {k}: {v['ms']:.2f} ms against {v['fixed_L_ms_alternated']:.2f} ms alternated "
+                      f"({v['speedup_vs_fixed_L']:.3f}x; same orders given {v['batch_at_chosen_orders_ms']:.2f} ms), "
                       f"mean L {v['L_used']['mean']:.1f}, "
                       f"diff/bounds {v['max_diff_over_bounds']:.2e}" for k, v in adaptive["adaptive"].items()))
 

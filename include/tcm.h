@@ -198,6 +198,15 @@ int tcm_batch_energy(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, dou
  * context: their device memory is returned to its budget. */
 int tcm_plan_create(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, int use_graph,
                     tcm_plan **plan_out);
+/* A plan whose contractions take adaptive truncation (the rule of tcm_batch_energy_adaptive,
+ * each request's L its maximum order, tol > 0): every run recomputes the moments, then chooses
+ * each pair's order on the device from the requested one, lists the pairs again by chosen
+ * order and contracts them -- the same launches, the same bits and the same orders as
+ * tcm_batch_energy_adaptive on the same requests and moments.  sum |q| of each molecule is
+ * computed when the plan is created (once per molecule, as there).  Runs, results and
+ * destruction as for tcm_plan_create; tcm_plan_orders reads the chosen orders and bounds. */
+int tcm_plan_create_adaptive(tcm_ctx *ctx, const tcm_pair_req *reqs, int64_t npairs, double tol,
+                             int use_graph, tcm_plan **plan_out);
 int tcm_plan_run(tcm_ctx *ctx, tcm_plan *plan);
 /* The serial-order launches issued directly (no graph); results are identical bit for
  * bit. */
@@ -208,6 +217,9 @@ int tcm_plan_run_phased(tcm_ctx *ctx, tcm_plan *plan);
 int tcm_plan_run_timed(tcm_ctx *ctx, tcm_plan *plan, double *ms_out);
 /* Wait for the last run and copy U/status to the host (either may be NULL). */
 int tcm_plan_results(tcm_ctx *ctx, tcm_plan *plan, double *U_out, int32_t *status_out);
+/* Adaptive plans: wait for the last run and copy each pair's chosen order and its bound (as
+ * tcm_batch_energy_adaptive reports them; either may be NULL).  TCM_EINVAL for other plans. */
+int tcm_plan_orders(tcm_ctx *ctx, tcm_plan *plan, int32_t *L_out, double *bound_out);
 /* Device addresses of the plan's outputs (FP64 U[npairs], int32 status[npairs]). */
 int tcm_plan_device_outputs(tcm_plan *plan, double **d_U, int32_t **d_status);
 /* Work counts of the plan: atoms, moment flops (algorithmic convention 6(L+1)(L+2) per

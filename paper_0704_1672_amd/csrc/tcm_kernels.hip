@@ -888,15 +888,16 @@ __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_final(DevPlan P, int beg
 // truncation error meets tol -- square S_A S_B / (R (1-a-b)) [(a/(1-b))^{L'+1} + (b/(1-a))^{L'+1}],
 // triangular S_A S_B t^{L'+1} / (R (1-t)), t = a + b, with a = a_A/R, b = a_B/R and S = sum |q|
 // (meta[5] of each molecule) -- by running products of the ratios (no power per order), L when
-// none does.  The pair's order in the plan is lowered to it; Lout[out] and bout[out] receive the
-// order and its bound (infinite outside the domain of eq. 2, where the pair keeps L).
+// none does.  Lout[out] and bout[out] receive the order and its bound (infinite outside the
+// domain of eq. 2, where the pair keeps L); the plan's own pair records keep the requested
+// orders, so that a plan runs the choice again from them on every replay.
 __global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int end, double tol, int32_t* Lout,
                                                        double* bout)
 {
     const int p = begin + (int)blockIdx.x * WG + (int)threadIdx.x;
     int L = -1;
     if (p < end) {
-        PairWork& pw = const_cast<PairWork&>(P.pairs[p]);
+        const PairWork& pw = P.pairs[p];
         const double R = sqrt(pw.R[0] * pw.R[0] + pw.R[1] * pw.R[1] + pw.R[2] * pw.R[2]);
         const double al = pw.metaA[3] / R, be = pw.metaB[3] / R;
         L = pw.L;
@@ -914,36 +915,33 @@ __global__ __launch_bounds__(WG) void tcm_pairs_choose(DevPlan P, int begin, int
                 }
             }
         }
-        pw.L = L;
         Lout[pw.out] = L;
         bout[pw.out] = b;
     }
-    // a wavefront covers one group of the pair launches: its new largest order
-    const int gmax = wave_max(L);
-    if ((threadIdx.x & (PAIR_LANES - 1)) == 0 && p < end) P.gorder[(p - begin) / PAIR_LANES] = gmax;
 }
 
-// Regrouping after the order choice: the pairs listed again by decreasing chosen order, so that
-// a group of PAIR_LANES pairs runs to (about) the orders its pairs need.  cnt[0 .. LMAX] counts
+// Regrouping after the order choice: the pairs listed again by decreasing chosen order (Lc[out],
+// which the copies carry as their order), so that a group of PAIR_LANES pairs runs to (about)
+// the orders its pairs need.  cnt[0 .. LMAX] counts
 // the pairs of each order (zeroed before), cnt[LMAX + 1 ..] are the placement cursors.  Each
 // workgroup counts its pairs per order in LDS and takes its places with one global atomic per
 // order (one per pair put thousands of atomics on a few addresses: 0.25 ms for 32k pairs).  The
 // place of a pair within its order is taken by atomics (any order: a pair's arithmetic is its
 // own lane's and its result goes to U[out], so its value does not depend on where it lands).
-__global__ __launch_bounds__(WG) void tcm_pairs_count(DevPlan P, int npairs, int32_t* cnt)
+__global__ __launch_bounds__(WG) void tcm_pairs_count(DevPlan P, int npairs, const int32_t* Lc, int32_t* cnt)
 {
     __shared__ int h[LMAX + 1];
     const int tid = (int)threadIdx.x;
     if (tid <= LMAX) h[tid] = 0;
     __syncthreads();
     const int p = (int)blockIdx.x * WG + tid;
-    if (p < npairs) atomicAdd(&h[P.pairs[p].L], 1);
+    if (p < npairs) atomicAdd(&h[Lc[P.pairs[p].out]], 1);
     __syncthreads();
     if (tid <= LMAX && h[tid] > 0) atomicAdd(&cnt[tid], h[tid]);
 }
 
-__global__ __launch_bounds__(WG) void tcm_pairs_regroup(DevPlan P, int npairs, int32_t* cnt, PairWork* pairs2,
-                                                        double* frame2)
+__global__ __launch_bounds__(WG) void tcm_pairs_regroup(DevPlan P, int npairs, const int32_t* Lc, int32_t* cnt,
+                                                        PairWork* pairs2, double* frame2)
 {
     __shared__ int h[LMAX + 1], base[LMAX + 1];
     const int tid = (int)threadIdx.x;
@@ -954,6 +952,7 @@ __global__ __launch_bounds__(WG) void tcm_pairs_regroup(DevPlan P, int npairs, i
     int r = 0;                                           // the pair's rank among the workgroup's of its order
     if (p < npairs) {
         w = P.pairs[p];
+        w.L = Lc[w.out];
         r = atomicAdd(&h[w.L], 1);
     }
     __syncthreads();
@@ -1774,16 +1773,16 @@ hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol,
     return hipGetLastError();
 }
 
-hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, int32_t* cnt, PairWork* pairs2, double* frame2,
-                                int32_t* gorder2, hipStream_t s)
+hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, const int32_t* Lc, int32_t* cnt, PairWork* pairs2,
+                                double* frame2, int32_t* gorder2, hipStream_t s)
 {
     if (npairs <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((npairs + WG - 1) / WG);
     hipError_t e;
     if ((e = launch_clear(cnt, 2 * (LMAX + 1), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_count, dim3(grid), dim3(WG), 0, s, P, npairs, cnt);
+    hipLaunchKernelGGL(tcm_pairs_count, dim3(grid), dim3(WG), 0, s, P, npairs, Lc, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_regroup, dim3(grid), dim3(WG), 0, s, P, npairs, cnt, pairs2, frame2);
+    hipLaunchKernelGGL(tcm_pairs_regroup, dim3(grid), dim3(WG), 0, s, P, npairs, Lc, cnt, pairs2, frame2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int groups = (npairs + PAIR_LANES - 1) / PAIR_LANES;
     hipLaunchKernelGGL(tcm_pairs_group_orders, dim3((unsigned)((groups + WG - 1) / WG)), dim3(WG), 0, s, pairs2,

@@ -1488,9 +1488,26 @@ extern "C" int tcm_all_pairs(tcm_ctx* t, const tcm_mol_id* ids, int64_t K, int L
 }
 
 // ---------------------------------------------------------------- plans (graph replay)
-extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, int use_graph, tcm_plan** out)
+static int abs_sums(Ctx& c, const ReqPlan& rp, hipStream_t s);
+
+// One run of a plan on s: the moment pass, then the contraction (adaptive plans: the order
+// choice, the regrouping and the contraction at the chosen orders).  ev (may be null): the
+// phase events of run_plan, the last one recorded after the contraction.
+static int plan_issue(Ctx& c, tcm_plan* pl, hipStream_t s, bool serial, hipEvent_t* ev)
+{
+    int rc = run_plan(&c, pl->bp, s, serial, ev, !pl->adaptive);
+    if (rc == TCM_OK && pl->adaptive) {
+        rc = adapt_launch(pl->bp, pl->ab, pl->tol, s);
+        if (rc == TCM_OK && ev && hipEventRecord(ev[4], s) != hipSuccess) rc = TCM_EDEVICE;
+    }
+    return rc;
+}
+
+static int plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, int use_graph, bool adaptive, double tol,
+                       tcm_plan** out)
 {
     if (!t || !out || np < 0 || (np > 0 && !reqs)) return TCM_EINVAL;
+    if (adaptive && !(tol > 0.0)) return TCM_EINVAL;
     *out = nullptr;
     Ctx& c = t->c;
     std::lock_guard<std::mutex> g(c.mu);
@@ -1503,12 +1520,18 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
     tcm_plan* pl = new (std::nothrow) tcm_plan();
     if (!pl) return TCM_ENOMEM;
     pl->ctx = &c;
-    if ((rc = build_plan(&c, pl->ws, rp.mj, rp.pj, pl->bp, s)) != TCM_OK) {
+    pl->adaptive = adaptive;
+    pl->tol = tol;
+    if ((rc = build_plan(&c, pl->ws, rp.mj, rp.pj, pl->bp, s)) != TCM_OK ||
+        (adaptive && ((rc = adapt_setup(c, pl->adapt, pl->bp, pl->ab)) != TCM_OK ||
+                      (rc = abs_sums(c, rp, s)) != TCM_OK))) {
+        c.release(pl->adapt);
         free_workspace(&c, pl->ws);
         delete pl;
         return rc;
     }
     if (hipStreamSynchronize(s) != hipSuccess) {
+        c.release(pl->adapt);
         free_workspace(&c, pl->ws);
         delete pl;
         return TCM_EDEVICE;
@@ -1529,7 +1552,7 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
         if (ok) {
             // the serial order: the graph runtime replays a captured fork/join one node at a
             // time anyway, and serially the statistics are a single launch over the batch
-            int r2 = run_plan(&c, pl->bp, cs, true, nullptr);
+            int r2 = plan_issue(c, pl, cs, true, nullptr);
             hipGraph_t gr = nullptr;
             ok = hipStreamEndCapture(cs, &gr) == hipSuccess && r2 == TCM_OK;
             if (ok) {
@@ -1547,6 +1570,7 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
             pl->ctx = nullptr;
             if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
             if (pl->graph) (void)hipGraphDestroy(pl->graph);
+            c.release(pl->adapt);
             free_workspace(&c, pl->ws);
             delete pl;
             return TCM_EDEVICE;
@@ -1554,6 +1578,17 @@ extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np,
     }
     *out = pl;
     return TCM_OK;
+}
+
+extern "C" int tcm_plan_create(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, int use_graph, tcm_plan** out)
+{
+    return plan_create(t, reqs, np, use_graph, false, 0.0, out);
+}
+
+extern "C" int tcm_plan_create_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double tol, int use_graph,
+                                        tcm_plan** out)
+{
+    return plan_create(t, reqs, np, use_graph, true, tol, out);
 }
 
 // A run issued on the context's stream: the moments it writes count as resident from here on
@@ -1574,7 +1609,7 @@ extern "C" int tcm_plan_run(tcm_ctx* t, tcm_plan* pl)
     (void)hipSetDevice(c.device);
     int rc;
     if (pl->exec) rc = hipGraphLaunch(pl->exec, c.stream) == hipSuccess ? TCM_OK : TCM_EDEVICE;
-    else rc = run_plan(&c, pl->bp, c.stream, false, nullptr);
+    else rc = plan_issue(c, pl, c.stream, false, nullptr);
     if (rc == TCM_OK) plan_issued(c, pl);
     return rc;
 }
@@ -1583,7 +1618,7 @@ extern "C" int tcm_plan_run_phased(tcm_ctx* t, tcm_plan* pl)
 {
     if (!t || !pl || pl->ctx != &t->c) return TCM_EINVAL;
     (void)hipSetDevice(t->c.device);
-    const int rc = run_plan(&t->c, pl->bp, t->c.stream, true, nullptr);
+    const int rc = plan_issue(t->c, pl, t->c.stream, true, nullptr);
     if (rc == TCM_OK) plan_issued(t->c, pl);
     return rc;
 }
@@ -1597,7 +1632,7 @@ extern "C" int tcm_plan_run_timed(tcm_ctx* t, tcm_plan* pl, double* ms_out)
     int rc = TCM_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = TCM_EDEVICE;
-    if (rc == TCM_OK) rc = run_plan(&c, pl->bp, c.stream, true, ev);
+    if (rc == TCM_OK) rc = plan_issue(c, pl, c.stream, true, ev);
     if (rc == TCM_OK) plan_issued(c, pl);
     if (rc == TCM_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = TCM_EDEVICE;
     for (int k = 0; rc == TCM_OK && k < 4; ++k) {
@@ -1620,6 +1655,20 @@ extern "C" int tcm_plan_results(tcm_ctx* t, tcm_plan* pl, double* U_out, int32_t
         return TCM_EDEVICE;
     if (status_out && n &&
         hipMemcpyAsync(status_out, pl->bp.P.status, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    return check_err(&c, pl->bp, s);
+}
+
+extern "C" int tcm_plan_orders(tcm_ctx* t, tcm_plan* pl, int32_t* L_out, double* bound_out)
+{
+    if (!t || !pl || pl->ctx != &t->c || !pl->adaptive) return TCM_EINVAL;
+    Ctx& c = t->c;
+    hipStream_t s = c.stream;
+    const int n = pl->bp.npairs;
+    if (L_out && n && hipMemcpyAsync(L_out, pl->ab.L, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TCM_EDEVICE;
+    if (bound_out && n &&
+        hipMemcpyAsync(bound_out, pl->ab.bound, sizeof(double) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
         return TCM_EDEVICE;
     return check_err(&c, pl->bp, s);
 }
@@ -1654,6 +1703,7 @@ extern "C" void tcm_plan_destroy(tcm_plan* pl)
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     // the plan's buffers were charged to the context that created it (plans are destroyed
     // before their context): return them to its budget
+    if (pl->ctx) pl->ctx->release(pl->adapt);
     free_workspace(pl->ctx, pl->ws);
     delete pl;
 }
@@ -1838,6 +1888,65 @@ extern "C" int tcm_alu_calibrate(tcm_ctx* t, int precision, double* tflops_out)
 // S_A S_B / (R (1 - alpha - beta)) [(alpha/(1-beta))^{L+1} + (beta/(1-alpha))^{L+1}]
 // (infinite when alpha + beta >= 1).
 
+namespace tcm {
+
+int adapt_setup(Ctx& c, DevBuf& buf, const BuiltPlan& bp, AdaptBufs& ab)
+{
+    const int npj = bp.npairs;
+    const size_t np1 = npj > 0 ? (size_t)npj : 1, ngr = (np1 + PAIR_LANES - 1) / PAIR_LANES;
+    const size_t o_L = align_up(sizeof(double) * np1, 256);
+    const size_t o_pw = align_up(o_L + sizeof(int32_t) * np1, 256);
+    const size_t o_fr = align_up(o_pw + sizeof(PairWork) * np1, 256);
+    const size_t o_go = align_up(o_fr + sizeof(double) * 2 * FRAME_N * np1, 256);
+    const size_t o_cn = align_up(o_go + sizeof(int32_t) * ngr, 256);
+    int rc;
+    if ((rc = c.alloc(buf, o_cn + sizeof(int32_t) * 2 * (LMAX + 1))) != TCM_OK) return rc;
+    char* ad = (char*)buf.p;
+    ab.bound = (double*)ad;
+    ab.L = (int32_t*)(ad + o_L);
+    ab.cnt = (int32_t*)(ad + o_cn);
+    ab.P2 = bp.P;                                        // the contraction over the regrouped listing
+    ab.P2.pairs = (const PairWork*)(ad + o_pw);
+    ab.P2.frame = (const double*)(ad + o_fr);
+    ab.P2.gorder = (int32_t*)(ad + o_go);
+    ab.P2.gorder_uniform = 0;                            // the orders are chosen on the device
+    ab.npj = npj;
+    return TCM_OK;
+}
+
+int adapt_launch(const BuiltPlan& bp, const AdaptBufs& ab, double tol, hipStream_t s)
+{
+    if (launch_pairs_choose(bp.P, 0, ab.npj, tol, ab.L, ab.bound, s) != hipSuccess ||
+        launch_pairs_regroup(bp.P, ab.npj, ab.L, ab.cnt, const_cast<PairWork*>(ab.P2.pairs),
+                             const_cast<double*>(ab.P2.frame), ab.P2.gorder, s) != hipSuccess ||
+        launch_pairs(ab.P2, 0, ab.npj, s) != hipSuccess)
+        return TCM_EDEVICE;
+    return TCM_OK;
+}
+
+}  // namespace tcm
+
+// sum |q| (meta[5], the bound's charge scale) of the planned molecules that lack it, once per
+// molecule, ordered on s
+static int abs_sums(Ctx& c, const ReqPlan& rp, hipStream_t s)
+{
+    (void)c;
+    std::vector<Mol*> need;
+    for (size_t k = 0; k < rp.side.size(); ++k) {
+        Mol* m = rp.side[k];
+        if (m && !m->absq_dev) {
+            m->absq_dev = true;
+            need.push_back(m);
+        }
+    }
+    for (Mol* m : need)
+        if (launch_abs_sum(m->q, m->n, (double*)m->meta.p + 5, s) != hipSuccess) {
+            for (Mol* x : need) x->absq_dev = false;
+            return TCM_EDEVICE;
+        }
+    return TCM_OK;
+}
+
 extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, int64_t np, double tol, double* U_out,
                                          int32_t* L_out, double* bound_out, int32_t* status_out)
 {
@@ -1856,44 +1965,13 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
     BuiltPlan bp;
     if ((rc = build_plan(&c, c.ws, rp.mj, rp.pj, bp, s)) != TCM_OK) return rc;
     const int npj = (int)rp.pj.size();
-    // per pair: bound, chosen order, the pair record and frames listed again by chosen order;
-    // then the group orders of that listing and the regrouping's counters
-    const size_t np1 = npj > 0 ? (size_t)npj : 1, ngr = (np1 + PAIR_LANES - 1) / PAIR_LANES;
-    const size_t o_L = align_up(sizeof(double) * np1, 256);
-    const size_t o_pw = align_up(o_L + sizeof(int32_t) * np1, 256);
-    const size_t o_fr = align_up(o_pw + sizeof(PairWork) * np1, 256);
-    const size_t o_go = align_up(o_fr + sizeof(double) * 2 * FRAME_N * np1, 256);
-    const size_t o_cn = align_up(o_go + sizeof(int32_t) * ngr, 256);
-    if ((rc = c.alloc(c.adapt, o_cn + sizeof(int32_t) * 2 * (LMAX + 1))) != TCM_OK) return rc;
-    char* ad = (char*)c.adapt.p;
-    double* dB = (double*)ad;
-    int32_t* dL = (int32_t*)(ad + o_L);
-    DevPlan P2 = bp.P;                                   // the contraction over the regrouped listing
-    P2.pairs = (const PairWork*)(ad + o_pw);
-    P2.frame = (const double*)(ad + o_fr);
-    P2.gorder = (int32_t*)(ad + o_go);
-    P2.gorder_uniform = 0;                               // the orders are chosen on the device
+    AdaptBufs ab;
+    if ((rc = adapt_setup(c, c.adapt, bp, ab)) != TCM_OK) return rc;
     if ((rc = run_plan(&c, bp, s, false, nullptr, false)) != TCM_OK) return rc;
-    std::vector<Mol*> need;
-    for (int64_t i = 0; i < np; ++i) {
-        if (rp.pre_status[i] != TCM_OK) continue;
-        for (Mol* m : {rp.side[2 * i], rp.side[2 * i + 1]})
-            if (!m->absq_dev) {
-                m->absq_dev = true;
-                need.push_back(m);
-            }
-    }
-    for (Mol* m : need)
-        if (launch_abs_sum(m->q, m->n, (double*)m->meta.p + 5, s) != hipSuccess) rc = TCM_EDEVICE;
-    if (rc != TCM_OK) {
-        for (Mol* m : need) m->absq_dev = false;
-        return rc;
-    }
-    if (launch_pairs_choose(bp.P, 0, npj, tol, dL, dB, s) != hipSuccess ||
-        launch_pairs_regroup(bp.P, npj, (int32_t*)(ad + o_cn), (PairWork*)(ad + o_pw), (double*)(ad + o_fr),
-                             P2.gorder, s) != hipSuccess ||
-        launch_pairs(P2, 0, npj, s) != hipSuccess)
-        return TCM_EDEVICE;
+    if ((rc = abs_sums(c, rp, s)) != TCM_OK) return rc;
+    if ((rc = adapt_launch(bp, ab, tol, s)) != TCM_OK) return rc;
+    double* dB = ab.bound;
+    int32_t* dL = ab.L;
     std::vector<double> U(npj > 0 ? npj : 1), B(npj > 0 ? npj : 1);
     std::vector<int32_t> st(npj > 0 ? npj : 1), Lc(npj > 0 ? npj : 1);
     {

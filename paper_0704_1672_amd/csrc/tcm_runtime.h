@@ -27,13 +27,14 @@ int noalloc_init(int device);
 hipError_t launch_clear(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevPlan& P, int begin, int end, hipStream_t s);
 hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s);
-// Adaptive truncation: lowers each pair's order in the plan to the smallest meeting tol.
+// Adaptive truncation: each pair's smallest order meeting tol and its bound, into Lout[out] and
+// bout[out] (the plan's pair records are left as they are).
 hipError_t launch_pairs_choose(const DevPlan& P, int begin, int end, double tol, int32_t* Lout, double* bout,
                                hipStream_t s);
-// Lists the pairs again by decreasing (chosen) order into pairs2 / frame2 and writes the group
-// orders of that listing; cnt: 2 (LMAX + 1) ints of scratch.
-hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, int32_t* cnt, PairWork* pairs2, double* frame2,
-                                int32_t* gorder2, hipStream_t s);
+// Lists the pairs again by decreasing chosen order Lc[out] into pairs2 / frame2 (the copies take
+// that order) and writes the group orders of that listing; cnt: 2 (LMAX + 1) ints of scratch.
+hipError_t launch_pairs_regroup(const DevPlan& P, int npairs, const int32_t* Lc, int32_t* cnt, PairWork* pairs2,
+                                double* frame2, int32_t* gorder2, hipStream_t s);
 hipError_t launch_stats_finalize(const DevPlan& P, int mol_begin, int mol_end, hipStream_t s);
 hipError_t launch_moments_finalize(const DevPlan& P, hipStream_t s);
 hipError_t launch_tiles(int prec, int L, const DevPlan& P, int begin, int end, hipStream_t s);
@@ -185,6 +186,21 @@ int check_err(Ctx* c, const BuiltPlan& bp, hipStream_t s);
 void free_workspace(Ctx* c, Workspace& ws);
 int64_t tune_key(int prec, int L, int64_t n);
 
+// Adaptive truncation over the pairs of a built plan, on device buffers carved from one
+// allocation: the chosen order and its bound per output, the pair records and frames listed
+// again by chosen order, the group orders of that listing and the regrouping's counters; P2
+// is the contraction launch over the regrouped listing (U and status those of the plan).
+struct AdaptBufs {
+    double* bound = nullptr;
+    int32_t* L = nullptr;
+    int32_t* cnt = nullptr;
+    DevPlan P2{};
+    int npj = 0;
+};
+int adapt_setup(Ctx& c, DevBuf& buf, const BuiltPlan& bp, AdaptBufs& ab);
+// order choice, regrouping and the contraction, ordered on s
+int adapt_launch(const BuiltPlan& bp, const AdaptBufs& ab, double tol, hipStream_t s);
+
 // serving (tcm_server.cpp)
 void server_destroy(Ctx* c);
 
@@ -201,6 +217,11 @@ struct tcm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int npairs = 0;
+    // adaptive plans: the tolerance, the order choice's outputs and the regrouped listing
+    bool adaptive = false;
+    double tol = 0.0;
+    tcm::DevBuf adapt;
+    tcm::AdaptBufs ab;
     std::vector<tcm::Mol*> refs;   // molecules the plan names (pinned: not released while it lives)
     std::vector<std::pair<tcm::Mol*, int>> computed;   // moments each run writes, and their order
 };

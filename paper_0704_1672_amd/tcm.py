@@ -64,6 +64,8 @@ _SIGS = {
     "tcm_mol_moments": (C.c_int, [_vp, C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp]),
     "tcm_batch_energy": (C.c_int, [_vp, _vp, C.c_int64, _dp, _ip32]),
     "tcm_plan_create": (C.c_int, [_vp, _vp, C.c_int64, C.c_int, C.POINTER(_vp)]),
+    "tcm_plan_create_adaptive": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, C.c_int, C.POINTER(_vp)]),
+    "tcm_plan_orders": (C.c_int, [_vp, _vp, _ip32, _dp]),
     "tcm_plan_run": (C.c_int, [_vp, _vp]),
     "tcm_plan_run_phased": (C.c_int, [_vp, _vp]),
     "tcm_plan_run_timed": (C.c_int, [_vp, _vp, _dp]),
@@ -311,6 +313,22 @@ def tcm_plan_run_timed(ctx, plan):
     ms = np.zeros(4)
     _check(lib().tcm_plan_run_timed(ctx, plan, _p(ms)), "tcm_plan_run_timed")
     return ms
+
+
+def tcm_plan_create_adaptive(ctx, reqs, tol, use_graph=True):
+    reqs = np.ascontiguousarray(reqs, dtype=PAIR_REQ_DTYPE)
+    h = _vp()
+    _check(lib().tcm_plan_create_adaptive(ctx, reqs.ctypes.data if len(reqs) else None, len(reqs), float(tol),
+                                          int(use_graph), C.byref(h)), "tcm_plan_create_adaptive")
+    return h.value
+
+
+def tcm_plan_orders(ctx, plan, n):
+    """Chosen orders and their bounds of an adaptive plan's last run."""
+    Lc = np.empty(max(n, 1), dtype=np.int32)
+    b = np.empty(max(n, 1))
+    _check(lib().tcm_plan_orders(ctx, plan, Lc.ctypes.data_as(_ip32), _p(b)), "tcm_plan_orders")
+    return Lc[:n], b[:n]
 
 
 def tcm_plan_results(ctx, plan, n):

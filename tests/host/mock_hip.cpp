@@ -103,13 +103,14 @@ hipError_t launch_atom_forces(const double*, int, int, const double*, const doub
 hipError_t launch_pairs_choose(const DevPlan& P, int b, int e, double, int32_t* Lout, double* bout, hipStream_t) {
     for (int p = b; p < e; ++p) { const PairWork& w = P.pairs[p]; Lout[w.out] = w.L; bout[w.out] = 0.0; }
     return 0; }
-hipError_t launch_pairs_regroup(const DevPlan& P, int n, int32_t*, PairWork* pairs2, double* frame2, int32_t* go,
-                                hipStream_t) {
+hipError_t launch_pairs_regroup(const DevPlan& P, int n, const int32_t* Lc, int32_t*, PairWork* pairs2, double* frame2,
+                                int32_t* go, hipStream_t) {
     int q = 0;
     for (int L = LMAX; L >= 0; --L)
         for (int p = 0; p < n; ++p)
-            if (P.pairs[p].L == L) {
+            if (Lc[P.pairs[p].out] == L) {
                 pairs2[q] = P.pairs[p];
+                pairs2[q].L = L;
                 for (int c = 0; c < 2 * FRAME_N; ++c) frame2[(size_t)c * n + q] = P.frame[(size_t)c * n + p];
                 ++q;
             }

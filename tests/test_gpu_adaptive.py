@@ -73,3 +73,96 @@ def test_adaptive_errors_and_limits(ctx, synth):
         assert st[0] == tcm.TCM_ENOTFOUND
     finally:
         tcm.tcm_mol_release(ctx, mA)
+
+
+def _adaptive_requests(synth, a, b, n, seed):
+    rng = np.random.default_rng(seed)
+    R = rng.normal(size=(n, 3))
+    R *= (rng.uniform(12.0, 40.0, n) / np.linalg.norm(R, axis=1))[:, None]
+    flags = np.where(rng.random(n) < 0.3, tcm.TCM_TRIANGULAR, 0)
+    return tcm.make_requests(a, b, R, 16, synth.quaternions(seed, 0, n), flags=flags)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_adaptive_plan_equals_adaptive_call(ctx, synth, use_graph):
+    """An adaptive plan, run and replayed (graph, direct, phased, timed), gives the one-shot
+    adaptive call's energies, orders, bounds and statuses bit for bit."""
+    xa, qa = synth.ball(101, 0, 400, 4.0)
+    xb, qb = synth.ball(102, 0, 300, 3.5)
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    b = tcm.tcm_mol_upload(ctx, xb, qb, precision=tcm.TCM_F64)
+    pl = None
+    try:
+        n = 300
+        req = _adaptive_requests(synth, a, b, n, 103)
+        tol = 1e-6 * np.sum(np.abs(qa)) * np.sum(np.abs(qb)) / 20.0
+        U1, L1, b1, st1, rc = tcm.tcm_batch_energy_adaptive(ctx, req, tol)
+        assert rc == tcm.TCM_OK and np.all(st1 == 0)
+        assert L1.min() < L1.max() <= 16                      # the orders differ from pair to pair
+        pl = tcm.tcm_plan_create_adaptive(ctx, req, tol, use_graph=use_graph)
+        runs = [lambda: tcm.tcm_plan_run(ctx, pl), lambda: tcm.tcm_plan_run(ctx, pl),
+                lambda: tcm.tcm_plan_run_phased(ctx, pl), lambda: tcm.tcm_plan_run_timed(ctx, pl)]
+        for run in runs:
+            run()
+            U, st = tcm.tcm_plan_results(ctx, pl, n)
+            Lc, bc = tcm.tcm_plan_orders(ctx, pl, n)
+            assert np.array_equal(U, U1) and np.array_equal(st, st1)
+            assert np.array_equal(Lc, L1) and np.array_equal(bc, b1)
+    finally:
+        if pl is not None:
+            tcm.tcm_plan_destroy(pl)
+        tcm.tcm_mol_release(ctx, a)
+        tcm.tcm_mol_release(ctx, b)
+
+
+def test_adaptive_plan_replay_chooses_again(ctx, synth):
+    """A replay chooses every pair's order again from the requested one: after the atoms of B
+    (device memory the plan reads) move apart by 30%, the bounds grow and orders rise, and the
+    replay equals a fresh adaptive call on the moved atoms bit for bit."""
+    import torch
+    xa, qa = synth.ball(111, 0, 400, 4.0)
+    xb, qb = synth.ball(112, 0, 300, 3.5)
+    t = torch.tensor(np.vstack([xb.T, qb[None, :]]), dtype=torch.float64, device="cuda").contiguous()
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    b = tcm.tcm_mol_register_device(ctx, t[0], t[1], t[2], t[3], len(qb), precision=tcm.TCM_F64)
+    pl = None
+    try:
+        n = 200
+        req = _adaptive_requests(synth, a, b, n, 113)
+        tol = 1e-6 * np.sum(np.abs(qa)) * np.sum(np.abs(qb)) / 20.0
+        pl = tcm.tcm_plan_create_adaptive(ctx, req, tol)
+        tcm.tcm_plan_run(ctx, pl)
+        L0, _ = tcm.tcm_plan_orders(ctx, pl, n)
+        torch.cuda.synchronize()
+        t[0:3] *= 1.3
+        torch.cuda.synchronize()
+        tcm.tcm_plan_run(ctx, pl)
+        U, st = tcm.tcm_plan_results(ctx, pl, n)
+        Lc, bc = tcm.tcm_plan_orders(ctx, pl, n)
+        U1, L1, b1, st1, rc = tcm.tcm_batch_energy_adaptive(ctx, req, tol)
+        assert rc == tcm.TCM_OK and np.all(st1 == 0)
+        assert np.any(L1 > L0)                                # some orders had to rise
+        assert np.array_equal(Lc, L1) and np.array_equal(bc, b1)
+        assert np.array_equal(U, U1) and np.array_equal(st, st1)
+    finally:
+        if pl is not None:
+            tcm.tcm_plan_destroy(pl)
+        tcm.tcm_mol_release(ctx, a)
+        tcm.tcm_mol_release(ctx, b)
+        torch.cuda.synchronize()
+
+
+def test_plan_orders_rejects_fixed_plans(ctx, synth):
+    xa, qa = synth.ball(121, 0, 100, 3.0)
+    a = tcm.tcm_mol_upload(ctx, xa, qa, precision=tcm.TCM_F64)
+    pl = None
+    try:
+        pl = tcm.tcm_plan_create(ctx, tcm.make_requests(a, a, [20.0, 0.0, 0.0], 8))
+        with pytest.raises(tcm.TCMError):
+            tcm.tcm_plan_orders(ctx, pl, 1)
+        with pytest.raises(tcm.TCMError):
+            tcm.tcm_plan_create_adaptive(ctx, tcm.make_requests(a, a, [20.0, 0.0, 0.0], 8), 0.0)
+    finally:
+        if pl is not None:
+            tcm.tcm_plan_destroy(pl)
+        tcm.tcm_mol_release(ctx, a)
