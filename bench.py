@@ -510,6 +510,11 @@ def adaptive_section(tcm, synth, L=24, npose=32768, fracs=(1e-3, 1e-5)):
 
     fixed = lambda: tcm.tcm_batch_energy(ctx.h, req)
     U24, st24, _ = fixed()
+    plan_fix = tcm.tcm_plan_create(ctx.h, req, use_graph=True)           # replays: the moments recomputed
+
+    def replay(pl):
+        tcm.tcm_plan_run(ctx.h, pl)
+        return tcm.tcm_plan_results(ctx.h, pl, npose)
     _, _, b24, _, _ = tcm.tcm_batch_energy_adaptive(ctx.h, req, 1e-300)     # the bound at order 24
     scale = float(np.sum(np.abs(w["qA"])) * np.sum(np.abs(w["qB"])) / np.median(np.linalg.norm(w["R"], axis=1)))
     runs = {}
@@ -523,20 +528,31 @@ def adaptive_section(tcm, synth, L=24, npose=32768, fracs=(1e-3, 1e-5)):
         reqL = req.copy()
         reqL["L"] = np.maximum(Lu, 0)
         t_at, _ = med(lambda: tcm.tcm_batch_energy(ctx.h, reqL))     # the same orders, given
+        plan_ad = tcm.tcm_plan_create_adaptive(ctx.h, req, tol, use_graph=True)
+        t_pf, (Upf, _), t_pa, (Upa, stpa), _ = alternate(lambda: replay(plan_fix), lambda: replay(plan_ad))
+        tcm.tcm_plan_destroy(plan_ad)
+        same = bool(np.array_equal(Upa, U) and np.array_equal(stpa, st) and np.array_equal(Upf, U24))
         runs[f"{f:g}"] = {"tol": tol, "ms": 1e3 * t_ad, "pairs_per_s": npose / t_ad,
                           "fixed_L_ms_alternated": 1e3 * t_fx,
                           "speedup_vs_fixed_L": t_fx / t_ad, "statuses_ok": int(np.sum(st == 0)),
                           "batch_at_chosen_orders_ms": 1e3 * t_at,
+                          "plan_replay": {"fixed_L_ms": 1e3 * t_pf, "adaptive_ms": 1e3 * t_pa,
+                                          "speedup_vs_fixed_L": t_pf / t_pa,
+                                          "results_equal_the_calls": same},
                           "L_used": {"min": int(Lu[ok].min()), "median": float(np.median(Lu[ok])),
                                      "mean": float(Lu[ok].mean()), "max": int(Lu[ok].max())},
                           "pairs_meeting_tol": int(np.sum(met)),
                           "max_diff_over_bounds": float(np.max(np.abs(U[ok] - U24[ok]) / (b[ok] + b24[ok])))}
+    tcm.tcm_plan_destroy(plan_fix)
     t_fix = float(np.median(t_fix_all))
     res = {"workload": f"two 50k-charge balls (q ~ U[-1, 1]), {npose} poses at 3..6 Rg, maximum L = {L}, "
                        "FP32-compensated resident moments; tol = fraction x S_A S_B / median |R|",
            "fixed_L": {"L": L, "ms": 1e3 * t_fix, "pairs_per_s": npose / t_fix}, "adaptive": runs,
            "timing": "median of 11 calls; each tolerance's adaptive calls alternate with fixed-order calls, "
-                     "against which its speedup is taken (batch_at_chosen_orders_ms: median of 5)"}
+                     "against which its speedup is taken (batch_at_chosen_orders_ms: median of 5); "
+                     "plan_replay: the same requests as a fixed-order plan and an adaptive plan (one HIP "
+                     "graph each, the moments recomputed in every run), replays alternated, each replay "
+                     "with its results read back, median of 11"}
     tcm.tcm_mol_release(ctx.h, mA)
     tcm.tcm_mol_release(ctx.h, mB)
     ctx.close()
@@ -1019,7 +1035,9 @@ def main():
         adaptive = adaptive_section(tcm, synth)
         log(f"bench: adaptive section in {time.time() - t_s:.1f}s: fixed L {adaptive['fixed_L']['ms']:.2f} ms; " +
             "; ".join(f"tol {k}: {v['ms']:.2f} ms against {v['fixed_L_ms_alternated']:.2f} ms alternated "
-                      f"({v['speedup_vs_fixed_L']:.3f}x; same orders given {v['batch_at_chosen_orders_ms']:.2f} ms), "
+                      f"({v['speedup_vs_fixed_L']:.3f}x; same orders given {v['batch_at_chosen_orders_ms']:.2f} ms; "
+                      f"plan replays {v['plan_replay']['adaptive_ms']:.3f} against "
+                      f"{v['plan_replay']['fixed_L_ms']:.3f} ms, {v['plan_replay']['speedup_vs_fixed_L']:.2f}x), "
                       f"mean L {v['L_used']['mean']:.1f}, "
                       f"diff/bounds {v['max_diff_over_bounds']:.2e}" for k, v in adaptive["adaptive"].items()))
 
