@@ -1958,7 +1958,8 @@ extern "C" int tcm_batch_energy_adaptive(tcm_ctx* t, const tcm_pair_req* reqs, i
     hipStream_t s = c.stream;
     // one plan at each request's maximum order; every step on the device, one read-back:
     // moments (computed or reused), sum |q| of molecules that lack it (meta[5], once per
-    // molecule), the order choice lowering each pair's order in the plan, the contractions
+    // molecule), each pair's order chosen, the pairs listed again by chosen order, the
+    // contractions at those orders
     ReqPlan rp;
     int rc = plan_requests(c, reqs, np, true, rp);
     if (rc != TCM_OK) return rc;
