@@ -856,6 +856,8 @@ __global__ __launch_bounds__(PAIR_LANES * PAIR_WAVES) void tcm_pairs_sum_m(DevPl
 // U = (1/R) sum_{m = 0..L} (the m-terms of tcm_pairs_sum_w or tcm_pairs_sum_m) and the status
 // (from the check row of pum); every load issued at once (rows past the pair's order are read
 // and not added).
+// N: rows loaded, N - 1 >= the launch's largest order (17, 25 or LMAX + 1).
+template <int N>
 __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_final(DevPlan P, int begin, int end)
 {
     const int p = begin + (int)blockIdx.x * PAIR_LANES + (int)threadIdx.x;
@@ -863,9 +865,9 @@ __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_final(DevPlan P, int beg
     const double* pum = P.pum + p;
     const size_t st = P.npairs;
     const int Lm = P.pair_lmax;
-    double t[LMAX + 1];
+    double t[N];
 #pragma unroll
-    for (int m = 0; m <= LMAX; ++m) t[m] = pum[(size_t)min(m, Lm) * st];
+    for (int m = 0; m < N; ++m) t[m] = pum[(size_t)min(m, Lm) * st];
     const double rn = pum[(size_t)(Lm + 1) * st];
     const PairWork& pw = P.pairs[p];
     const int Lp = pw.L, out = pw.out;
@@ -878,7 +880,7 @@ __global__ __launch_bounds__(PAIR_LANES) void tcm_pairs_final(DevPlan P, int beg
 #pragma clang fp contract(off)
         double V[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int m = 0; m <= LMAX; ++m) V[m & 3] += m <= Lp ? t[m] : 0.0;   // (adding zero changes nothing)
+        for (int m = 0; m < N; ++m) V[m & 3] += m <= Lp ? t[m] : 0.0;   // (adding zero changes nothing)
         P.U[out] = ((V[0] + V[1]) + (V[2] + V[3])) / rn;
         P.status[out] = TCM_OK;
     }
@@ -1759,8 +1761,13 @@ hipError_t launch_pairs(const DevPlan& P, int begin, int end, hipStream_t s)
                            end);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(tcm_pairs_final, dim3((unsigned)((end - begin + PAIR_LANES - 1) / PAIR_LANES)), dim3(PAIR_LANES), 0,
-                       s, P, begin, end);
+    const dim3 fg((unsigned)((end - begin + PAIR_LANES - 1) / PAIR_LANES));
+    if (Lm <= 16)
+        hipLaunchKernelGGL(tcm_pairs_final<17>, fg, dim3(PAIR_LANES), 0, s, P, begin, end);
+    else if (Lm <= SW_L)
+        hipLaunchKernelGGL(tcm_pairs_final<SW_L + 1>, fg, dim3(PAIR_LANES), 0, s, P, begin, end);
+    else
+        hipLaunchKernelGGL(tcm_pairs_final<LMAX + 1>, fg, dim3(PAIR_LANES), 0, s, P, begin, end);
     return hipGetLastError();
 }
 
