@@ -51,3 +51,21 @@ def test_server_stress_tsan(tmp_path):
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert len([l for l in r.stdout.splitlines() if l.startswith("seed")]) == 4
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_adaptive_plans_asan_ubsan(tmp_path):
+    """Adaptive plans on the HIP stand-in under ASan/UBSan: every run equals the one-shot
+    adaptive call, destroyed plans give their memory back, and creations failing under
+    injected allocation failures leave the budget as it was."""
+    exe = str(tmp_path / "adaptive_plan")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-I", HOST, "-I", os.path.join(ROOT, "include"), "-I", SRC, "-o", exe,
+           os.path.join(HOST, "adaptive_plan.cpp"), os.path.join(HOST, "mock_hip.cpp"),
+           os.path.join(SRC, "tcm_runtime.cpp"), os.path.join(SRC, "tcm_server.cpp"), "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "adaptive plans ok" in r.stdout
